@@ -1,0 +1,290 @@
+"""CPU oracle for the Wilson-Dirac operator in higher representations.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark use this package to check and time the GPU library.  The
+library itself never imports, links or runs anything here.
+
+The arithmetic lives in ``oracle.c`` (plain FP64 C, OpenMP over sites); this
+module marshals numpy arrays in the canonical layout:
+
+  * gauge field ``[V][4][n][n]`` complex128, spinor ``[V][4][nr]`` complex128;
+  * half-parity fields list that parity's sites in lexicographic order, with
+    even sites having ``x0+x1+x2+x3`` even.
+
+Each function names the passage of arXiv 2405.19294 it follows; conventions the
+paper leaves open are fixed in ``oracle.c``'s header.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+REP_IDS = {"fund": 0, "adj": 1, "sym": 2, "asym": 3}
+FMT_IDS = {"f32": 0, "bf16": 1, "f16": 2}
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so (gcc, -O2, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared",
+               "-Wall", "-Wno-unknown-pragmas", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I = ctypes.c_int
+        L = ctypes.c_long
+        D = ctypes.c_double
+        sig = {
+            "orc_gamma": (None, [I, P]),
+            "orc_rep_dim": (I, [I, I]),
+            "orc_rep_map": (I, [I, I, L, P, P]),
+            "orc_rep_basis": (I, [I, I, P]),
+            "orc_hop": (I, [P, I, P, P, I, P, P]),
+            "orc_dw": (I, [P, I, P, D, P, I, P, P]),
+            "orc_hop_eo": (I, [P, I, P, P, I, I, P, P]),
+            "orc_deo": (I, [P, I, P, D, P, I, P, P]),
+            "orc_cg": (I, [P, I, P, D, P, I, P, P, D, I, P, P, P]),
+            "orc_round": (I, [I, L, P]),
+            "orc_parity_count": (I, [P, I]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c128(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def _dims(dims) -> np.ndarray:
+    d = np.ascontiguousarray(dims, dtype=np.int32)
+    if d.shape != (4,):
+        raise ValueError("dims must have 4 entries")
+    return d
+
+
+def _theta(theta) -> np.ndarray:
+    t = np.zeros(4) if theta is None else np.ascontiguousarray(theta, dtype=np.float64)
+    if t.shape != (4,):
+        raise ValueError("theta must have 4 entries")
+    return t
+
+
+def _check(rc: int, what: str):
+    if rc < 0:
+        raise ValueError(f"oracle {what} rejected its arguments (code {rc})")
+
+
+# ---------------------------------------------------------------- conventions
+
+def gamma(m: int) -> np.ndarray:
+    """Euclidean chiral gamma matrix m (0..3; 4 = gamma_5), 4x4 complex."""
+    out = np.zeros((4, 4), dtype=np.complex128)
+    _load().orc_gamma(int(m), _ptr(out))
+    return out
+
+
+def rep_dim(nc: int, rep: str) -> int:
+    """Dimension N_R of representation ``rep`` of SU(nc) (Sec. 3.1.2 scaling ~N_f)."""
+    return int(_load().orc_rep_dim(int(nc), REP_IDS[rep]))
+
+
+def rep_basis(nc: int, rep: str) -> np.ndarray:
+    """Basis matrices of the representation space, [nr][nc][nc]."""
+    nr = rep_dim(nc, rep)
+    out = np.zeros((nr, nc, nc), dtype=np.complex128)
+    _check(_load().orc_rep_basis(int(nc), REP_IDS[rep], _ptr(out)), "rep_basis")
+    return out
+
+
+def rep_map(nc: int, rep: str, u_f) -> np.ndarray:
+    """Represented links U_R for fundamental links U_F (any leading shape).
+
+    Fermions in a higher representation see the gauge field through U_R
+    (Sec. 3.1, Sec. 3.1.2).
+    """
+    u = _c128(u_f)
+    if u.shape[-2:] != (nc, nc):
+        raise ValueError("u_f must end in (nc, nc)")
+    nr = rep_dim(nc, rep)
+    lead = u.shape[:-2]
+    n = int(np.prod(lead)) if lead else 1
+    out = np.zeros(lead + (nr, nr), dtype=np.complex128)
+    _check(_load().orc_rep_map(int(nc), REP_IDS[rep], n, _ptr(u), _ptr(out)), "rep_map")
+    return out
+
+
+# ---------------------------------------------------------------- operator
+
+def _nr_of(u_r) -> int:
+    return int(u_r.shape[-1])
+
+
+def hop(dims, u_r, psi, theta=None, dagger=False) -> np.ndarray:
+    """Hopping term H psi (or H^+ psi) on the full lattice (Sec. 3.1)."""
+    u, p = _c128(u_r), _c128(psi)
+    out = np.zeros_like(p)
+    _check(_load().orc_hop(_ptr(_dims(dims)), _nr_of(u), _ptr(u), _ptr(_theta(theta)),
+                           int(bool(dagger)), _ptr(p), _ptr(out)), "hop")
+    return out
+
+
+def dw(dims, u_r, kappa, psi, theta=None, dagger=False) -> np.ndarray:
+    """Wilson-Dirac operator D psi = psi - kappa H psi (or D^+ psi) (Sec. 3.1)."""
+    u, p = _c128(u_r), _c128(psi)
+    out = np.zeros_like(p)
+    _check(_load().orc_dw(_ptr(_dims(dims)), _nr_of(u), _ptr(u), float(kappa),
+                          _ptr(_theta(theta)), int(bool(dagger)), _ptr(p), _ptr(out)), "dw")
+    return out
+
+
+def hop_eo(dims, u_r, in_half, out_parity, theta=None, dagger=False) -> np.ndarray:
+    """Off-diagonal block of H from parity 1-out_parity to out_parity (Sec. 3.1, even/odd)."""
+    u, p = _c128(u_r), _c128(in_half)
+    out = np.zeros_like(p)
+    _check(_load().orc_hop_eo(_ptr(_dims(dims)), _nr_of(u), _ptr(u), _ptr(_theta(theta)),
+                              int(bool(dagger)), int(out_parity), _ptr(p), _ptr(out)), "hop_eo")
+    return out
+
+
+def deo(dims, u_r, kappa, in_e, theta=None, dagger=False) -> np.ndarray:
+    """Even/odd Schur operator D_hat = 1 - kappa^2 H_eo H_oe on even sites (Sec. 3.1)."""
+    u, p = _c128(u_r), _c128(in_e)
+    out = np.zeros_like(p)
+    _check(_load().orc_deo(_ptr(_dims(dims)), _nr_of(u), _ptr(u), float(kappa),
+                           _ptr(_theta(theta)), int(bool(dagger)), _ptr(p), _ptr(out)), "deo")
+    return out
+
+
+def gamma5(psi) -> np.ndarray:
+    """gamma_5 applied to a spinor field [..., 4, nr]."""
+    g5 = gamma(4)
+    return np.einsum("ab,...bc->...ac", g5, _c128(psi))
+
+
+# ---------------------------------------------------------------- parity helpers
+
+def parity_of_sites(dims) -> np.ndarray:
+    x = np.indices(tuple(int(v) for v in dims)).reshape(4, -1)
+    return (x.sum(axis=0) & 1).astype(np.int8)
+
+
+def split_eo(dims, psi):
+    """Full field -> (even half, odd half), each listing its sites lexicographically."""
+    par = parity_of_sites(dims)
+    p = _c128(psi)
+    return np.ascontiguousarray(p[..., par == 0, :, :]), np.ascontiguousarray(p[..., par == 1, :, :])
+
+
+def merge_eo(dims, even, odd):
+    par = parity_of_sites(dims)
+    e = _c128(even)
+    out = np.zeros(e.shape[:-3] + (len(par),) + e.shape[-2:], dtype=np.complex128)
+    out[..., par == 0, :, :] = e
+    out[..., par == 1, :, :] = _c128(odd)
+    return out
+
+
+# ---------------------------------------------------------------- CG
+
+SYSTEM_FULL = 0   # A = D^+ D on the full lattice
+SYSTEM_EO = 1     # A = D_hat^+ D_hat on the even sites
+
+
+def cg(dims, u_r, kappa, eta, theta=None, system=SYSTEM_EO, tol=1e-10, max_iter=10000):
+    """Conjugate gradient for A x = eta from x = 0 (Sec. 3.3).
+
+    Returns (x, info) with info = {"status", "iters", "true_rel_resid",
+    "restarts", "alpha", "beta"}; the true residual is recomputed in FP64.
+    """
+    u, b = _c128(u_r), _c128(eta)
+    x = np.zeros_like(b)
+    alpha = np.zeros(max_iter)
+    beta = np.zeros(max_iter)
+    info = np.zeros(3)
+    rc = _load().orc_cg(_ptr(_dims(dims)), _nr_of(u), _ptr(u), float(kappa), _ptr(_theta(theta)),
+                        int(system), _ptr(b), _ptr(x), float(tol), int(max_iter),
+                        _ptr(alpha), _ptr(beta), _ptr(info))
+    _check(rc if rc != -5 else 0, "cg")
+    it = int(info[0])
+    return x, {"status": int(rc), "iters": it, "true_rel_resid": float(info[1]),
+               "restarts": int(info[2]), "alpha": alpha[:it].copy(), "beta": beta[:it].copy()}
+
+
+def lanczos_extremes(alpha, beta):
+    """Extreme eigenvalues of A from CG coefficients (CG-Lanczos relation).
+
+    T_kk = 1/alpha_k + beta_{k-1}/alpha_{k-1}, T_k,k+1 = sqrt(beta_k)/alpha_k
+    (Golub & Van Loan, Matrix Computations, Sec. 11.3).
+    """
+    a = np.asarray(alpha, dtype=np.float64)
+    b = np.asarray(beta, dtype=np.float64)
+    k = len(a)
+    if k == 0:
+        return 0.0, 0.0
+    diag = 1.0 / a
+    diag[1:] += b[:-1] / a[:-1]
+    off = np.sqrt(b[:-1]) / a[:-1]
+    t = np.diag(diag) + np.diag(off, 1) + np.diag(off, -1)
+    ev = np.linalg.eigvalsh(t)
+    return float(ev[0]), float(ev[-1])
+
+
+def solve_d_eo(dims, u_r, kappa, b, theta=None, tol=1e-10, max_iter=10000):
+    """Solve D x = b by the even/odd Schur complement and CG on the normal equations.
+
+    b'_e = b_e + kappa H_eo b_o; D_hat x_e = b'_e (as D_hat^+ D_hat x_e =
+    D_hat^+ b'_e); x_o = b_o + kappa H_oe x_e (Sec. 3.1 even/odd, Sec. 3.3 CG).
+    """
+    be, bo = split_eo(dims, b)
+    bpe = be + kappa * hop_eo(dims, u_r, bo, 0, theta)
+    eta = deo(dims, u_r, kappa, bpe, theta, dagger=True)
+    xe, info = cg(dims, u_r, kappa, eta, theta, SYSTEM_EO, tol, max_iter)
+    xo = bo + kappa * hop_eo(dims, u_r, xe, 1, theta)
+    return merge_eo(dims, xe, xo), info
+
+
+# ---------------------------------------------------------------- 16-bit storage
+
+def round_to(fmt: str, a) -> np.ndarray:
+    """Round every real component to binary32 / bfloat16 / binary16 (ties to even),
+    returned as float64 (complex arrays round real and imaginary parts)."""
+    arr = np.array(a, dtype=np.complex128 if np.iscomplexobj(a) else np.float64, copy=True)
+    flat = arr.view(np.float64).reshape(-1)
+    _check(_load().orc_round(FMT_IDS[fmt], flat.size, _ptr(flat)), "round")
+    return arr
+
+
+def num_threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    v = os.environ.get("OMP_NUM_THREADS")
+    if v and v.isdigit():
+        return int(v)
+    return os.cpu_count() or 1

@@ -1,0 +1,615 @@
+/*
+ * Plain FP64 CPU oracle for the Wilson-Dirac operator with fermions in a
+ * representation R of SU(N), its even/odd (Schur) form and conjugate-gradient
+ * inversion of D^dagger D.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct
+ * definition the GPU library is checked against.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it; the GPU
+ * library shares no code, header, table or helper with it.
+ *
+ * Sources of each definition (arXiv 2405.19294):
+ *   - the operator is the Wilson-Dirac operator in single/double precision for
+ *     any N_c and higher representations, with even/odd preconditioning
+ *     (Sec. 3.1); the spinor carries ~N_f colour components and the
+ *     represented link is an N_f x N_f matrix (Sec. 3.1.2);
+ *   - the inverters are CG (Sec. 3.3); inner products and norms are global
+ *     reductions (Sec. 3.2).
+ * The paper prints no formula for D, the gamma basis, the representation
+ * bases or the boundary-phase placement; the readings fixed here are:
+ *   - Euclidean chiral gamma basis, gamma_5 = g0 g1 g2 g3 = diag(1,1,-1,-1);
+ *   - (H psi)(x) = sum_mu [ ph+_mu(x) (1 - g_mu) U_mu(x) psi(x+mu)
+ *                         + ph-_mu(x) (1 + g_mu) U_mu(x-mu)^+ psi(x-mu) ],
+ *     D = 1 - kappa H (Wilson r = 1);
+ *   - ph+_mu(x) = exp(i theta_mu) when x_mu = N_mu - 1, ph-_mu(x) =
+ *     exp(-i theta_mu) when x_mu = 0, else 1; phases are never folded into U;
+ *   - adjoint generators T^a = generalised Gell-Mann / 2 (symmetric
+ *     off-diagonal, antisymmetric off-diagonal, diagonal), (U_A)_ab =
+ *     2 Re Tr(T^a U T^b U^+); two-index bases e_(jk) with M -> U M U^T and
+ *     (U_R)_ab = Tr(e_a^+ U e_b U^T);
+ *   - even sites have x0+x1+x2+x3 even; D_hat = 1 - kappa^2 H_eo H_oe.
+ * Gamma matrices are multiplied as literal 4x4 matrices (no spin
+ * projection), and the even/odd blocks are taken by masking the full hop, so
+ * that nothing in here mirrors the GPU kernels' structure.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_NOT_CONVERGED 1
+#define ORC_BREAKDOWN (-5)
+
+enum { REP_FUND = 0, REP_ADJ = 1, REP_SYM = 2, REP_ASYM = 3 };
+
+/* ------------------------------------------------------------------ lattice */
+
+static long vol(const int d[4]) { return (long)d[0] * d[1] * d[2] * d[3]; }
+
+static void coords(const int d[4], long s, int x[4])
+{
+    x[3] = (int)(s % d[3]);
+    s /= d[3];
+    x[2] = (int)(s % d[2]);
+    s /= d[2];
+    x[1] = (int)(s % d[1]);
+    x[0] = (int)(s / d[1]);
+}
+
+static long index_of(const int d[4], const int x[4])
+{
+    return (((long)x[0] * d[1] + x[1]) * d[2] + x[2]) * d[3] + x[3];
+}
+
+static int parity_of(const int x[4]) { return (x[0] + x[1] + x[2] + x[3]) & 1; }
+
+/* ------------------------------------------------------------------ gamma */
+
+static cplx G[5][4][4];
+static int gamma_ready = 0;
+
+static void init_gamma(void)
+{
+    if (gamma_ready) return;
+    memset(G, 0, sizeof G);
+    /* g0 = [[0,-1],[-1,0]] in 2x2 blocks */
+    G[0][0][2] = -1; G[0][1][3] = -1; G[0][2][0] = -1; G[0][3][1] = -1;
+    /* gk = [[0, -i sigma_k], [i sigma_k, 0]] */
+    G[1][0][3] = -I; G[1][1][2] = -I; G[1][2][1] = I; G[1][3][0] = I;
+    G[2][0][3] = -1; G[2][1][2] = 1; G[2][2][1] = 1; G[2][3][0] = -1;
+    G[3][0][2] = -I; G[3][1][3] = I; G[3][2][0] = I; G[3][3][1] = -I;
+    /* g5 = g0 g1 g2 g3, computed by matrix products */
+    cplx a[4][4], b[4][4];
+    memcpy(a, G[0], sizeof a);
+    for (int m = 1; m < 4; ++m) {
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+                cplx s = 0;
+                for (int k = 0; k < 4; ++k) s += a[i][k] * G[m][k][j];
+                b[i][j] = s;
+            }
+        memcpy(a, b, sizeof a);
+    }
+    memcpy(G[4], a, sizeof a);
+    gamma_ready = 1;
+}
+
+/* Copy gamma matrix m (0..3, 4 = gamma_5) out, row-major complex. */
+void orc_gamma(int m, double *out)
+{
+    init_gamma();
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            out[2 * (4 * i + j)] = creal(G[m][i][j]);
+            out[2 * (4 * i + j) + 1] = cimag(G[m][i][j]);
+        }
+}
+
+/* ------------------------------------------------------------------ rep map */
+
+int orc_rep_dim(int nc, int rep)
+{
+    if (nc < 1) return -1;
+    switch (rep) {
+    case REP_FUND: return nc;
+    case REP_ADJ: return nc * nc - 1;
+    case REP_SYM: return nc * (nc + 1) / 2;
+    case REP_ASYM: return nc * (nc - 1) / 2;
+    }
+    return -1;
+}
+
+/* dense N x N helpers */
+static void mm(int n, const cplx *a, const cplx *b, cplx *c)
+{
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            cplx s = 0;
+            for (int k = 0; k < n; ++k) s += a[i * n + k] * b[k * n + j];
+            c[i * n + j] = s;
+        }
+}
+
+static void dagger(int n, const cplx *a, cplx *c)
+{
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) c[i * n + j] = conj(a[j * n + i]);
+}
+
+static void transpose(int n, const cplx *a, cplx *c)
+{
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) c[i * n + j] = a[j * n + i];
+}
+
+static cplx trace(int n, const cplx *a)
+{
+    cplx s = 0;
+    for (int i = 0; i < n; ++i) s += a[i * n + i];
+    return s;
+}
+
+/* Basis matrices of the representation space, each N x N; returns count. */
+static int build_basis(int n, int rep, cplx *basis /* [nr][n*n] */)
+{
+    int a = 0;
+    const int nn = n * n;
+    if (rep == REP_ADJ) {
+        /* generalised Gell-Mann matrices divided by 2 */
+        for (int j = 0; j < n; ++j)
+            for (int k = j + 1; k < n; ++k) {
+                cplx *t = basis + (long)a * nn;
+                memset(t, 0, sizeof(cplx) * nn);
+                t[j * n + k] = 0.5;
+                t[k * n + j] = 0.5;
+                ++a;
+            }
+        for (int j = 0; j < n; ++j)
+            for (int k = j + 1; k < n; ++k) {
+                cplx *t = basis + (long)a * nn;
+                memset(t, 0, sizeof(cplx) * nn);
+                t[j * n + k] = -0.5 * I;
+                t[k * n + j] = 0.5 * I;
+                ++a;
+            }
+        for (int l = 1; l < n; ++l) {
+            cplx *t = basis + (long)a * nn;
+            memset(t, 0, sizeof(cplx) * nn);
+            const double c = 1.0 / sqrt(2.0 * l * (l + 1));
+            for (int m = 0; m < l; ++m) t[m * n + m] = c;
+            t[l * n + l] = -l * c;
+            ++a;
+        }
+    } else if (rep == REP_SYM) {
+        for (int j = 0; j < n; ++j)
+            for (int k = j; k < n; ++k) {
+                cplx *e = basis + (long)a * nn;
+                memset(e, 0, sizeof(cplx) * nn);
+                if (j == k) {
+                    e[j * n + j] = 1.0;
+                } else {
+                    e[j * n + k] = M_SQRT1_2;
+                    e[k * n + j] = M_SQRT1_2;
+                }
+                ++a;
+            }
+    } else if (rep == REP_ASYM) {
+        for (int j = 0; j < n; ++j)
+            for (int k = j + 1; k < n; ++k) {
+                cplx *e = basis + (long)a * nn;
+                memset(e, 0, sizeof(cplx) * nn);
+                e[j * n + k] = M_SQRT1_2;
+                e[k * n + j] = -M_SQRT1_2;
+                ++a;
+            }
+    }
+    return a;
+}
+
+/* One link U (N x N) -> U_R (nr x nr) by the trace definitions. */
+static void rep_one(int n, int rep, int nr, const cplx *basis, const cplx *u, cplx *ur,
+                    cplx *w1, cplx *w2, cplx *w3)
+{
+    const int nn = n * n;
+    if (rep == REP_FUND) {
+        memcpy(ur, u, sizeof(cplx) * nn);
+        return;
+    }
+    if (rep == REP_ADJ) {
+        cplx ud[64];
+        dagger(n, u, ud);
+        for (int b = 0; b < nr; ++b) {
+            mm(n, u, basis + (long)b * nn, w1);  /* U T^b */
+            mm(n, w1, ud, w2);                   /* U T^b U^+ */
+            for (int a = 0; a < nr; ++a) {
+                mm(n, basis + (long)a * nn, w2, w3);
+                ur[a * nr + b] = 2.0 * creal(trace(n, w3));
+            }
+        }
+        return;
+    }
+    /* two-index: M -> U M U^T, (U_R)_ab = Tr(e_a^+ U e_b U^T) */
+    cplx ut[64], ed[64];
+    transpose(n, u, ut);
+    for (int b = 0; b < nr; ++b) {
+        mm(n, u, basis + (long)b * nn, w1);
+        mm(n, w1, ut, w2);
+        for (int a = 0; a < nr; ++a) {
+            dagger(n, basis + (long)a * nn, ed);
+            mm(n, ed, w2, w3);
+            ur[a * nr + b] = trace(n, w3);
+        }
+    }
+}
+
+/* u_f: n_links x N x N complex; u_r: n_links x nr x nr complex. */
+int orc_rep_map(int nc, int rep, long n_links, const double *u_f, double *u_r)
+{
+    const int nr = orc_rep_dim(nc, rep);
+    if (nr < 1 || nc > 8 || n_links < 0 || !u_f || !u_r) return ORC_EINVAL;
+    const int nn = nc * nc;
+    cplx *basis = (cplx *)malloc(sizeof(cplx) * (size_t)(nr > 0 ? nr : 1) * nn);
+    build_basis(nc, rep, basis);
+    const cplx *uf = (const cplx *)u_f;
+    cplx *ur = (cplx *)u_r;
+#pragma omp parallel
+    {
+        cplx w1[64], w2[64], w3[64];
+#pragma omp for schedule(static)
+        for (long l = 0; l < n_links; ++l)
+            rep_one(nc, rep, nr, basis, uf + l * nn, ur + l * (long)nr * nr, w1, w2, w3);
+    }
+    free(basis);
+    return ORC_OK;
+}
+
+/* Basis matrices for the tests (nr x N x N complex). */
+int orc_rep_basis(int nc, int rep, double *out)
+{
+    if (rep == REP_FUND || orc_rep_dim(nc, rep) < 1) return ORC_EINVAL;
+    build_basis(nc, rep, (cplx *)out);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ hop */
+
+/* Hopping term H (sign = +1) or its adjoint H^+ (sign = -1) on the full
+ * lattice.  u: [V][4][nr][nr], in/out: [V][4][nr]. */
+static void hop_full(const int d[4], int nr, const cplx *u, const double theta[4], int sign,
+                     const cplx *in, cplx *out)
+{
+    init_gamma();
+    const long v = vol(d);
+    const int sp = 4 * nr;
+    const long ls = (long)nr * nr;
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < v; ++s) {
+        int x[4];
+        coords(d, s, x);
+        cplx acc[4 * 16];
+        cplx t[4 * 16];
+        for (int i = 0; i < sp; ++i) acc[i] = 0;
+        for (int mu = 0; mu < 4; ++mu) {
+            for (int dir = 0; dir < 2; ++dir) {
+                int y[4] = {x[0], x[1], x[2], x[3]};
+                cplx ph = 1.0;
+                const cplx *link;
+                int adj;
+                if (dir == 0) { /* forward: U_mu(x) psi(x+mu), projector (1 - sign g_mu) */
+                    y[mu] = (x[mu] + 1) % d[mu];
+                    if (x[mu] == d[mu] - 1) ph = cexp(I * theta[mu]);
+                    link = u + (s * 4 + mu) * ls;
+                    adj = 0;
+                } else { /* backward: U_mu(x-mu)^+ psi(x-mu), projector (1 + sign g_mu) */
+                    y[mu] = (x[mu] + d[mu] - 1) % d[mu];
+                    if (x[mu] == 0) ph = cexp(-I * theta[mu]);
+                    link = u + (index_of(d, y) * 4 + mu) * ls;
+                    adj = 1;
+                }
+                const cplx *src = in + index_of(d, y) * sp;
+                /* t[spin][a] = sum_b link(a,b) src[spin][b] (or the adjoint) */
+                for (int al = 0; al < 4; ++al)
+                    for (int a = 0; a < nr; ++a) {
+                        cplx z = 0;
+                        for (int b = 0; b < nr; ++b) {
+                            cplx l = adj ? conj(link[b * nr + a]) : link[a * nr + b];
+                            z += l * src[al * nr + b];
+                        }
+                        t[al * nr + a] = z;
+                    }
+                const double gs = (dir == 0 ? -1.0 : 1.0) * sign;
+                for (int al = 0; al < 4; ++al)
+                    for (int a = 0; a < nr; ++a) {
+                        cplx z = t[al * nr + a];
+                        for (int be = 0; be < 4; ++be) z += gs * G[mu][al][be] * t[be * nr + a];
+                        acc[al * nr + a] += ph * z;
+                    }
+            }
+        }
+        for (int i = 0; i < sp; ++i) out[s * sp + i] = acc[i];
+    }
+}
+
+static int check_dims(const int d[4], int nr)
+{
+    if (!d || nr < 1 || nr > 16) return 0;
+    for (int m = 0; m < 4; ++m)
+        if (d[m] < 2) return 0;
+    return 1;
+}
+
+int orc_hop(const int *dims, int nr, const double *u, const double *theta, int dagger_,
+            const double *in, double *out)
+{
+    if (!check_dims(dims, nr) || !u || !in || !out) return ORC_EINVAL;
+    const double zero[4] = {0, 0, 0, 0};
+    hop_full(dims, nr, (const cplx *)u, theta ? theta : zero, dagger_ ? -1 : 1,
+             (const cplx *)in, (cplx *)out);
+    return ORC_OK;
+}
+
+/* D psi = psi - kappa H psi (dagger: psi - kappa H^+ psi). */
+int orc_dw(const int *dims, int nr, const double *u, double kappa, const double *theta,
+           int dagger_, const double *in, double *out)
+{
+    if (!check_dims(dims, nr) || !u || !in || !out || in == out) return ORC_EINVAL;
+    int rc = orc_hop(dims, nr, u, theta, dagger_, in, out);
+    if (rc) return rc;
+    const long n = vol(dims) * 4 * nr;
+    const cplx *a = (const cplx *)in;
+    cplx *b = (cplx *)out;
+    for (long i = 0; i < n; ++i) b[i] = a[i] - kappa * b[i];
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ even/odd */
+
+/* Half-parity fields list the sites of one parity in lexicographic order. */
+static long half_count(const int d[4], int p)
+{
+    long c = 0;
+    const long v = vol(d);
+    for (long s = 0; s < v; ++s) {
+        int x[4];
+        coords(d, s, x);
+        c += parity_of(x) == p;
+    }
+    return c;
+}
+
+static void embed(const int d[4], int nr, int p, const cplx *half, cplx *full)
+{
+    const long v = vol(d);
+    const int sp = 4 * nr;
+    long k = 0;
+    for (long s = 0; s < v; ++s) {
+        int x[4];
+        coords(d, s, x);
+        if (parity_of(x) == p) {
+            memcpy(full + s * sp, half + k * sp, sizeof(cplx) * sp);
+            ++k;
+        } else {
+            memset(full + s * sp, 0, sizeof(cplx) * sp);
+        }
+    }
+}
+
+static void extract(const int d[4], int nr, int p, const cplx *full, cplx *half)
+{
+    const long v = vol(d);
+    const int sp = 4 * nr;
+    long k = 0;
+    for (long s = 0; s < v; ++s) {
+        int x[4];
+        coords(d, s, x);
+        if (parity_of(x) == p) {
+            memcpy(half + k * sp, full + s * sp, sizeof(cplx) * sp);
+            ++k;
+        }
+    }
+}
+
+static int even_dims(const int d[4])
+{
+    for (int m = 0; m < 4; ++m)
+        if (d[m] % 2) return 0;
+    return 1;
+}
+
+/* Block of H (or H^+) mapping parity 1-out_parity to out_parity. */
+int orc_hop_eo(const int *dims, int nr, const double *u, const double *theta, int dagger_,
+               int out_parity, const double *in_half, double *out_half)
+{
+    if (!check_dims(dims, nr) || !even_dims(dims) || (out_parity & ~1) || !u || !in_half ||
+        !out_half)
+        return ORC_EINVAL;
+    const long v = vol(dims);
+    const size_t bytes = sizeof(cplx) * (size_t)v * 4 * nr;
+    cplx *a = (cplx *)malloc(bytes), *b = (cplx *)malloc(bytes);
+    embed(dims, nr, 1 - out_parity, (const cplx *)in_half, a);
+    const double zero[4] = {0, 0, 0, 0};
+    hop_full(dims, nr, (const cplx *)u, theta ? theta : zero, dagger_ ? -1 : 1, a, b);
+    extract(dims, nr, out_parity, b, (cplx *)out_half);
+    free(a);
+    free(b);
+    return ORC_OK;
+}
+
+/* D_hat psi_e = psi_e - kappa^2 H_eo H_oe psi_e (dagger: with H^+ blocks). */
+int orc_deo(const int *dims, int nr, const double *u, double kappa, const double *theta,
+            int dagger_, const double *in_e, double *out_e)
+{
+    if (!check_dims(dims, nr) || !even_dims(dims) || !in_e || !out_e || in_e == out_e)
+        return ORC_EINVAL;
+    const long h = vol(dims) / 2;
+    cplx *t = (cplx *)malloc(sizeof(cplx) * (size_t)h * 4 * nr);
+    int rc = orc_hop_eo(dims, nr, u, theta, dagger_, 1, in_e, (double *)t);
+    if (!rc) rc = orc_hop_eo(dims, nr, u, theta, dagger_, 0, (const double *)t, out_e);
+    free(t);
+    if (rc) return rc;
+    const long n = h * 4 * nr;
+    const cplx *a = (const cplx *)in_e;
+    cplx *b = (cplx *)out_e;
+    for (long i = 0; i < n; ++i) b[i] = a[i] - kappa * kappa * b[i];
+    return ORC_OK;
+}
+
+int orc_parity_count(const int *dims, int parity) { return (int)half_count(dims, parity & 1); }
+
+/* ------------------------------------------------------------------ CG */
+
+typedef struct {
+    const int *dims;
+    int nr;
+    const double *u;
+    double kappa;
+    const double *theta;
+    int system; /* 0: D^+D full lattice, 1: D_hat^+ D_hat on even sites */
+    cplx *tmp;
+} op_ctx;
+
+static void apply_normal(op_ctx *c, const cplx *in, cplx *out)
+{
+    if (c->system == 0) {
+        orc_dw(c->dims, c->nr, c->u, c->kappa, c->theta, 0, (const double *)in, (double *)c->tmp);
+        orc_dw(c->dims, c->nr, c->u, c->kappa, c->theta, 1, (const double *)c->tmp, (double *)out);
+    } else {
+        orc_deo(c->dims, c->nr, c->u, c->kappa, c->theta, 0, (const double *)in, (double *)c->tmp);
+        orc_deo(c->dims, c->nr, c->u, c->kappa, c->theta, 1, (const double *)c->tmp, (double *)out);
+    }
+}
+
+static double norm2(long n, const cplx *a)
+{
+    double s = 0;
+    for (long i = 0; i < n; ++i) s += creal(a[i]) * creal(a[i]) + cimag(a[i]) * cimag(a[i]);
+    return s;
+}
+
+static double re_dot(long n, const cplx *a, const cplx *b)
+{
+    double s = 0;
+    for (long i = 0; i < n; ++i) s += creal(conj(a[i]) * b[i]);
+    return s;
+}
+
+/*
+ * Conjugate gradient (Hestenes-Stiefel) for A x = eta, A = D^+D (system 0) or
+ * D_hat^+ D_hat on the even sites (system 1), starting from x = 0.  The loop
+ * stops when the recursive residual reaches tol; the true residual eta - A x
+ * is then recomputed and, if still above tol, CG restarts from it.
+ * alpha/beta (length max_iter, may be NULL) receive the coefficients for the
+ * Lanczos condition-number estimate.  info[0] = iterations, info[1] = true
+ * relative residual, info[2] = restarts.
+ */
+int orc_cg(const int *dims, int nr, const double *u, double kappa, const double *theta,
+           int system, const double *eta, double *x_out, double tol, int max_iter,
+           double *alpha_hist, double *beta_hist, double *info)
+{
+    if (!check_dims(dims, nr) || (system != 0 && system != 1) || !eta || !x_out)
+        return ORC_EINVAL;
+    if (system == 1 && !even_dims(dims)) return ORC_EINVAL;
+    const long sites = system == 0 ? vol(dims) : vol(dims) / 2;
+    const long n = sites * 4 * nr;
+    const size_t bytes = sizeof(cplx) * (size_t)n;
+    op_ctx c = {dims, nr, u, kappa, theta, system, (cplx *)malloc(bytes)};
+    cplx *x = (cplx *)x_out, *r = (cplx *)malloc(bytes), *p = (cplx *)malloc(bytes),
+         *q = (cplx *)malloc(bytes);
+    const cplx *b = (const cplx *)eta;
+    memset(x, 0, bytes);
+    memcpy(r, b, bytes);
+    memcpy(p, b, bytes);
+    const double bb = norm2(n, b);
+    double rr = bb;
+    int it = 0, restarts = 0, status = ORC_NOT_CONVERGED;
+    double true_rel = bb > 0 ? 1.0 : 0.0;
+    if (bb == 0) status = ORC_OK;
+    while (status == ORC_NOT_CONVERGED && it < max_iter) {
+        apply_normal(&c, p, q);
+        const double pq = re_dot(n, p, q);
+        if (!(pq > 0) || !isfinite(pq)) {
+            status = ORC_BREAKDOWN;
+            break;
+        }
+        const double a = rr / pq;
+        for (long i = 0; i < n; ++i) {
+            x[i] += a * p[i];
+            r[i] -= a * q[i];
+        }
+        const double rr_new = norm2(n, r);
+        const double bt = rr_new / rr;
+        if (alpha_hist) alpha_hist[it] = a;
+        if (beta_hist) beta_hist[it] = bt;
+        ++it;
+        if (sqrt(rr_new / bb) <= tol) {
+            apply_normal(&c, x, q);
+            for (long i = 0; i < n; ++i) r[i] = b[i] - q[i];
+            rr = norm2(n, r);
+            true_rel = sqrt(rr / bb);
+            if (true_rel <= tol) {
+                status = ORC_OK;
+                break;
+            }
+            memcpy(p, r, bytes);
+            ++restarts;
+            continue;
+        }
+        for (long i = 0; i < n; ++i) p[i] = r[i] + bt * p[i];
+        rr = rr_new;
+    }
+    if (status == ORC_NOT_CONVERGED) {
+        apply_normal(&c, x, q);
+        for (long i = 0; i < n; ++i) r[i] = b[i] - q[i];
+        true_rel = sqrt(norm2(n, r) / bb);
+    }
+    if (info) {
+        info[0] = it;
+        info[1] = true_rel;
+        info[2] = restarts;
+    }
+    free(c.tmp);
+    free(r);
+    free(p);
+    free(q);
+    return status;
+}
+
+/* ------------------------------------------------------------------ 16-bit rounding */
+
+/*
+ * Round a double to the nearest value of a binary floating-point format with
+ * p significand bits and smallest normal exponent emin (ties to even), by
+ * scaling to an integer: x = m 2^e with 0.5 <= |m| < 1, quantum
+ * 2^(max(e, emin + 1) - p).  Values beyond the largest finite number go to
+ * infinity as IEEE round-to-nearest prescribes.
+ */
+static double round_to_format(double x, int p, int emin, double maxfin)
+{
+    if (x == 0 || !isfinite(x)) return x;
+    int e;
+    frexp(x, &e);
+    if (e < emin + 1) e = emin + 1;
+    const double q = ldexp(1.0, e - p);
+    const double r = nearbyint(x / q) * q; /* default rounding mode: ties to even */
+    if (fabs(r) > maxfin) return copysign(INFINITY, x);
+    return r;
+}
+
+/* fmt: 0 = IEEE binary32, 1 = bfloat16, 2 = IEEE binary16. In-place on n doubles. */
+int orc_round(int fmt, long n, double *a)
+{
+    int p, emin;
+    double maxfin;
+    switch (fmt) {
+    case 0: p = 24; emin = -126; maxfin = ldexp(2.0 - ldexp(1.0, -23), 127); break;
+    case 1: p = 8; emin = -126; maxfin = ldexp(2.0 - ldexp(1.0, -7), 127); break;
+    case 2: p = 11; emin = -14; maxfin = 65504.0; break;
+    default: return ORC_EINVAL;
+    }
+    for (long i = 0; i < n; ++i) a[i] = round_to_format(a[i], p, emin, maxfin);
+    return ORC_OK;
+}
