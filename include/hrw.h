@@ -1,0 +1,216 @@
+/*
+ * hrw.h - C ABI of libhrw, the MI355X (gfx950) library for the Wilson-Dirac
+ * operator with fermions in a representation R of SU(N), its even/odd
+ * (Schur) form and conjugate-gradient inversion of D^dagger D.
+ *
+ * Method: arXiv 2405.19294, Sec. 3.1 (Wilson-Dirac operator in single and
+ * double precision for general higher representations of SU(N_c), with
+ * even/odd preconditioning), Sec. 3.1.2 (spinors carry N_f = N_R colour
+ * components, links are N_R x N_R matrices), Sec. 3.2 (site-wise linear
+ * algebra and reductions) and Sec. 3.3 (CG).
+ *
+ * Conventions (the paper leaves them open; these readings are binding):
+ *   - Lattice extents dims[0..3]; dims[0] is time; site index lexicographic
+ *     with x3 fastest.  Every extent must be even and >= 2.
+ *   - Euclidean chiral gamma basis, gamma_5 = g0 g1 g2 g3 = diag(1,1,-1,-1):
+ *       g0 = [[0,-1],[-1,0]],  gk = [[0,-i s_k],[i s_k,0]]  (2x2 blocks).
+ *   - (H psi)(x) = sum_mu ph+_mu(x) (1 - g_mu) U_mu(x) psi(x+mu)
+ *                       + ph-_mu(x) (1 + g_mu) U_mu(x-mu)^+ psi(x-mu),
+ *     D_W = 1 - kappa H (Wilson r = 1).  ph+_mu(x) = exp(i theta_mu) if
+ *     x_mu = N_mu - 1, ph-_mu(x) = exp(-i theta_mu) if x_mu = 0, else 1.
+ *     Phases are applied on wrap-crossing hops, never stored in U, so one
+ *     resident gauge field serves every theta.  theta = (pi,0,0,0) is
+ *     antiperiodic time.
+ *   - Even sites: x0+x1+x2+x3 even.  H_eo maps odd to even sites, H_oe even
+ *     to odd.  D_hat = 1 - kappa^2 H_eo H_oe acts on even sites.
+ *   - Representation bases: adjoint generators T^a = generalised Gell-Mann / 2
+ *     (symmetric off-diagonal pairs j<k, antisymmetric pairs j<k, then the
+ *     diagonal ones), (U_adj)_ab = 2 Re Tr(T^a U T^b U^+); two-index
+ *     symmetric / antisymmetric bases e_(jk) over lexicographic pairs
+ *     (j<=k / j<k), normalised to Tr(e^+ e) = 1, acted on by M -> U M U^T.
+ *
+ * Canonical layout (every pointer argument below, unless stated otherwise):
+ *   - interleaved complex FP64 (re, im);
+ *   - spinor field [site][spin 4][colour N_R]; n_rhs fields are stacked
+ *     [rhs][site][spin][colour];
+ *   - gauge field [site][mu 4][row][col], U_mu(x) joins x to x+mu;
+ *   - half-parity fields list that parity's sites in lexicographic order.
+ * The library converts to its own device layout internally.
+ *
+ * Ownership: every field, storage and workspace pointer is device memory owned
+ * by the caller (the Python binding takes it from torch).  The library
+ * allocates no device memory.  A gauge handle owns only a small host struct;
+ * the represented links live in the caller's storage until
+ * hrw_gauge_destroy.  Calls are ordered on the caller's HIP stream (NULL =
+ * default stream) and return after enqueueing, except hrw_cg_solve, which
+ * returns when the solve is complete.
+ *
+ * Errors: every call returns an int status.  Arguments are validated before
+ * anything is enqueued; on a negative status nothing was enqueued (except
+ * HRW_EDEVICE, which reports a failed HIP call) and hrw_last_error() returns
+ * a message for the calling thread.
+ */
+#ifndef HRW_H
+#define HRW_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+#define HRW_OK 0
+#define HRW_NOT_CONVERGED 1 /* result written, tolerance not reached */
+#define HRW_EINVAL (-1)       /* null pointer, bad extent, bad enum value */
+#define HRW_EUNSUPPORTED (-2) /* N_c / representation / dtype combination not built */
+#define HRW_ENOMEM (-3)       /* storage or workspace smaller than required */
+#define HRW_EDEVICE (-4)      /* a HIP call failed */
+#define HRW_EBREAKDOWN (-5)   /* CG breakdown: non-finite value or Re<p,Ap> <= 0 */
+
+/* ---------------------------------------------------------------- enums */
+enum hrw_rep { HRW_REP_FUND = 0, HRW_REP_ADJ = 1, HRW_REP_SYM = 2, HRW_REP_ASYM = 3 };
+
+/* Precision of link/spinor storage; arithmetic is FP64 for HRW_F64 and FP32
+ * for the others (FP32 accumulation for the 16-bit storage formats). */
+enum hrw_dtype { HRW_F64 = 0, HRW_F32 = 1, HRW_BF16 = 2, HRW_F16 = 3 };
+
+/* storage_mask bits for hrw_gauge_create: which link precisions to keep */
+#define HRW_STORE_F64 (1u << HRW_F64)
+#define HRW_STORE_F32 (1u << HRW_F32)
+#define HRW_STORE_BF16 (1u << HRW_BF16)
+#define HRW_STORE_F16 (1u << HRW_F16)
+
+/* Linear systems hrw_cg_solve can solve. */
+enum hrw_system {
+    HRW_SYS_DDAG_D_FULL = 0, /* D^+ D x = b on the full lattice                       */
+    HRW_SYS_DDAG_D_EO = 1,   /* D_hat^+ D_hat x_e = b_e on the even sites (half field) */
+    HRW_SYS_D_CGNR_EO = 2    /* D x = b on the full lattice via the even/odd Schur
+                                complement, CG on its normal equations, and
+                                reconstruction of the odd sites                     */
+};
+
+typedef struct hrw_gauge hrw_gauge; /* opaque resident represented gauge field */
+
+typedef struct {
+    double tol;            /* stop when the FP64 true relative residual <= tol   */
+    int max_iter;          /* iteration cap (per right-hand side)                */
+    int system;            /* enum hrw_system                                     */
+    int inner_dtype;       /* HRW_F64: plain FP64 CG; F32/BF16/F16: mixed precision
+                              with FP64 reliable updates                          */
+    int reliable_every;    /* iterations between FP64 reliable updates (mixed)   */
+    double reliable_delta; /* also update when |r| fell by this factor since the
+                              last update (0 = off)                               */
+    double theta[4];       /* boundary phases                                     */
+} hrw_solve_params;
+
+typedef struct {
+    int status;                 /* HRW_OK, HRW_NOT_CONVERGED or HRW_EBREAKDOWN        */
+    int iters;                  /* CG iterations performed                            */
+    int reliable_updates;       /* FP64 reliable updates (mixed precision)            */
+    int restarts;               /* restarts after a failed true-residual check        */
+    double true_rel_resid;      /* |b - A x| / |b| recomputed in FP64 at exit         */
+    double recursive_rel_resid; /* the iterated residual at exit                      */
+    double d_rel_resid;         /* HRW_SYS_D_CGNR_EO: |b - D x| / |b| in FP64, else 0 */
+    double seconds;             /* wall time of the whole call                        */
+} hrw_solve_result;
+
+/* ---------------------------------------------------------------- calls */
+
+/* Last error message of the calling thread ("" if none). */
+const char *hrw_last_error(void);
+
+/* Library version string. */
+const char *hrw_version(void);
+
+/* Dimension N_R of representation rep of SU(nc): N, N^2-1, N(N+1)/2, N(N-1)/2.
+ * Sec. 3.1.2 (spinor ~ N_f, link ~ N_f^2).  EINVAL for nc < 2 or bad rep. */
+int hrw_rep_dim(int nc, int rep, int *n_r);
+
+/* Stateless representation map U_F -> U_R for n_links links (Sec. 3.1:
+ * fermions in general higher representations; the link each fermion sees is
+ * the represented one).  u_f: device [n_links][nc][nc] complex FP64;
+ * u_r: device [n_links][N_R][N_R] complex FP64 (caller-allocated, must not
+ * overlap u_f).  Supported nc: 2, 3, 4.  Enqueued on stream. */
+int hrw_rep_map(int nc, int rep, long long n_links, const double *u_f, double *u_r,
+                void *stream);
+
+/* Bytes of device storage hrw_gauge_create needs for the given links.
+ * The resident field keeps, per requested precision, each link twice (once
+ * per parity's hopping block) in the library's device layout. */
+int hrw_gauge_storage_size(const int dims[4], int nc, int rep, unsigned storage_mask,
+                           size_t *bytes);
+
+/* Build a resident represented gauge field from fundamental links u_f
+ * (device, canonical [V][4][nc][nc] complex FP64).  The representation map
+ * runs on the device in FP64 and the result is rounded once (ties to even)
+ * into each precision in storage_mask (must include HRW_STORE_F64 whenever
+ * FP64 operators or solves will be used).  storage: caller-owned device
+ * memory of at least hrw_gauge_storage_size bytes, alive until destroy.
+ * On success *out receives the handle. */
+int hrw_gauge_create(const int dims[4], int nc, int rep, const double *u_f,
+                     unsigned storage_mask, void *storage, size_t storage_bytes, void *stream,
+                     hrw_gauge **out);
+
+/* Free the host struct (the caller frees the storage). NULL is accepted. */
+int hrw_gauge_destroy(hrw_gauge *g);
+
+/* Representation dimension and lattice of a handle. */
+int hrw_gauge_info(const hrw_gauge *g, int dims[4], int *nc, int *rep, int *n_r,
+                   unsigned *storage_mask);
+
+/* Workspace bytes for the operator applies (params == NULL) or for
+ * hrw_cg_solve with these params, for n_rhs right-hand sides.  This is also
+ * the per-request device footprint the serving loop admits by. */
+int hrw_workspace_size(const int dims[4], int nc, int rep, int n_rhs,
+                       const hrw_solve_params *params, size_t *bytes);
+
+/* out = D_W in (dagger = 0) or D_W^+ in (dagger = 1), D_W = 1 - kappa H
+ * (Sec. 3.1), for n_rhs stacked full-lattice fields, computed with links and
+ * spinors stored in dtype (inputs are rounded once to dtype; FP32
+ * accumulation below FP64).  in/out: device canonical FP64, must not overlap.
+ * theta: host double[4]. */
+int hrw_dw_apply(const hrw_gauge *g, double kappa, const double theta[4], int dtype, int n_rhs,
+                 int dagger, const double *in, double *out, void *workspace, size_t ws_bytes,
+                 void *stream);
+
+/* Off-diagonal hopping block: out_parity = 0 gives H_eo (odd -> even), 1 gives
+ * H_oe (even -> odd); dagger = 1 gives the corresponding block of H^+
+ * (Sec. 3.1, even/odd preconditioning).  in_half / out_half: device canonical
+ * half-parity fields, n_rhs stacked. */
+int hrw_hop_eo(const hrw_gauge *g, int out_parity, const double theta[4], int dtype, int n_rhs,
+               int dagger, const double *in_half, double *out_half, void *workspace,
+               size_t ws_bytes, void *stream);
+
+/* out_e = D_hat in_e, D_hat = 1 - kappa^2 H_eo H_oe on even sites (dagger: the
+ * adjoint, 1 - kappa^2 (H^+)_eo (H^+)_oe).  kappa_per_rhs: host double[n_rhs]. */
+int hrw_deo_apply(const hrw_gauge *g, const double *kappa_per_rhs, const double theta[4],
+                  int dtype, int n_rhs, int dagger, const double *in_e, double *out_e,
+                  void *workspace, size_t ws_bytes, void *stream);
+
+/* Conjugate gradient (Sec. 3.3) for n_rhs independent systems sharing the
+ * gauge field, each with its own kappa (host double[n_rhs]).  b and x are
+ * device canonical fields: half-parity (even) for HRW_SYS_DDAG_D_EO, full
+ * lattice otherwise.  x = 0 is the start vector; the loop stops each system
+ * on its FP64 true relative residual.  res: host array of n_rhs results.
+ * Returns HRW_OK when every system converged, HRW_NOT_CONVERGED if any hit
+ * max_iter, HRW_EBREAKDOWN if any broke down (others are still solved). */
+int hrw_cg_solve(const hrw_gauge *g, const hrw_solve_params *params, int n_rhs,
+                 const double *kappa_per_rhs, const double *b, double *x, hrw_solve_result *res,
+                 void *workspace, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------- timing
+ * Optional per-kernel timing with HIP events recorded on the launch stream
+ * around every hopping-kernel launch.  hrw_timing_enable(1) clears the
+ * counters; hrw_timing_read fills, for kernel class k (0 = hopping kernel,
+ * 1 = CG vector kernels, 2 = reductions), the launch count, summed event
+ * time in ms and summed algorithmic bytes (min-traffic model).  Returns
+ * EINVAL for an unknown class.  Not thread-safe against concurrent solves. */
+int hrw_timing_enable(int on);
+int hrw_timing_read(int kernel_class, long long *launches, double *total_ms, double *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HRW_H */

@@ -288,3 +288,35 @@ def num_threads() -> int:
     if v and v.isdigit():
         return int(v)
     return os.cpu_count() or 1
+
+
+# ---------------------------------------------------------------- rounding-error bound
+
+def hop_abs(dims, u_r_abs, psi_abs) -> np.ndarray:
+    """|H| |psi|: the hop with every link, projector and spinor entry replaced by
+    its absolute value (boundary phases have modulus one and drop out).
+
+    Used for the a-priori componentwise bound of a low-precision D_W
+    evaluation, |D psi - fl(D psi)| <= gamma_k (|psi| + kappa |H| |psi|),
+    gamma_k = k u / (1 - k u) (Higham, Accuracy and Stability of Numerical
+    Algorithms, Sec. 3.1).
+    """
+    d = tuple(int(v) for v in dims)
+    nr = psi_abs.shape[-1]
+    u = np.asarray(u_r_abs, dtype=np.float64).reshape(d + (4, nr, nr))
+    p = np.asarray(psi_abs, dtype=np.float64).reshape(d + (4, nr))
+    out = np.zeros_like(p)
+    for mu in range(4):
+        g = np.abs(gamma(mu))
+        pf = np.roll(p, -1, axis=mu)            # psi(x + mu)
+        pb = np.roll(p, 1, axis=mu)             # psi(x - mu)
+        ub = np.roll(u[..., mu, :, :], 1, axis=mu)  # U_mu(x - mu)
+        proj = np.eye(4) + g                    # |1 -+ g| entrywise
+        tf = np.einsum("...ab,...sb->...sa", u[..., mu, :, :], pf)
+        tb = np.einsum("...ba,...sb->...sa", ub, pb)
+        out += np.einsum("st,...tc->...sc", proj, tf + tb)
+    return out.reshape(np.asarray(psi_abs).shape)
+
+
+def gamma_k(k: int, unit_roundoff: float) -> float:
+    return k * unit_roundoff / (1 - k * unit_roundoff)

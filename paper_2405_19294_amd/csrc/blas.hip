@@ -1,0 +1,384 @@
+// Site-wise linear algebra and reductions for the solvers (arXiv 2405.19294,
+// Sec. 3.2: streaming spinor kernels; inner products and norms reduce a field
+// to a number in two stages).  Here the first stage is fused into the kernel
+// that produces the field (per-workgroup partials in FP64, wave shuffles then
+// LDS, fixed order) and the second stage is one small kernel per right-hand
+// side that also evaluates the CG coefficients on the device, so no scalar
+// travels to the host inside the iteration.  Every reduction uses a fixed
+// order: results are bitwise reproducible run to run.
+#include <math.h>
+
+#include "kernels.h"
+
+namespace hrw {
+
+static __device__ inline double block_sum(double v, double *sh)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) r += sh[k];
+    __syncthreads();
+    return r;
+}
+
+int vec_grid(size_t elems)
+{
+    size_t b = (elems + WG - 1) / WG;
+    if (b > 2048) b = 2048;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+// ------------------------------------------------------------------ fills and copies
+
+__global__ void __launch_bounds__(WG) zero_kernel(uint4 *p, size_t n16, unsigned char *tail, size_t ntail)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n16; t += stride)
+        p[t] = make_uint4(0, 0, 0, 0);
+    if (blockIdx.x == 0 && threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+hipError_t launch_zero(void *dst, size_t bytes, hipStream_t st)
+{
+    if (bytes == 0) return hipSuccess;
+    // callers pass 16-byte aligned buffers; the tail (< 16 bytes) is cleared bytewise
+    const size_t n16 = bytes / 16;
+    const size_t ntail = bytes - n16 * 16;
+    size_t b = (n16 + WG - 1) / WG;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    zero_kernel<<<(unsigned)b, WG, 0, st>>>((uint4 *)dst, n16, (unsigned char *)dst + n16 * 16, ntail);
+    return hipGetLastError();
+}
+
+template <class S>
+__global__ void __launch_bounds__(WG) copy_kernel(const cpx<S> *__restrict__ a, cpx<S> *__restrict__ b, size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) b[t] = a[t];
+}
+
+template <class S>
+hipError_t launch_copy(const cpx<S> *src, cpx<S> *dst, size_t elems, hipStream_t st)
+{
+    copy_kernel<S><<<vec_grid(elems), WG, 0, st>>>(src, dst, elems);
+    return hipGetLastError();
+}
+
+template <class Ss, class Sd>
+__global__ void __launch_bounds__(WG) convert_kernel(const cpx<Ss> *__restrict__ a, cpx<Sd> *__restrict__ b, size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+        typename acc_of<Ss>::type re, im;
+        load_c(a + t, re, im);
+        cpx<Sd> v;
+        // FP64 sources round once to the destination format; others go through FP32
+        if constexpr (std::is_same<Ss, double>::value) {
+            v.re = conv<Sd>::from_f64(re);
+            v.im = conv<Sd>::from_f64(im);
+        } else {
+            v.re = conv<Sd>::from_acc((typename acc_of<Sd>::type)re);
+            v.im = conv<Sd>::from_acc((typename acc_of<Sd>::type)im);
+        }
+        b[t] = v;
+    }
+}
+
+hipError_t launch_convert(int dt_src, const void *src, int dt_dst, void *dst, size_t elems,
+                          hipStream_t st)
+{
+    bool ok = dispatch_dtype(dt_src, [&](auto sa) {
+        typedef decltype(sa) Ss;
+        dispatch_dtype(dt_dst, [&](auto sb) {
+            typedef decltype(sb) Sd;
+            convert_kernel<Ss, Sd><<<vec_grid(elems), WG, 0, st>>>((const cpx<Ss> *)src, (cpx<Sd> *)dst, elems);
+        });
+    });
+    if (!ok) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ reductions
+
+template <class S>
+__global__ void __launch_bounds__(WG) norm2_kernel(const cpx<S> *__restrict__ a, size_t n, size_t rstride,
+                                                    double *partial, int pstride)
+{
+    __shared__ double sh[WG / 64];
+    const int rhs = blockIdx.y;
+    const cpx<S> *ar = a + (size_t)rhs * rstride;
+    double s = 0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+        typename acc_of<S>::type re, im;
+        load_c(ar + t, re, im);
+        s += (double)re * re + (double)im * im;
+    }
+    const double tot = block_sum(s, sh);
+    if (threadIdx.x == 0) partial[(size_t)rhs * pstride + blockIdx.x] = tot;
+}
+
+template <class S>
+hipError_t launch_norm2(const cpx<S> *a, size_t elems, size_t rstride, int n_rhs, double *partial,
+                        int pstride, int nblocks, hipStream_t st)
+{
+    norm2_kernel<S><<<dim3(nblocks, n_rhs), WG, 0, st>>>(a, elems, rstride, partial, pstride);
+    return hipGetLastError();
+}
+
+template <class S>
+__global__ void __launch_bounds__(WG) residual_kernel(const cpx<S> *__restrict__ b, const cpx<S> *__restrict__ q,
+                                                       cpx<S> *__restrict__ r, size_t n, size_t rstride,
+                                                       double *partial, int pstride)
+{
+    typedef typename acc_of<S>::type A;
+    __shared__ double sh[WG / 64];
+    const int rhs = blockIdx.y;
+    const size_t ro = (size_t)rhs * rstride;
+    double s = 0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+        A br, bi, qr, qi;
+        load_c(b + ro + t, br, bi);
+        load_c(q + ro + t, qr, qi);
+        const A vr = br - qr, vi = bi - qi;
+        store_c(r + ro + t, vr, vi);
+        s += (double)vr * vr + (double)vi * vi;
+    }
+    const double tot = block_sum(s, sh);
+    if (threadIdx.x == 0) partial[(size_t)rhs * pstride + blockIdx.x] = tot;
+}
+
+template <class S>
+hipError_t launch_residual(const cpx<S> *b, const cpx<S> *q, cpx<S> *r, size_t elems, size_t rstride,
+                           int n_rhs, double *partial, int pstride, int nblocks, hipStream_t st)
+{
+    residual_kernel<S><<<dim3(nblocks, n_rhs), WG, 0, st>>>(b, q, r, elems, rstride, partial, pstride);
+    return hipGetLastError();
+}
+
+template <class S>
+__global__ void __launch_bounds__(WG) xpay_kernel(const cpx<S> *__restrict__ r, cpx<S> *__restrict__ p,
+                                                   const double *beta, const int *active, size_t n,
+                                                   size_t rstride)
+{
+    typedef typename acc_of<S>::type A;
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    const A bt = (A)beta[rhs];
+    const size_t ro = (size_t)rhs * rstride;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+        A rr, ri, pr, pi;
+        load_c(r + ro + t, rr, ri);
+        load_c(p + ro + t, pr, pi);
+        store_c(p + ro + t, rr + bt * pr, ri + bt * pi);
+    }
+}
+
+template <class S>
+hipError_t launch_xpay(const cpx<S> *r, cpx<S> *p, const double *beta, const int *active, size_t elems,
+                       size_t rstride, int n_rhs, hipStream_t st)
+{
+    xpay_kernel<S><<<dim3(vec_grid(elems), n_rhs), WG, 0, st>>>(r, p, beta, active, elems, rstride);
+    return hipGetLastError();
+}
+
+template <class Sx, class Sy>
+__global__ void __launch_bounds__(WG) axpy_mixed_kernel(const cpx<Sx> *__restrict__ x, cpx<Sy> *__restrict__ y,
+                                                         const double *a, size_t n, size_t rsx, size_t rsy)
+{
+    typedef typename acc_of<Sy>::type A;
+    const int rhs = blockIdx.y;
+    const A al = (A)a[rhs];
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+        typename acc_of<Sx>::type xr, xi;
+        load_c(x + (size_t)rhs * rsx + t, xr, xi);
+        A yr, yi;
+        load_c(y + (size_t)rhs * rsy + t, yr, yi);
+        store_c(y + (size_t)rhs * rsy + t, yr + al * (A)xr, yi + al * (A)xi);
+    }
+}
+
+hipError_t launch_axpy_mixed(int dt_x, const void *x, int dt_y, void *y, const double *a, size_t elems,
+                             size_t rstride_x, size_t rstride_y, int n_rhs, hipStream_t st)
+{
+    bool ok = dispatch_dtype(dt_x, [&](auto sx) {
+        typedef decltype(sx) Sx;
+        dispatch_dtype(dt_y, [&](auto sy) {
+            typedef decltype(sy) Sy;
+            axpy_mixed_kernel<Sx, Sy><<<dim3(vec_grid(elems), n_rhs), WG, 0, st>>>(
+                (const cpx<Sx> *)x, (cpx<Sy> *)y, a, elems, rstride_x, rstride_y);
+        });
+    });
+    if (!ok) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ second stage + CG scalars
+
+// sum of nparts partials of one rhs, in a fixed order; valid in thread 0
+static __device__ double sum_parts(const double *partial, int nparts, double *sh)
+{
+    double s = 0;
+    for (int k = threadIdx.x; k < nparts; k += blockDim.x) s += partial[k];
+    return block_sum(s, sh);
+}
+
+__global__ void __launch_bounds__(WG) sum_partials_kernel(const double *partial, int pstride, int nparts,
+                                                           double *out)
+{
+    __shared__ double sh[WG / 64];
+    const int rhs = blockIdx.x;
+    const double s = sum_parts(partial + (size_t)rhs * pstride, nparts, sh);
+    if (threadIdx.x == 0) out[rhs] = s;
+}
+
+hipError_t launch_sum_partials(const double *partial, int pstride, int nparts, int n_rhs, double *out,
+                               hipStream_t st)
+{
+    sum_partials_kernel<<<n_rhs, WG, 0, st>>>(partial, pstride, nparts, out);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(WG) cg_init_kernel(CgState *cs, const double *partial, int pstride,
+                                                      int nparts, double tol, int *active_out)
+{
+    __shared__ double sh[WG / 64];
+    const int rhs = blockIdx.x;
+    const double s = sum_parts(partial + (size_t)rhs * pstride, nparts, sh);
+    if (threadIdx.x == 0) {
+        CgState c;
+        c.rr = s;
+        c.rr0 = s;
+        c.pap = 0;
+        c.alpha = 0;
+        c.beta = 0;
+        c.tol2 = tol * tol * s;
+        c.rr_true = s;
+        c.iters = 0;
+        c.restarts = 0;
+        c.updates = 0;
+        c.pad_ = 0;
+        if (!(s == s) || isinf(s)) {
+            c.status = CG_BREAKDOWN;
+            c.active = 0;
+        } else if (s == 0) {
+            c.status = CG_DONE;
+            c.active = 0;
+        } else {
+            c.status = CG_RUNNING;
+            c.active = 1;
+        }
+        cs[rhs] = c;
+        active_out[rhs] = c.active;
+    }
+}
+
+hipError_t launch_cg_init(CgState *cs, const double *partial, int pstride, int nparts, int n_rhs,
+                          double tol, int *active_out, hipStream_t st)
+{
+    cg_init_kernel<<<n_rhs, WG, 0, st>>>(cs, partial, pstride, nparts, tol, active_out);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(WG) cg_alpha_kernel(CgState *cs, const double *partial, int pstride,
+                                                       int nparts, double *alpha_out)
+{
+    __shared__ double sh[WG / 64];
+    const int rhs = blockIdx.x;
+    const double pap = sum_parts(partial + (size_t)rhs * pstride, nparts, sh);
+    if (threadIdx.x == 0) {
+        CgState c = cs[rhs];
+        c.pap = pap;
+        if (c.active) {
+            if (!(pap > 0) || isinf(pap)) {
+                c.status = CG_BREAKDOWN;
+                c.active = 0;
+                c.alpha = 0;
+            } else {
+                c.alpha = c.rr / pap;
+            }
+        } else {
+            c.alpha = 0;
+        }
+        cs[rhs] = c;
+        alpha_out[rhs] = c.alpha;
+    }
+}
+
+hipError_t launch_cg_alpha(CgState *cs, const double *partial, int pstride, int nparts, int n_rhs,
+                           double *alpha_out, hipStream_t st)
+{
+    cg_alpha_kernel<<<n_rhs, WG, 0, st>>>(cs, partial, pstride, nparts, alpha_out);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(WG) cg_beta_kernel(CgState *cs, const double *partial, int pstride,
+                                                      int nparts, int max_iter, double *beta_out,
+                                                      int *active_out, volatile int *host_active)
+{
+    __shared__ double sh[WG / 64];
+    const int rhs = blockIdx.x;
+    const double rr_new = sum_parts(partial + (size_t)rhs * pstride, nparts, sh);
+    if (threadIdx.x == 0) {
+        CgState c = cs[rhs];
+        if (c.active) {
+            c.iters += 1;
+            c.beta = rr_new / c.rr;
+            c.rr = rr_new;
+            if (!(rr_new == rr_new) || isinf(rr_new)) {
+                c.status = CG_BREAKDOWN;
+                c.active = 0;
+            } else if (rr_new <= c.tol2) {
+                c.status = CG_RECURSIVE_DONE;
+                c.active = 0;
+            } else if (c.iters >= max_iter) {
+                c.status = CG_MAXITER;
+                c.active = 0;
+            }
+        } else {
+            c.beta = 0;
+        }
+        cs[rhs] = c;
+        beta_out[rhs] = c.beta;
+        active_out[rhs] = c.active;
+        if (host_active) host_active[rhs] = c.active;
+    }
+}
+
+hipError_t launch_cg_beta(CgState *cs, const double *partial, int pstride, int nparts, int n_rhs,
+                          int max_iter, double *beta_out, int *active_out, int *host_active,
+                          hipStream_t st)
+{
+    cg_beta_kernel<<<n_rhs, WG, 0, st>>>(cs, partial, pstride, nparts, max_iter, beta_out, active_out,
+                                         host_active);
+    return hipGetLastError();
+}
+
+
+template hipError_t launch_copy<double>(const cpx<double> *, cpx<double> *, size_t, hipStream_t);
+template hipError_t launch_copy<float>(const cpx<float> *, cpx<float> *, size_t, hipStream_t);
+template hipError_t launch_copy<bf16_t>(const cpx<bf16_t> *, cpx<bf16_t> *, size_t, hipStream_t);
+template hipError_t launch_copy<f16_t>(const cpx<f16_t> *, cpx<f16_t> *, size_t, hipStream_t);
+#define HRW_INST(S)                                                                                     \
+    template hipError_t launch_norm2<S>(const cpx<S> *, size_t, size_t, int, double *, int, int,        \
+                                        hipStream_t);                                                  \
+    template hipError_t launch_residual<S>(const cpx<S> *, const cpx<S> *, cpx<S> *, size_t, size_t, int, \
+                                           double *, int, int, hipStream_t);                           \
+    template hipError_t launch_xpay<S>(const cpx<S> *, cpx<S> *, const double *, const int *, size_t,   \
+                                       size_t, int, hipStream_t);
+HRW_INST(double)
+HRW_INST(float)
+HRW_INST(bf16_t)
+HRW_INST(f16_t)
+#undef HRW_INST
+
+}  // namespace hrw

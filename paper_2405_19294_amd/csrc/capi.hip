@@ -1,0 +1,284 @@
+// extern "C" entry points of libhrw (declared in include/hrw.h).  Each call
+// validates its arguments before enqueueing anything and reports failures
+// through a status code plus a thread-local message.
+#include <string.h>
+
+#include <exception>
+#include <new>
+
+#include "engine.h"
+
+namespace hrw {
+const char *last_error();
+}
+
+using namespace hrw;
+
+namespace {
+
+int rep_dim_of(int nc, int rep)
+{
+    switch (rep) {
+    case HRW_REP_FUND: return nc;
+    case HRW_REP_ADJ: return nc * nc - 1;
+    case HRW_REP_SYM: return nc * (nc + 1) / 2;
+    case HRW_REP_ASYM: return nc * (nc - 1) / 2;
+    }
+    return -1;
+}
+
+int check_lattice(const int dims[4])
+{
+    if (!dims) return fail(HRW_EINVAL, "dims is null");
+    long long v = 1;
+    for (int m = 0; m < 4; ++m) {
+        if (dims[m] < 2 || dims[m] % 2) return fail(HRW_EINVAL, "extent dims[%d] = %d must be even and >= 2", m, dims[m]);
+        v *= dims[m];
+    }
+    if (v / 2 > (1LL << 30)) return fail(HRW_EINVAL, "lattice too large");
+    return HRW_OK;
+}
+
+int check_group(int nc, int rep, int *nr)
+{
+    if (nc < 2 || rep < 0 || rep > 3) return fail(HRW_EINVAL, "bad nc %d or rep %d", nc, rep);
+    if (nc > 4) return fail(HRW_EUNSUPPORTED, "nc = %d not built (2..4)", nc);
+    const int r = rep_dim_of(nc, rep);
+    if (r < 2 || !nr_supported(r)) return fail(HRW_EUNSUPPORTED, "representation dimension %d has no kernels", r);
+    *nr = r;
+    return HRW_OK;
+}
+
+int check_dtype(int dt)
+{
+    if (dt < 0 || dt > 3) return fail(HRW_EINVAL, "bad dtype %d", dt);
+    return HRW_OK;
+}
+
+int check_rhs(int n)
+{
+    if (n < 1 || n > MAX_RHS) return fail(HRW_EINVAL, "n_rhs = %d outside 1..%d", n, MAX_RHS);
+    return HRW_OK;
+}
+
+template <class F>
+int guarded(F &&f)
+{
+    clear_error();
+    try {
+        return f();
+    } catch (const std::bad_alloc &) {
+        return fail(HRW_ENOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(HRW_EDEVICE, "internal error: %s", e.what());
+    } catch (...) {
+        return fail(HRW_EDEVICE, "internal error");
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hrw_last_error(void) { return last_error(); }
+
+const char *hrw_version(void) { return "hrw 0.1 gfx950"; }
+
+int hrw_rep_dim(int nc, int rep, int *n_r)
+{
+    return guarded([&] {
+        if (!n_r) return fail(HRW_EINVAL, "n_r is null");
+        if (nc < 2 || rep < 0 || rep > 3) return fail(HRW_EINVAL, "bad nc %d or rep %d", nc, rep);
+        *n_r = rep_dim_of(nc, rep);
+        return HRW_OK;
+    });
+}
+
+int hrw_rep_map(int nc, int rep, long long n_links, const double *u_f, double *u_r, void *stream)
+{
+    return guarded([&] {
+        if (nc < 2 || rep < 0 || rep > 3 || n_links < 0) return fail(HRW_EINVAL, "bad arguments");
+        if (nc > 4) return fail(HRW_EUNSUPPORTED, "nc = %d not built (2..4)", nc);
+        if (rep_dim_of(nc, rep) < 2) return fail(HRW_EUNSUPPORTED, "trivial representation");
+        if (n_links > 0 && (!u_f || !u_r)) return fail(HRW_EINVAL, "null field pointer");
+        HRW_HIP(launch_rep_map(nc, rep, n_links, u_f, u_r, (hipStream_t)stream));
+        return HRW_OK;
+    });
+}
+
+int hrw_gauge_storage_size(const int dims[4], int nc, int rep, unsigned storage_mask, size_t *bytes)
+{
+    return guarded([&] {
+        int nr, rc;
+        if ((rc = check_lattice(dims)) || (rc = check_group(nc, rep, &nr))) return rc;
+        if (!bytes || !(storage_mask & 0xf) || (storage_mask & ~0xfu)) return fail(HRW_EINVAL, "bad storage mask or null output");
+        return gauge_storage_bytes(make_geom(dims), nr, storage_mask, bytes);
+    });
+}
+
+int hrw_gauge_create(const int dims[4], int nc, int rep, const double *u_f, unsigned storage_mask, void *storage,
+                     size_t storage_bytes, void *stream, hrw_gauge **out)
+{
+    return guarded([&] {
+        int nr, rc;
+        if ((rc = check_lattice(dims)) || (rc = check_group(nc, rep, &nr))) return rc;
+        if (!u_f || !storage || !out) return fail(HRW_EINVAL, "null pointer");
+        if (!(storage_mask & 0xf) || (storage_mask & ~0xfu)) return fail(HRW_EINVAL, "bad storage mask");
+        const Geom g = make_geom(dims);
+        size_t need;
+        gauge_storage_bytes(g, nr, storage_mask, &need);
+        if (storage_bytes < need) return fail(HRW_ENOMEM, "storage too small: need %zu bytes", need);
+        hrw_gauge *h = new hrw_gauge;
+        memset(h, 0, sizeof *h);
+        for (int m = 0; m < 4; ++m) h->dims[m] = dims[m];
+        h->nc = nc;
+        h->rep = rep;
+        h->nr = nr;
+        h->mask = storage_mask;
+        h->g = g;
+        Arena ar(storage, storage_bytes);
+        for (int d = 0; d < 4; ++d)
+            if (storage_mask & (1u << d))
+                for (int q = 0; q < 2; ++q) h->blocks[d][q] = ar.take(gauge_block_elems(g, nr) * dtype_cbytes(d));
+        hipError_t e = launch_gauge_pack(nc, rep, nr, g, u_f, h->blocks, (hipStream_t)stream);
+        if (e != hipSuccess) {
+            delete h;
+            return fail(HRW_EDEVICE, "gauge packing failed: %s", hipGetErrorString(e));
+        }
+        *out = h;
+        return HRW_OK;
+    });
+}
+
+int hrw_gauge_destroy(hrw_gauge *g)
+{
+    delete g;
+    return HRW_OK;
+}
+
+int hrw_gauge_info(const hrw_gauge *g, int dims[4], int *nc, int *rep, int *n_r, unsigned *storage_mask)
+{
+    if (!g) return fail(HRW_EINVAL, "null gauge");
+    if (dims)
+        for (int m = 0; m < 4; ++m) dims[m] = g->dims[m];
+    if (nc) *nc = g->nc;
+    if (rep) *rep = g->rep;
+    if (n_r) *n_r = g->nr;
+    if (storage_mask) *storage_mask = g->mask;
+    return HRW_OK;
+}
+
+static int check_params(const hrw_solve_params *p)
+{
+    if (!p) return fail(HRW_EINVAL, "params is null");
+    if (!(p->tol > 0) || p->max_iter < 1) return fail(HRW_EINVAL, "tol must be > 0 and max_iter >= 1");
+    if (p->system < 0 || p->system > 2) return fail(HRW_EINVAL, "bad system %d", p->system);
+    if (p->inner_dtype < 0 || p->inner_dtype > 3) return fail(HRW_EINVAL, "bad inner dtype %d", p->inner_dtype);
+    if (p->reliable_every < 0) return fail(HRW_EINVAL, "reliable_every must be >= 0");
+    return HRW_OK;
+}
+
+int hrw_workspace_size(const int dims[4], int nc, int rep, int n_rhs, const hrw_solve_params *params, size_t *bytes)
+{
+    return guarded([&] {
+        int nr, rc;
+        if ((rc = check_lattice(dims)) || (rc = check_group(nc, rep, &nr)) || (rc = check_rhs(n_rhs))) return rc;
+        if (!bytes) return fail(HRW_EINVAL, "bytes is null");
+        const Geom g = make_geom(dims);
+        if (!params) return apply_workspace(g, nr, n_rhs, bytes);
+        if ((rc = check_params(params))) return rc;
+        return cg_workspace(g, nr, n_rhs, params, bytes);
+    });
+}
+
+static int check_apply(const hrw_gauge *g, int dt, int n_rhs, const void *in, const void *out)
+{
+    int rc;
+    if (!g) return fail(HRW_EINVAL, "null gauge");
+    if ((rc = check_dtype(dt)) || (rc = check_rhs(n_rhs))) return rc;
+    if (!in || !out) return fail(HRW_EINVAL, "null field pointer");
+    if (in == out) return fail(HRW_EINVAL, "in and out must not overlap");
+    if (!g->blocks[dt][0]) return fail(HRW_EUNSUPPORTED, "gauge field has no links stored in dtype %d", dt);
+    return HRW_OK;
+}
+
+int hrw_dw_apply(const hrw_gauge *g, double kappa, const double theta[4], int dtype, int n_rhs, int dagger,
+                 const double *in, double *out, void *workspace, size_t ws_bytes, void *stream)
+{
+    return guarded([&] {
+        int rc;
+        if ((rc = check_apply(g, dtype, n_rhs, in, out))) return rc;
+        if (!workspace) return fail(HRW_EINVAL, "null workspace");
+        return dw_apply(g, kappa, theta, dtype, n_rhs, dagger, in, out, workspace, ws_bytes, (hipStream_t)stream);
+    });
+}
+
+int hrw_hop_eo(const hrw_gauge *g, int out_parity, const double theta[4], int dtype, int n_rhs, int dagger,
+               const double *in_half, double *out_half, void *workspace, size_t ws_bytes, void *stream)
+{
+    return guarded([&] {
+        int rc;
+        if ((rc = check_apply(g, dtype, n_rhs, in_half, out_half))) return rc;
+        if (out_parity != 0 && out_parity != 1) return fail(HRW_EINVAL, "out_parity must be 0 or 1");
+        if (!workspace) return fail(HRW_EINVAL, "null workspace");
+        return hop_eo_apply(g, out_parity, theta, dtype, n_rhs, dagger, in_half, out_half, workspace, ws_bytes,
+                            (hipStream_t)stream);
+    });
+}
+
+int hrw_deo_apply(const hrw_gauge *g, const double *kappa_per_rhs, const double theta[4], int dtype, int n_rhs,
+                  int dagger, const double *in_e, double *out_e, void *workspace, size_t ws_bytes, void *stream)
+{
+    return guarded([&] {
+        int rc;
+        if ((rc = check_apply(g, dtype, n_rhs, in_e, out_e))) return rc;
+        if (!kappa_per_rhs || !workspace) return fail(HRW_EINVAL, "null kappa or workspace");
+        return deo_apply(g, kappa_per_rhs, theta, dtype, n_rhs, dagger, in_e, out_e, workspace, ws_bytes,
+                         (hipStream_t)stream);
+    });
+}
+
+int hrw_cg_solve(const hrw_gauge *g, const hrw_solve_params *params, int n_rhs, const double *kappa_per_rhs,
+                 const double *b, double *x, hrw_solve_result *res, void *workspace, size_t ws_bytes, void *stream)
+{
+    return guarded([&] {
+        int rc;
+        if (!g) return fail(HRW_EINVAL, "null gauge");
+        if ((rc = check_params(params)) || (rc = check_rhs(n_rhs))) return rc;
+        if (!kappa_per_rhs || !b || !x || !res || !workspace) return fail(HRW_EINVAL, "null pointer");
+        if (b == x) return fail(HRW_EINVAL, "b and x must not overlap");
+        if (params->reliable_delta != 0) return fail(HRW_EUNSUPPORTED, "reliable_delta is not implemented (use 0)");
+        if (!g->blocks[0][0]) return fail(HRW_EUNSUPPORTED, "CG needs FP64 links (HRW_STORE_F64)");
+        if (!g->blocks[params->inner_dtype][0]) return fail(HRW_EUNSUPPORTED, "gauge field lacks links in the inner dtype");
+        return cg_solve(g, params, n_rhs, kappa_per_rhs, b, x, res, workspace, ws_bytes, (hipStream_t)stream);
+    });
+}
+
+int hrw_timing_enable(int on)
+{
+    Timing &t = timing();
+    timing_harvest();
+    std::lock_guard<std::mutex> lk(t.mu);
+    t.on = on != 0;
+    for (int k = 0; k < KC_COUNT; ++k) {
+        t.launches[k] = 0;
+        t.ms[k] = 0;
+        t.bytes[k] = 0;
+    }
+    return HRW_OK;
+}
+
+int hrw_timing_read(int kernel_class, long long *launches, double *total_ms, double *bytes)
+{
+    if (kernel_class < 0 || kernel_class >= KC_COUNT) return fail(HRW_EINVAL, "unknown kernel class");
+    int rc = timing_harvest();
+    if (rc) return rc;
+    Timing &t = timing();
+    std::lock_guard<std::mutex> lk(t.mu);
+    if (launches) *launches = t.launches[kernel_class];
+    if (total_ms) *total_ms = t.ms[kernel_class];
+    if (bytes) *bytes = t.bytes[kernel_class];
+    return HRW_OK;
+}
+
+}  // extern "C"

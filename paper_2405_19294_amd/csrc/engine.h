@@ -1,0 +1,138 @@
+// Host-side engine of libhrw: resident gauge fields, workspace planning,
+// operator applies and the CG driver.  Internal to the library.
+#pragma once
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/hrw.h"
+#include "kernels.h"
+
+struct hrw_gauge {
+    int dims[4];
+    int nc, rep, nr;
+    unsigned mask;
+    hrw::Geom g;
+    void *blocks[4][2];  // [dtype][output parity] packed hopping blocks (or null)
+};
+
+namespace hrw {
+
+// error reporting (thread-local message)
+int fail(int code, const char *fmt, ...);
+void clear_error();
+
+#define HRW_HIP(call)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess) return ::hrw::fail(HRW_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// bump allocator over a caller buffer; with base == nullptr it only measures
+struct Arena {
+    char *base;
+    size_t cap, off;
+    // the base is rounded up to 256 bytes; sizes reported to callers carry 256 bytes of slack
+    Arena(void *b, size_t c) : base(nullptr), cap(0), off(0)
+    {
+        if (b) {
+            const size_t a = ((size_t)b + 255) & ~(size_t)255;
+            const size_t lost = a - (size_t)b;
+            base = (char *)a;
+            cap = c > lost ? c - lost : 0;
+        }
+    }
+    void *take(size_t bytes)
+    {
+        off = (off + 255) & ~(size_t)255;
+        void *p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    }
+    bool fits() const { return off <= cap; }
+};
+
+// ------------------------------------------------------------------ timing
+
+struct Timing {
+    std::mutex mu;
+    bool on = false;
+    struct Pending {
+        hipEvent_t a, b;
+        int kc;
+        double bytes;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    long long launches[KC_COUNT] = {0, 0, 0};
+    double ms[KC_COUNT] = {0, 0, 0};
+    double bytes[KC_COUNT] = {0, 0, 0};
+};
+Timing &timing();
+// record a start event (returns false when timing is off)
+bool timed_begin(hipStream_t st, hipEvent_t *ev);
+void timed_end(hipStream_t st, hipEvent_t start, int kc, double bytes);
+int timing_harvest();
+
+// ------------------------------------------------------------------ operator plumbing
+
+struct Phases {
+    double re[4], im[4];
+};
+Phases make_phases(const double theta[4]);
+
+// algorithmic bytes of one hop launch (min-traffic model)
+double hop_bytes(const Geom &g, int nr, int dt, int parity, int epi, int n_rhs);
+
+// generic hop launch with timing, dtype-erased pointers
+struct HopCall {
+    int dt = 0;
+    int parity = 0;
+    bool dagger = false;
+    int epi = EPI_PLAIN;
+    int n_rhs = 1;
+    size_t rstride = 0;
+    const void *in[2] = {nullptr, nullptr};
+    void *out[2] = {nullptr, nullptr};
+    const void *self[2] = {nullptr, nullptr};
+    void *r[2] = {nullptr, nullptr};
+    void *x[2] = {nullptr, nullptr};
+    const void *p[2] = {nullptr, nullptr};
+    const double *coef = nullptr;
+    const double *alpha = nullptr;
+    const int *active = nullptr;
+    double *partial = nullptr;
+    int pstride = 0;
+};
+int run_hop(const hrw_gauge *g, const Phases &ph, const HopCall &c, hipStream_t st);
+
+// write host values into a device double / int array (by-value kernel argument)
+int set_device_doubles(double *dst, const double *vals, int n, hipStream_t st);
+
+// pinned, device-visible host flags for convergence polling
+struct HostFlags {
+    int *host = nullptr;
+    int *dev = nullptr;
+    int slot = -1;
+};
+int host_flags_acquire(HostFlags *f);
+void host_flags_release(HostFlags *f);
+
+// ------------------------------------------------------------------ engine entry points
+
+int gauge_storage_bytes(const Geom &g, int nr, unsigned mask, size_t *bytes);
+int apply_workspace(const Geom &g, int nr, int n_rhs, size_t *bytes);
+int cg_workspace(const Geom &g, int nr, int n_rhs, const hrw_solve_params *p, size_t *bytes);
+
+int dw_apply(const hrw_gauge *g, double kappa, const double theta[4], int dt, int n_rhs, int dagger,
+             const double *in, double *out, void *ws, size_t ws_bytes, hipStream_t st);
+int hop_eo_apply(const hrw_gauge *g, int out_parity, const double theta[4], int dt, int n_rhs,
+                 int dagger, const double *in, double *out, void *ws, size_t ws_bytes, hipStream_t st);
+int deo_apply(const hrw_gauge *g, const double *kappa, const double theta[4], int dt, int n_rhs,
+              int dagger, const double *in, double *out, void *ws, size_t ws_bytes, hipStream_t st);
+int cg_solve(const hrw_gauge *g, const hrw_solve_params *p, int n_rhs, const double *kappa,
+             const double *b, double *x, hrw_solve_result *res, void *ws, size_t ws_bytes,
+             hipStream_t st);
+
+}  // namespace hrw

@@ -1,0 +1,924 @@
+// Host engine of libhrw: resident represented gauge fields, operator applies
+// and the conjugate-gradient driver (arXiv 2405.19294, Sec. 3.1 operator and
+// even/odd preconditioning, Sec. 3.3 CG).
+//
+// All device memory belongs to the caller: the engine lays its packed fields,
+// partial sums and scalars out in the caller's workspace with a bump
+// allocator, and the same planner answers the workspace-size queries.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <chrono>
+
+#include "engine.h"
+
+namespace hrw {
+
+// ------------------------------------------------------------------ errors
+
+static thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+void clear_error() { g_err[0] = 0; }
+const char *last_error() { return g_err; }
+
+// ------------------------------------------------------------------ timing
+
+Timing &timing()
+{
+    static Timing t;
+    return t;
+}
+
+bool timed_begin(hipStream_t st, hipEvent_t *ev)
+{
+    Timing &t = timing();
+    std::lock_guard<std::mutex> lk(t.mu);
+    if (!t.on) return false;
+    if (t.pool.empty()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return false;
+        t.pool.push_back(e);
+    }
+    *ev = t.pool.back();
+    t.pool.pop_back();
+    if (hipEventRecord(*ev, st) != hipSuccess) {
+        t.pool.push_back(*ev);
+        return false;
+    }
+    return true;
+}
+
+void timed_end(hipStream_t st, hipEvent_t start, int kc, double bytes)
+{
+    Timing &t = timing();
+    std::lock_guard<std::mutex> lk(t.mu);
+    hipEvent_t e;
+    if (t.pool.empty()) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            t.pool.push_back(start);
+            return;
+        }
+    } else {
+        e = t.pool.back();
+        t.pool.pop_back();
+    }
+    (void)hipEventRecord(e, st);
+    t.pending.push_back({start, e, kc, bytes});
+}
+
+int timing_harvest()
+{
+    Timing &t = timing();
+    std::lock_guard<std::mutex> lk(t.mu);
+    for (auto &p : t.pending) {
+        hipError_t e = hipEventSynchronize(p.b);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.a, p.b);
+        if (e != hipSuccess) return fail(HRW_EDEVICE, "timing event: %s", hipGetErrorString(e));
+        t.launches[p.kc] += 1;
+        t.ms[p.kc] += ms;
+        t.bytes[p.kc] += p.bytes;
+        t.pool.push_back(p.a);
+        t.pool.push_back(p.b);
+    }
+    t.pending.clear();
+    return HRW_OK;
+}
+
+// ------------------------------------------------------------------ small helpers
+
+Phases make_phases(const double theta[4])
+{
+    Phases p;
+    for (int m = 0; m < 4; ++m) {
+        const double t = theta ? theta[m] : 0.0;
+        p.re[m] = cos(t);
+        p.im[m] = sin(t);
+    }
+    return p;
+}
+
+double hop_bytes(const Geom &g, int nr, int dt, int parity, int epi, int n_rhs)
+{
+    const double sites = (double)g.half * (parity < 0 ? 2 : 1);
+    const double cb = (double)dtype_cbytes(dt);
+    const double links = 8.0 * nr * nr * cb;
+    const double sp = 4.0 * nr * cb;
+    double per = links + sp;  // links + neighbour spinors (each input spinor once)
+    if (epi == EPI_PLAIN) per += sp;            // out
+    else if (epi == EPI_AXPY) per += 2 * sp;    // self + out
+    else per += 6 * sp;                         // self, r, x, p read; r, x written
+    return per * sites * n_rhs;
+}
+
+int run_hop(const hrw_gauge *g, const Phases &ph, const HopCall &c, hipStream_t st)
+{
+    if (!g->blocks[c.dt][0]) return fail(HRW_EUNSUPPORTED, "gauge field has no links stored in dtype %d", c.dt);
+    hipEvent_t ev;
+    const bool tm = timed_begin(st, &ev);
+    hipError_t err = hipErrorInvalidValue;
+    dispatch_dtype(c.dt, [&](auto sv) {
+        typedef decltype(sv) S;
+        HopArgs<S> a;
+        memset(&a, 0, sizeof a);
+        a.g = g->g;
+        a.parity = c.parity;
+        a.n_rhs = c.n_rhs;
+        a.rstride = c.rstride;
+        for (int q = 0; q < 2; ++q) {
+            a.gauge[q] = (const cpx<S> *)g->blocks[c.dt][q];
+            a.in[q] = (const cpx<S> *)c.in[q];
+            a.out[q] = (cpx<S> *)c.out[q];
+            a.self[q] = (const cpx<S> *)c.self[q];
+            a.r[q] = (cpx<S> *)c.r[q];
+            a.x[q] = (cpx<S> *)c.x[q];
+            a.p[q] = (const cpx<S> *)c.p[q];
+        }
+        for (int m = 0; m < 4; ++m) {
+            a.ph_re[m] = ph.re[m];
+            a.ph_im[m] = ph.im[m];
+        }
+        a.coef = c.coef;
+        a.alpha = c.alpha;
+        a.active = c.active;
+        a.partial = c.partial;
+        a.pstride = c.pstride;
+        err = launch_hop<S>(g->nr, c.dagger, c.epi, a, st);
+    });
+    if (err != hipSuccess) return fail(HRW_EDEVICE, "hop launch failed: %s", hipGetErrorString(err));
+    if (tm) timed_end(st, ev, KC_HOP, hop_bytes(g->g, g->nr, c.dt, c.parity, c.epi, c.n_rhs));
+    return HRW_OK;
+}
+
+struct DoubleArg {
+    double v[MAX_RHS];
+};
+__global__ void set_doubles_kernel(double *dst, DoubleArg a, int n)
+{
+    if ((int)threadIdx.x < n) dst[threadIdx.x] = a.v[threadIdx.x];
+}
+
+int set_device_doubles(double *dst, const double *vals, int n, hipStream_t st)
+{
+    if (n > MAX_RHS) return fail(HRW_EINVAL, "too many values");
+    DoubleArg a;
+    memset(&a, 0, sizeof a);
+    for (int k = 0; k < n; ++k) a.v[k] = vals[k];
+    set_doubles_kernel<<<1, 64, 0, st>>>(dst, a, n);
+    HRW_HIP(hipGetLastError());
+    return HRW_OK;
+}
+
+// pool of pinned, device-mapped host slots for convergence flags
+static std::mutex g_flags_mu;
+static int *g_flags_host = nullptr;
+static int *g_flags_dev = nullptr;
+static std::vector<int> g_flags_free;
+constexpr int FLAG_SLOTS = 64;
+
+int host_flags_acquire(HostFlags *f)
+{
+    std::lock_guard<std::mutex> lk(g_flags_mu);
+    if (!g_flags_host) {
+        void *p = nullptr;
+        HRW_HIP(hipHostMalloc(&p, sizeof(int) * FLAG_SLOTS * MAX_RHS, hipHostMallocMapped));
+        void *d = nullptr;
+        HRW_HIP(hipHostGetDevicePointer(&d, p, 0));
+        g_flags_host = (int *)p;
+        g_flags_dev = (int *)d;
+        for (int s = FLAG_SLOTS - 1; s >= 0; --s) g_flags_free.push_back(s);
+    }
+    if (g_flags_free.empty()) return fail(HRW_ENOMEM, "too many concurrent solves");
+    f->slot = g_flags_free.back();
+    g_flags_free.pop_back();
+    f->host = g_flags_host + f->slot * MAX_RHS;
+    f->dev = g_flags_dev + f->slot * MAX_RHS;
+    return HRW_OK;
+}
+
+void host_flags_release(HostFlags *f)
+{
+    if (f->slot < 0) return;
+    std::lock_guard<std::mutex> lk(g_flags_mu);
+    g_flags_free.push_back(f->slot);
+    f->slot = -1;
+}
+
+// ------------------------------------------------------------------ sizes
+
+int gauge_storage_bytes(const Geom &g, int nr, unsigned mask, size_t *bytes)
+{
+    Arena ar(nullptr, 0);
+    for (int d = 0; d < 4; ++d)
+        if (mask & (1u << d))
+            for (int q = 0; q < 2; ++q) ar.take(gauge_block_elems(g, nr) * dtype_cbytes(d));
+    *bytes = ar.off + 256;
+    return HRW_OK;
+}
+
+// per-rhs stride of packed fields with `halves` halves each
+static size_t half_elems(const Geom &g, int nr) { return spinor_elems(g, nr); }
+
+static int partial_stride(const Geom &g, int nr)
+{
+    const int a = 2 * hop_grid(g, HOP_MAX_G);
+    const int b = vec_grid(2 * half_elems(g, nr));
+    return a > b ? a : b;
+}
+
+struct ApplyPlan {
+    void *f[4];   // four full-size (two-half) fields, n_rhs each
+    double *coef;
+    double *partial;
+};
+
+static void plan_apply(Arena &ar, const Geom &g, int nr, int n_rhs, ApplyPlan &pl)
+{
+    const size_t H = half_elems(g, nr);
+    for (int k = 0; k < 4; ++k) pl.f[k] = ar.take(2 * H * n_rhs * 16);
+    pl.coef = (double *)ar.take(sizeof(double) * MAX_RHS);
+    pl.partial = (double *)ar.take(sizeof(double) * (size_t)partial_stride(g, nr) * n_rhs);
+}
+
+int apply_workspace(const Geom &g, int nr, int n_rhs, size_t *bytes)
+{
+    Arena ar(nullptr, 0);
+    ApplyPlan pl;
+    plan_apply(ar, g, nr, n_rhs, pl);
+    *bytes = ar.off + 256;
+    return HRW_OK;
+}
+
+// ------------------------------------------------------------------ operator applies
+
+static int check_ws(const Arena &ar, size_t ws_bytes)
+{
+    if (!ar.fits()) return fail(HRW_ENOMEM, "workspace too small: need %zu bytes, got %zu", ar.off, ws_bytes);
+    return HRW_OK;
+}
+
+int dw_apply(const hrw_gauge *g, double kappa, const double theta[4], int dt, int n_rhs, int dagger,
+             const double *in, double *out, void *ws, size_t ws_bytes, hipStream_t st)
+{
+    Arena ar(ws, ws_bytes);
+    ApplyPlan pl;
+    plan_apply(ar, g->g, g->nr, n_rhs, pl);
+    int rc = check_ws(ar, ws_bytes);
+    if (rc) return rc;
+    const size_t H = half_elems(g->g, g->nr);
+    const size_t cb = dtype_cbytes(dt);
+    char *fi = (char *)pl.f[0], *fo = (char *)pl.f[1];
+    HRW_HIP(launch_pack_spinor(dt, g->nr, g->g, true, 0, n_rhs, in, fi, fi + H * cb, 2 * H, st));
+    double k[MAX_RHS];
+    for (int j = 0; j < n_rhs; ++j) k[j] = kappa;
+    rc = set_device_doubles(pl.coef, k, n_rhs, st);
+    if (rc) return rc;
+    HopCall c;
+    c.dt = dt;
+    c.parity = -1;
+    c.dagger = dagger != 0;
+    c.epi = EPI_AXPY;
+    c.n_rhs = n_rhs;
+    c.rstride = 2 * H;
+    for (int q = 0; q < 2; ++q) {
+        c.in[q] = fi + q * H * cb;
+        c.self[q] = fi + q * H * cb;
+        c.out[q] = fo + q * H * cb;
+    }
+    c.coef = pl.coef;
+    rc = run_hop(g, make_phases(theta), c, st);
+    if (rc) return rc;
+    HRW_HIP(launch_unpack_spinor(dt, g->nr, g->g, true, 0, n_rhs, fo, fo + H * cb, 2 * H, out, st));
+    return HRW_OK;
+}
+
+int hop_eo_apply(const hrw_gauge *g, int out_parity, const double theta[4], int dt, int n_rhs,
+                 int dagger, const double *in, double *out, void *ws, size_t ws_bytes, hipStream_t st)
+{
+    Arena ar(ws, ws_bytes);
+    ApplyPlan pl;
+    plan_apply(ar, g->g, g->nr, n_rhs, pl);
+    int rc = check_ws(ar, ws_bytes);
+    if (rc) return rc;
+    const size_t H = half_elems(g->g, g->nr);
+    const int ip = 1 - out_parity;
+    HRW_HIP(launch_pack_spinor(dt, g->nr, g->g, false, ip, n_rhs, in, ip == 0 ? pl.f[0] : nullptr,
+                               ip == 1 ? pl.f[0] : nullptr, H, st));
+    HopCall c;
+    c.dt = dt;
+    c.parity = out_parity;
+    c.dagger = dagger != 0;
+    c.epi = EPI_PLAIN;
+    c.n_rhs = n_rhs;
+    c.rstride = H;
+    c.in[ip] = pl.f[0];
+    c.out[out_parity] = pl.f[1];
+    rc = run_hop(g, make_phases(theta), c, st);
+    if (rc) return rc;
+    HRW_HIP(launch_unpack_spinor(dt, g->nr, g->g, false, out_parity, n_rhs,
+                                 out_parity == 0 ? pl.f[1] : nullptr, out_parity == 1 ? pl.f[1] : nullptr,
+                                 H, out, st));
+    return HRW_OK;
+}
+
+int deo_apply(const hrw_gauge *g, const double *kappa, const double theta[4], int dt, int n_rhs,
+              int dagger, const double *in, double *out, void *ws, size_t ws_bytes, hipStream_t st)
+{
+    Arena ar(ws, ws_bytes);
+    ApplyPlan pl;
+    plan_apply(ar, g->g, g->nr, n_rhs, pl);
+    int rc = check_ws(ar, ws_bytes);
+    if (rc) return rc;
+    const size_t H = half_elems(g->g, g->nr);
+    HRW_HIP(launch_pack_spinor(dt, g->nr, g->g, false, 0, n_rhs, in, pl.f[0], nullptr, H, st));
+    double k2[MAX_RHS];
+    for (int j = 0; j < n_rhs; ++j) k2[j] = kappa[j] * kappa[j];
+    rc = set_device_doubles(pl.coef, k2, n_rhs, st);
+    if (rc) return rc;
+    const Phases ph = make_phases(theta);
+    HopCall c;
+    c.dt = dt;
+    c.dagger = dagger != 0;
+    c.n_rhs = n_rhs;
+    c.rstride = H;
+    c.parity = 1;
+    c.epi = EPI_PLAIN;
+    c.in[0] = pl.f[0];
+    c.out[1] = pl.f[1];
+    rc = run_hop(g, ph, c, st);
+    if (rc) return rc;
+    HopCall d;
+    d.dt = dt;
+    d.dagger = dagger != 0;
+    d.n_rhs = n_rhs;
+    d.rstride = H;
+    d.parity = 0;
+    d.epi = EPI_AXPY;
+    d.in[1] = pl.f[1];
+    d.self[0] = pl.f[0];
+    d.out[0] = pl.f[2];
+    d.coef = pl.coef;
+    rc = run_hop(g, ph, d, st);
+    if (rc) return rc;
+    HRW_HIP(launch_unpack_spinor(dt, g->nr, g->g, false, 0, n_rhs, pl.f[2], nullptr, H, out, st));
+    return HRW_OK;
+}
+
+// ------------------------------------------------------------------ CG
+
+// A packed field: n_rhs slots of `two ? 2 : 1` halves, rhs stride RS elements.
+struct Fld {
+    char *base = nullptr;
+    int dt = 0;
+    size_t H = 0;
+    bool two = false;
+    void *h(int q) const { return base + (two ? (size_t)q * H * dtype_cbytes(dt) : 0); }
+};
+
+struct CgPlan {
+    int sys;          // hrw_system
+    bool mixed;
+    int dl;           // inner dtype
+    size_t H, RS;     // half elems, rhs stride
+    // inner-precision fields
+    Fld x, r, p, s, t, u;
+    // FP64 fields (b always; x, r and temps for the FP64 operator in mixed mode)
+    Fld b, x64, r64, s64, t64, u64, q64;
+    // CGNR extras (FP64, two halves): full source, scratch
+    Fld bfull, dfull;
+    CgState *cs;
+    double *alpha, *beta, *coef_k, *coef_k2, *coef_mk, *scal;
+    int *active;
+    double *pa, *pb;
+    int pstride;
+};
+
+static Fld take_fld(Arena &ar, int dt, size_t H, bool two, size_t RS, int n_rhs)
+{
+    Fld f;
+    f.dt = dt;
+    f.H = H;
+    f.two = two;
+    f.base = (char *)ar.take(RS * n_rhs * dtype_cbytes(dt));
+    return f;
+}
+
+static int plan_cg(Arena &ar, const Geom &g, int nr, int n_rhs, const hrw_solve_params *prm, CgPlan &pl)
+{
+    pl.sys = prm->system;
+    pl.dl = prm->inner_dtype;
+    pl.mixed = pl.dl != 0;
+    pl.H = half_elems(g, nr);
+    const bool full = pl.sys == HRW_SYS_DDAG_D_FULL;
+    const bool cgnr = pl.sys == HRW_SYS_D_CGNR_EO;
+    const bool two = full || cgnr;  // fields carry both parities
+    pl.RS = two ? 2 * pl.H : pl.H;
+    const size_t H = pl.H, RS = pl.RS;
+    // e/o systems keep odd temporaries in their own half-size fields
+    auto mk = [&](int dt, bool tw) { return take_fld(ar, dt, H, tw, RS, n_rhs); };
+    pl.b = mk(0, two);
+    const int di = pl.dl;
+    pl.x = mk(di, two);
+    pl.r = mk(di, two);
+    pl.p = mk(di, two);
+    pl.s = mk(di, two);
+    if (!full) {
+        // odd temporaries: use odd halves of two-half fields in CGNR, own fields otherwise
+        pl.t = mk(di, two);
+        pl.u = mk(di, two);
+    }
+    if (pl.mixed) {
+        pl.x64 = mk(0, two);
+        pl.r64 = mk(0, two);
+        pl.s64 = mk(0, two);
+        pl.q64 = mk(0, two);
+        if (!full) {
+            pl.t64 = mk(0, two);
+            pl.u64 = mk(0, two);
+        }
+    }
+    if (cgnr) {
+        pl.bfull = mk(0, true);
+        pl.dfull = mk(0, true);
+        if (!pl.mixed) pl.q64 = mk(0, true);
+    }
+    pl.cs = (CgState *)ar.take(sizeof(CgState) * MAX_RHS);
+    pl.alpha = (double *)ar.take(sizeof(double) * MAX_RHS);
+    pl.beta = (double *)ar.take(sizeof(double) * MAX_RHS);
+    pl.coef_k = (double *)ar.take(sizeof(double) * MAX_RHS);
+    pl.coef_k2 = (double *)ar.take(sizeof(double) * MAX_RHS);
+    pl.coef_mk = (double *)ar.take(sizeof(double) * MAX_RHS);
+    pl.scal = (double *)ar.take(sizeof(double) * 4 * MAX_RHS);
+    pl.active = (int *)ar.take(sizeof(int) * MAX_RHS);
+    pl.pstride = partial_stride(g, nr);
+    pl.pa = (double *)ar.take(sizeof(double) * (size_t)pl.pstride * n_rhs);
+    pl.pb = (double *)ar.take(sizeof(double) * (size_t)pl.pstride * n_rhs);
+    return HRW_OK;
+}
+
+int cg_workspace(const Geom &g, int nr, int n_rhs, const hrw_solve_params *p, size_t *bytes)
+{
+    Arena ar(nullptr, 0);
+    CgPlan pl;
+    plan_cg(ar, g, nr, n_rhs, p, pl);
+    *bytes = ar.off + 256;
+    return HRW_OK;
+}
+
+struct CgRun {
+    const hrw_gauge *g;
+    CgPlan *pl;
+    Phases ph;
+    int n_rhs;
+    hipStream_t st;
+    bool full() const { return pl->sys == HRW_SYS_DDAG_D_FULL; }
+    int nparts_hop() const { return (full() ? 2 : 1) * hop_grid_for(g->g, g->nr, pl->dl); }
+    size_t elems() const { return full() ? 2 * pl->H : pl->H; }  // active elements per rhs
+};
+
+// q = A x with A = D^+ D (full) or D_hat^+ D_hat (e/o); fields share dtype.
+static int apply_A(CgRun &R, const Fld &x, const Fld &s, const Fld &t, const Fld &u, const Fld &q)
+{
+    CgPlan &P = *R.pl;
+    HopCall c;
+    c.dt = x.dt;
+    c.n_rhs = R.n_rhs;
+    c.rstride = P.RS;
+    int rc;
+    if (R.full()) {
+        c.parity = -1;
+        c.epi = EPI_AXPY;
+        c.coef = P.coef_k;
+        for (int k = 0; k < 2; ++k) {
+            c.in[k] = x.h(k);
+            c.self[k] = x.h(k);
+            c.out[k] = s.h(k);
+        }
+        if ((rc = run_hop(R.g, R.ph, c, R.st))) return rc;
+        c.dagger = true;
+        for (int k = 0; k < 2; ++k) {
+            c.in[k] = s.h(k);
+            c.self[k] = s.h(k);
+            c.out[k] = q.h(k);
+        }
+        return run_hop(R.g, R.ph, c, R.st);
+    }
+    HopCall a = c;
+    a.parity = 1;
+    a.epi = EPI_PLAIN;
+    a.in[0] = x.h(0);
+    a.out[1] = t.h(1);
+    if ((rc = run_hop(R.g, R.ph, a, R.st))) return rc;
+    HopCall b = c;
+    b.parity = 0;
+    b.epi = EPI_AXPY;
+    b.coef = P.coef_k2;
+    b.in[1] = t.h(1);
+    b.self[0] = x.h(0);
+    b.out[0] = s.h(0);
+    if ((rc = run_hop(R.g, R.ph, b, R.st))) return rc;
+    a.dagger = true;
+    a.in[0] = s.h(0);
+    a.out[1] = u.h(1);
+    if ((rc = run_hop(R.g, R.ph, a, R.st))) return rc;
+    b.dagger = true;
+    b.in[1] = u.h(1);
+    b.self[0] = s.h(0);
+    b.out[0] = q.h(0);
+    return run_hop(R.g, R.ph, b, R.st);
+}
+
+// one CG iteration on the inner fields
+static int cg_iteration(CgRun &R, int max_iter, int *host_active)
+{
+    CgPlan &P = *R.pl;
+    const int dt = P.dl;
+    HopCall c;
+    c.dt = dt;
+    c.n_rhs = R.n_rhs;
+    c.rstride = P.RS;
+    int rc;
+    if (R.full()) {
+        HopCall a = c;
+        a.parity = -1;
+        a.epi = EPI_AXPY;
+        a.coef = P.coef_k;
+        a.partial = P.pa;
+        a.pstride = P.pstride;
+        for (int k = 0; k < 2; ++k) {
+            a.in[k] = P.p.h(k);
+            a.self[k] = P.p.h(k);
+            a.out[k] = P.s.h(k);
+        }
+        if ((rc = run_hop(R.g, R.ph, a, R.st))) return rc;
+    } else {
+        HopCall a = c;
+        a.parity = 1;
+        a.epi = EPI_PLAIN;
+        a.in[0] = P.p.h(0);
+        a.out[1] = P.t.h(1);
+        if ((rc = run_hop(R.g, R.ph, a, R.st))) return rc;
+        HopCall b = c;
+        b.parity = 0;
+        b.epi = EPI_AXPY;
+        b.coef = P.coef_k2;
+        b.in[1] = P.t.h(1);
+        b.self[0] = P.p.h(0);
+        b.out[0] = P.s.h(0);
+        b.partial = P.pa;
+        b.pstride = P.pstride;
+        if ((rc = run_hop(R.g, R.ph, b, R.st))) return rc;
+    }
+    HRW_HIP(launch_cg_alpha(P.cs, P.pa, P.pstride, R.nparts_hop(), R.n_rhs, P.alpha, R.st));
+    if (R.full()) {
+        HopCall a = c;
+        a.parity = -1;
+        a.dagger = true;
+        a.epi = EPI_CG;
+        a.coef = P.coef_k;
+        for (int k = 0; k < 2; ++k) {
+            a.in[k] = P.s.h(k);
+            a.self[k] = P.s.h(k);
+            a.r[k] = P.r.h(k);
+            a.x[k] = P.x.h(k);
+            a.p[k] = P.p.h(k);
+        }
+        a.alpha = P.alpha;
+        a.active = P.active;
+        a.partial = P.pb;
+        a.pstride = P.pstride;
+        if ((rc = run_hop(R.g, R.ph, a, R.st))) return rc;
+    } else {
+        HopCall a = c;
+        a.parity = 1;
+        a.dagger = true;
+        a.epi = EPI_PLAIN;
+        a.in[0] = P.s.h(0);
+        a.out[1] = P.u.h(1);
+        if ((rc = run_hop(R.g, R.ph, a, R.st))) return rc;
+        HopCall b = c;
+        b.parity = 0;
+        b.dagger = true;
+        b.epi = EPI_CG;
+        b.coef = P.coef_k2;
+        b.in[1] = P.u.h(1);
+        b.self[0] = P.s.h(0);
+        b.r[0] = P.r.h(0);
+        b.x[0] = P.x.h(0);
+        b.p[0] = P.p.h(0);
+        b.alpha = P.alpha;
+        b.active = P.active;
+        b.partial = P.pb;
+        b.pstride = P.pstride;
+        if ((rc = run_hop(R.g, R.ph, b, R.st))) return rc;
+    }
+    HRW_HIP(launch_cg_beta(P.cs, P.pb, P.pstride, R.nparts_hop(), R.n_rhs, max_iter, P.beta, P.active,
+                           host_active, R.st));
+    int err = HRW_OK;
+    dispatch_dtype(dt, [&](auto sv) {
+        typedef decltype(sv) S;
+        if (launch_xpay<S>((const cpx<S> *)P.r.h(0), (cpx<S> *)P.p.h(0), P.beta, P.active, R.elems(), P.RS,
+                           R.n_rhs, R.st) != hipSuccess)
+            err = fail(HRW_EDEVICE, "xpay launch failed");
+    });
+    return err;
+}
+
+// r64 = b - A x64 in FP64 with |r64|^2 partials in pb (plain mode uses the inner fields)
+static int true_residual(CgRun &R, const Fld &x, const Fld &r, const Fld &s, const Fld &t, const Fld &u,
+                         const Fld &q)
+{
+    CgPlan &P = *R.pl;
+    int rc = apply_A(R, x, s, t, u, q);
+    if (rc) return rc;
+    const int nb = vec_grid(R.elems());
+    HRW_HIP(launch_residual<double>((const cpx<double> *)P.b.h(0), (const cpx<double> *)q.h(0),
+                                    (cpx<double> *)r.h(0), R.elems(), P.RS, R.n_rhs, P.pb, P.pstride, nb,
+                                    R.st));
+    return HRW_OK;
+}
+
+// CgState flags -> host after a true-residual check
+__global__ void flags_to_host_kernel(const int *active, int *host, int n)
+{
+    if ((int)threadIdx.x < n) host[threadIdx.x] = active[threadIdx.x];
+}
+
+// reliable-update decision: like the true-residual check, but a running rhs
+// keeps its search direction and only its residual norm is replaced
+__global__ void __launch_bounds__(WG) cg_reliable_kernel(CgState *cs, const double *partial, int pstride,
+                                                          int nparts, int *active_out, int max_restarts)
+{
+    __shared__ double sh[WG / 64];
+    const int rhs = blockIdx.x;
+    double s = 0;
+    for (int k = threadIdx.x; k < nparts; k += blockDim.x) s += partial[(size_t)rhs * pstride + k];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double rt = 0;
+        for (int k = 0; k < WG / 64; ++k) rt += sh[k];
+        CgState c = cs[rhs];
+        c.rr_true = rt;
+        if (c.status == CG_RUNNING || c.status == CG_RECURSIVE_DONE) {
+            c.updates += 1;
+            if (rt <= c.tol2) {
+                c.status = CG_DONE;
+                c.active = 0;
+            } else if (!(rt == rt) || isinf(rt)) {
+                c.status = CG_BREAKDOWN;
+                c.active = 0;
+            } else {
+                if (c.status == CG_RECURSIVE_DONE) c.restarts += 1;
+                if (c.restarts > max_restarts) {
+                    c.status = CG_MAXITER;
+                    c.active = 0;
+                } else {
+                    c.status = CG_RUNNING;
+                    c.active = 1;
+                    c.rr = rt;
+                }
+            }
+        }
+        cs[rhs] = c;
+        active_out[rhs] = c.active;
+    }
+}
+
+static int any_active(const int *host, int n)
+{
+    int a = 0;
+    for (int j = 0; j < n; ++j) a |= host[j];
+    return a;
+}
+
+int cg_solve(const hrw_gauge *g, const hrw_solve_params *prm, int n_rhs, const double *kappa,
+             const double *b_in, double *x_out, hrw_solve_result *res, void *ws, size_t ws_bytes,
+             hipStream_t st)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    Arena ar(ws, ws_bytes);
+    CgPlan P;
+    plan_cg(ar, g->g, g->nr, n_rhs, prm, P);
+    int rc = check_ws(ar, ws_bytes);
+    if (rc) return rc;
+    if (!g->blocks[P.dl][0] || !g->blocks[0][0])
+        return fail(HRW_EUNSUPPORTED, "gauge field lacks FP64 links or links in the inner dtype");
+    // all workspace fields start at zero: padding lanes stay finite and x starts at 0
+    HRW_HIP(launch_zero(ar.base, ar.off, st));
+    CgRun R{g, &P, make_phases(prm->theta), n_rhs, st};
+    const size_t H = P.H;
+    const int nr = g->nr;
+    double kv[MAX_RHS], k2[MAX_RHS], mk[MAX_RHS];
+    for (int j = 0; j < n_rhs; ++j) {
+        kv[j] = kappa[j];
+        k2[j] = kappa[j] * kappa[j];
+        mk[j] = -kappa[j];
+    }
+    if ((rc = set_device_doubles(P.coef_k, kv, n_rhs, st))) return rc;
+    if ((rc = set_device_doubles(P.coef_k2, k2, n_rhs, st))) return rc;
+    if ((rc = set_device_doubles(P.coef_mk, mk, n_rhs, st))) return rc;
+
+    // ---- source
+    if (P.sys == HRW_SYS_DDAG_D_EO) {
+        HRW_HIP(launch_pack_spinor(0, nr, g->g, false, 0, n_rhs, b_in, P.b.h(0), nullptr, P.RS, st));
+    } else if (P.sys == HRW_SYS_DDAG_D_FULL) {
+        HRW_HIP(launch_pack_spinor(0, nr, g->g, true, 0, n_rhs, b_in, P.b.h(0), P.b.h(1), P.RS, st));
+    } else {
+        // b'_e = b_e + kappa H_eo b_o, then eta = D_hat^+ b'_e
+        HRW_HIP(launch_pack_spinor(0, nr, g->g, true, 0, n_rhs, b_in, P.bfull.h(0), P.bfull.h(1), P.RS, st));
+        HopCall c;
+        c.dt = 0;
+        c.n_rhs = n_rhs;
+        c.rstride = P.RS;
+        c.parity = 0;
+        c.epi = EPI_AXPY;
+        c.coef = P.coef_mk;
+        c.in[1] = P.bfull.h(1);
+        c.self[0] = P.bfull.h(0);
+        c.out[0] = P.dfull.h(0);
+        if ((rc = run_hop(g, R.ph, c, st))) return rc;
+        HopCall a;
+        a.dt = 0;
+        a.n_rhs = n_rhs;
+        a.rstride = P.RS;
+        a.parity = 1;
+        a.dagger = true;
+        a.epi = EPI_PLAIN;
+        a.in[0] = P.dfull.h(0);
+        a.out[1] = P.dfull.h(1);
+        if ((rc = run_hop(g, R.ph, a, st))) return rc;
+        HopCall d = a;
+        d.parity = 0;
+        d.epi = EPI_AXPY;
+        d.coef = P.coef_k2;
+        d.in[1] = P.dfull.h(1);
+        d.self[0] = P.dfull.h(0);
+        d.out[0] = P.b.h(0);
+        if ((rc = run_hop(g, R.ph, d, st))) return rc;
+    }
+    const size_t E = R.elems();
+    const int nbv = vec_grid(E);
+
+    // ---- initial state: r = p = b (x = 0), |b|^2
+    HRW_HIP(launch_norm2<double>((const cpx<double> *)P.b.h(0), E, P.RS, n_rhs, P.pa, P.pstride, nbv, st));
+    HRW_HIP(launch_cg_init(P.cs, P.pa, P.pstride, nbv, n_rhs, prm->tol, P.active, st));
+    const size_t felems = P.RS * n_rhs;  // complex elements of one field, all rhs
+    if (P.mixed) {
+        HRW_HIP(launch_convert(0, P.b.base, P.dl, P.r.base, felems, st));
+        HRW_HIP(launch_convert(0, P.b.base, P.dl, P.p.base, felems, st));
+    } else {
+        HRW_HIP(launch_copy<double>((const cpx<double> *)P.b.base, (cpx<double> *)P.r.base, felems, st));
+        HRW_HIP(launch_copy<double>((const cpx<double> *)P.b.base, (cpx<double> *)P.p.base, felems, st));
+    }
+
+    HostFlags hf;
+    if ((rc = host_flags_acquire(&hf))) return rc;
+    struct Guard {
+        HostFlags *f;
+        hipEvent_t ev[3];
+        ~Guard()
+        {
+            for (auto &e : ev)
+                if (e) (void)hipEventDestroy(e);
+            host_flags_release(f);
+        }
+    } guard{&hf, {nullptr, nullptr, nullptr}};
+    for (auto &e : guard.ev) HRW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (int j = 0; j < n_rhs; ++j) hf.host[j] = 1;
+
+    const int max_iter = prm->max_iter > 0 ? prm->max_iter : 1;
+    const int K = prm->reliable_every > 0 ? prm->reliable_every : 50;
+    const int max_restarts = 20;
+    int it_since = 0;
+    long long enq = 0;
+    for (;;) {
+        // ---- iterate until nothing is active (or, mixed, K iterations passed)
+        bool stop = false;
+        while (!stop) {
+            if ((rc = cg_iteration(R, max_iter, hf.dev))) return rc;
+            HRW_HIP(hipEventRecord(guard.ev[enq % 3], st));
+            ++enq;
+            ++it_since;
+            if (enq >= 2) {
+                HRW_HIP(hipEventSynchronize(guard.ev[(enq - 2) % 3]));
+                if (!any_active(hf.host, n_rhs)) stop = true;
+            }
+            if (P.mixed && it_since >= K) stop = true;
+        }
+        HRW_HIP(hipStreamSynchronize(st));
+        // ---- check in FP64
+        if (P.mixed) {
+            // x64 += x_lo; x_lo = 0; r64 = b - A64 x64; reseed r_lo; keep p
+            double one[MAX_RHS];
+            for (int j = 0; j < n_rhs; ++j) one[j] = 1.0;
+            if ((rc = set_device_doubles(P.scal, one, n_rhs, st))) return rc;
+            HRW_HIP(launch_axpy_mixed(P.dl, P.x.base, 0, P.x64.base, P.scal, felems, 0, 0, 1, st));
+            HRW_HIP(launch_zero(P.x.base, felems * dtype_cbytes(P.dl), st));
+            if ((rc = true_residual(R, P.x64, P.r64, P.s64, P.t64, P.u64, P.q64))) return rc;
+            cg_reliable_kernel<<<n_rhs, WG, 0, st>>>(P.cs, P.pb, P.pstride, nbv, P.active, max_restarts);
+            HRW_HIP(hipGetLastError());
+            HRW_HIP(launch_convert(0, P.r64.base, P.dl, P.r.base, felems, st));
+        } else {
+            // the search direction is dead here: reuse p as the output of A x
+            if ((rc = true_residual(R, P.x, P.r, P.s, P.t, P.u, P.p))) return rc;
+            cg_reliable_kernel<<<n_rhs, WG, 0, st>>>(P.cs, P.pb, P.pstride, nbv, P.active, max_restarts);
+            HRW_HIP(hipGetLastError());
+            // restarted rhs: p = r (beta = 0)
+            double zero[MAX_RHS] = {0};
+            if ((rc = set_device_doubles(P.beta, zero, n_rhs, st))) return rc;
+            HRW_HIP(launch_xpay<double>((const cpx<double> *)P.r.h(0), (cpx<double> *)P.p.h(0), P.beta,
+                                        P.active, E, P.RS, n_rhs, st));
+        }
+        flags_to_host_kernel<<<1, 64, 0, st>>>(P.active, hf.dev, n_rhs);
+        HRW_HIP(hipGetLastError());
+        HRW_HIP(hipStreamSynchronize(st));
+        it_since = 0;
+        if (!any_active(hf.host, n_rhs)) break;
+    }
+
+    // ---- solution out
+    const Fld &X = P.mixed ? P.x64 : P.x;
+    if (P.sys == HRW_SYS_DDAG_D_EO) {
+        HRW_HIP(launch_unpack_spinor(0, nr, g->g, false, 0, n_rhs, X.h(0), nullptr, P.RS, x_out, st));
+    } else if (P.sys == HRW_SYS_DDAG_D_FULL) {
+        HRW_HIP(launch_unpack_spinor(0, nr, g->g, true, 0, n_rhs, X.h(0), X.h(1), P.RS, x_out, st));
+    } else {
+        // x_o = b_o + kappa H_oe x_e; then |b - D x| over the full lattice
+        HopCall c;
+        c.dt = 0;
+        c.n_rhs = n_rhs;
+        c.rstride = P.RS;
+        c.parity = 1;
+        c.epi = EPI_AXPY;
+        c.coef = P.coef_mk;
+        c.in[0] = X.h(0);
+        c.self[1] = P.bfull.h(1);
+        c.out[1] = X.h(1);
+        if ((rc = run_hop(g, R.ph, c, st))) return rc;
+        HRW_HIP(launch_unpack_spinor(0, nr, g->g, true, 0, n_rhs, X.h(0), X.h(1), P.RS, x_out, st));
+        HopCall d;
+        d.dt = 0;
+        d.n_rhs = n_rhs;
+        d.rstride = P.RS;
+        d.parity = -1;
+        d.epi = EPI_AXPY;
+        d.coef = P.coef_k;
+        for (int k = 0; k < 2; ++k) {
+            d.in[k] = X.h(k);
+            d.self[k] = X.h(k);
+            d.out[k] = P.dfull.h(k);
+        }
+        if ((rc = run_hop(g, R.ph, d, st))) return rc;
+        const int nb2 = vec_grid(2 * H);
+        HRW_HIP(launch_residual<double>((const cpx<double> *)P.bfull.h(0), (const cpx<double> *)P.dfull.h(0),
+                                        (cpx<double> *)P.q64.h(0), 2 * H, P.RS, n_rhs, P.pa, P.pstride, nb2, st));
+        HRW_HIP(launch_sum_partials(P.pa, P.pstride, nb2, n_rhs, P.scal, st));
+        HRW_HIP(launch_norm2<double>((const cpx<double> *)P.bfull.h(0), 2 * H, P.RS, n_rhs, P.pb, P.pstride, nb2, st));
+        HRW_HIP(launch_sum_partials(P.pb, P.pstride, nb2, n_rhs, P.scal + MAX_RHS, st));
+    }
+    std::vector<CgState> hs(n_rhs);
+    HRW_HIP(hipMemcpyAsync(hs.data(), P.cs, sizeof(CgState) * n_rhs, hipMemcpyDeviceToHost, st));
+    double dres[2 * MAX_RHS] = {0};
+    if (P.sys == HRW_SYS_D_CGNR_EO)
+        HRW_HIP(hipMemcpyAsync(dres, P.scal, sizeof(double) * 2 * MAX_RHS, hipMemcpyDeviceToHost, st));
+    HRW_HIP(hipStreamSynchronize(st));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int overall = HRW_OK;
+    for (int j = 0; j < n_rhs; ++j) {
+        const CgState &c = hs[j];
+        hrw_solve_result &o = res[j];
+        o.iters = c.iters;
+        o.reliable_updates = P.mixed ? c.updates : 0;
+        o.restarts = c.restarts;
+        o.true_rel_resid = c.rr0 > 0 ? sqrt(c.rr_true / c.rr0) : 0.0;
+        o.recursive_rel_resid = c.rr0 > 0 ? sqrt(c.rr / c.rr0) : 0.0;
+        o.d_rel_resid = (P.sys == HRW_SYS_D_CGNR_EO && dres[MAX_RHS + j] > 0)
+                            ? sqrt(dres[j] / dres[MAX_RHS + j]) : 0.0;
+        o.seconds = secs;
+        if (c.status == CG_DONE) {
+            o.status = HRW_OK;
+        } else if (c.status == CG_BREAKDOWN) {
+            o.status = HRW_EBREAKDOWN;
+        } else {
+            o.status = HRW_NOT_CONVERGED;
+        }
+        if (o.status == HRW_EBREAKDOWN) overall = HRW_EBREAKDOWN;
+        else if (o.status == HRW_NOT_CONVERGED && overall == HRW_OK) overall = HRW_NOT_CONVERGED;
+    }
+    if (timing().on) timing_harvest();
+    return overall;
+}
+
+}  // namespace hrw

@@ -1,0 +1,10 @@
+// Hopping-kernel instances with bf16_t storage.
+#include "hop_impl.h"
+
+namespace hrw {
+template <>
+hipError_t launch_hop<bf16_t>(int nr, bool dagger, int epi, const HopArgs<bf16_t> &a, hipStream_t st)
+{
+    return launch_hop_impl<bf16_t>(nr, dagger, epi, a, st);
+}
+}  // namespace hrw

@@ -1,0 +1,10 @@
+// Hopping-kernel instances with f16_t storage.
+#include "hop_impl.h"
+
+namespace hrw {
+template <>
+hipError_t launch_hop<f16_t>(int nr, bool dagger, int epi, const HopArgs<f16_t> &a, hipStream_t st)
+{
+    return launch_hop_impl<f16_t>(nr, dagger, epi, a, st);
+}
+}  // namespace hrw

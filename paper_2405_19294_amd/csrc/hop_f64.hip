@@ -1,0 +1,10 @@
+// Hopping-kernel instances with double storage.
+#include "hop_impl.h"
+
+namespace hrw {
+template <>
+hipError_t launch_hop<double>(int nr, bool dagger, int epi, const HopArgs<double> &a, hipStream_t st)
+{
+    return launch_hop_impl<double>(nr, dagger, epi, a, st);
+}
+}  // namespace hrw

@@ -1,0 +1,305 @@
+// Wilson hopping kernel for the even/odd blocks of H (arXiv 2405.19294,
+// Sec. 3.1), one thread per output site.
+//
+// Per output site x and direction mu the thread
+//   1. loads the neighbour spinor psi(x +- mu) (4 N_R complex, coalesced
+//      across the wavefront by the site-blocked layout),
+//   2. projects it to a half-spinor h = (1 -+ g_mu) psi, which has only two
+//      independent spin components in the chiral basis (the same half-spinor
+//      trick the paper uses to halve its messages, Sec. 2.2),
+//   3. applies the boundary phase when the hop wraps,
+//   4. multiplies both components by the N_R x N_R link (forward: U_mu(x),
+//      backward: the stored U_mu(x - mu)^+), streaming the link from HBM,
+//   5. reconstructs the lower two spin components and accumulates.
+// The epilogue is fused: out = H in, out = self - c H in (with |out|^2
+// partials), or the CG update r -= alpha (self - c H in), x += alpha p with
+// |r|^2 partials.  Partials are reduced per workgroup in a fixed order, so
+// the result is bitwise reproducible.
+//
+// Spin projection in the chiral basis, with s = -1 for (1 - g_mu) and s = +1
+// for (1 + g_mu); psi = (p0, p1 | p2, p3) by spin, g = U h:
+//   mu = 0: h0 = p0 - s p2,    h1 = p1 - s p3;    out2 += -s g0,  out3 += -s g1
+//   mu = 1: h0 = p0 - s i p3,  h1 = p1 - s i p2;  out2 += s i g1, out3 += s i g0
+//   mu = 2: h0 = p0 - s p3,    h1 = p1 + s p2;    out2 += s g1,   out3 += -s g0
+//   mu = 3: h0 = p0 - s i p2,  h1 = p1 + s i p3;  out2 += s i g0, out3 += -s i g1
+// (out0 += g0, out1 += g1 always).  The forward hop of H uses s = -1 and the
+// backward hop s = +1; H^+ swaps them.
+#pragma once
+
+#include "kernels.h"
+
+namespace hrw {
+
+__device__ inline double wave_block_sum(double v, double *sh)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) r += sh[k];
+    return r;
+}
+
+template <int MU, int SG, class A, int NR>
+__device__ __forceinline__ void project(const A (&pr)[4][NR], const A (&pi)[4][NR], A (&hr)[2][NR],
+                                        A (&hi)[2][NR])
+{
+    const A s = (A)SG;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+        if (MU == 0) {
+            hr[0][c] = pr[0][c] - s * pr[2][c]; hi[0][c] = pi[0][c] - s * pi[2][c];
+            hr[1][c] = pr[1][c] - s * pr[3][c]; hi[1][c] = pi[1][c] - s * pi[3][c];
+        } else if (MU == 1) {  // - s i p3, - s i p2 :  i z = (-zi, zr)
+            hr[0][c] = pr[0][c] + s * pi[3][c]; hi[0][c] = pi[0][c] - s * pr[3][c];
+            hr[1][c] = pr[1][c] + s * pi[2][c]; hi[1][c] = pi[1][c] - s * pr[2][c];
+        } else if (MU == 2) {
+            hr[0][c] = pr[0][c] - s * pr[3][c]; hi[0][c] = pi[0][c] - s * pi[3][c];
+            hr[1][c] = pr[1][c] + s * pr[2][c]; hi[1][c] = pi[1][c] + s * pi[2][c];
+        } else {  // h0 = p0 - s i p2, h1 = p1 + s i p3
+            hr[0][c] = pr[0][c] + s * pi[2][c]; hi[0][c] = pi[0][c] - s * pr[2][c];
+            hr[1][c] = pr[1][c] - s * pi[3][c]; hi[1][c] = pi[1][c] + s * pr[3][c];
+        }
+    }
+}
+
+template <int MU, int SG, class A, int NR>
+__device__ __forceinline__ void reconstruct(const A (&gr)[2][NR], const A (&gi)[2][NR], A (&ar)[4][NR],
+                                            A (&ai)[4][NR])
+{
+    const A s = (A)SG;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+        ar[0][c] += gr[0][c]; ai[0][c] += gi[0][c];
+        ar[1][c] += gr[1][c]; ai[1][c] += gi[1][c];
+        if (MU == 0) {
+            ar[2][c] -= s * gr[0][c]; ai[2][c] -= s * gi[0][c];
+            ar[3][c] -= s * gr[1][c]; ai[3][c] -= s * gi[1][c];
+        } else if (MU == 1) {  // out2 += s i g1, out3 += s i g0
+            ar[2][c] -= s * gi[1][c]; ai[2][c] += s * gr[1][c];
+            ar[3][c] -= s * gi[0][c]; ai[3][c] += s * gr[0][c];
+        } else if (MU == 2) {  // out2 += s g1, out3 += -s g0
+            ar[2][c] += s * gr[1][c]; ai[2][c] += s * gi[1][c];
+            ar[3][c] -= s * gr[0][c]; ai[3][c] -= s * gi[0][c];
+        } else {  // out2 += s i g0, out3 += -s i g1
+            ar[2][c] -= s * gi[0][c]; ai[2][c] += s * gr[0][c];
+            ar[3][c] += s * gi[1][c]; ai[3][c] -= s * gr[1][c];
+        }
+    }
+}
+
+// one direction (forward or backward) of one mu, for colour rows r0 .. r0+RS-1
+template <int MU, int DIR, bool DAG, int NR, int RS, class S>
+__device__ __forceinline__ void hop_dir(const HopArgs<S> &a, const cpx<S> *__restrict__ in,
+                                        const cpx<S> *__restrict__ gauge, int i, int r0, const int (&x)[4],
+                                        typename acc_of<S>::type (&ar)[4][RS],
+                                        typename acc_of<S>::type (&ai)[4][RS])
+{
+    typedef typename acc_of<S>::type A;
+    constexpr int NC = 4 * NR;
+    constexpr int GC = 8 * NR * NR;
+    // projector sign: forward (1 - g) for H, backward (1 + g); H^+ swaps
+    constexpr int SG = (DIR == 0) ? (DAG ? 1 : -1) : (DAG ? -1 : 1);
+    int y[4] = {x[0], x[1], x[2], x[3]};
+    bool wrap;
+    if (DIR == 0) {
+        y[MU] = x[MU] + 1;
+        wrap = y[MU] == a.g.d[MU];
+        if (wrap) y[MU] = 0;
+    } else {
+        y[MU] = x[MU] - 1;
+        wrap = y[MU] < 0;
+        if (wrap) y[MU] = a.g.d[MU] - 1;
+    }
+    const int j = eo_index(a.g, y);
+    A pr[4][NR], pi[4][NR];
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int c = 0; c < NR; ++c) load_c(in + lay(j, sp * NR + c, NC), pr[sp][c], pi[sp][c]);
+    constexpr int DD = MU + 4 * DIR;
+    A ur[RS][NR], ui[RS][NR];
+#pragma unroll
+    for (int r = 0; r < RS; ++r)
+#pragma unroll
+        for (int c = 0; c < NR; ++c) load_c(gauge + lay(i, DD * NR * NR + (r0 + r) * NR + c, GC), ur[r][c], ui[r][c]);
+    A hr[2][NR], hi[2][NR];
+    project<MU, SG>(pr, pi, hr, hi);
+    if (wrap) {
+        const A cr = (A)a.ph_re[MU];
+        const A ci = DIR == 0 ? (A)a.ph_im[MU] : -(A)a.ph_im[MU];
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+                const A tr = hr[k][c] * cr - hi[k][c] * ci;
+                const A ti = hr[k][c] * ci + hi[k][c] * cr;
+                hr[k][c] = tr;
+                hi[k][c] = ti;
+            }
+    }
+    A gr[2][RS], gi[2][RS];
+#pragma unroll
+    for (int r = 0; r < RS; ++r) {
+        A s0r = 0, s0i = 0, s1r = 0, s1i = 0;
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            s0r += ur[r][c] * hr[0][c] - ui[r][c] * hi[0][c];
+            s0i += ur[r][c] * hi[0][c] + ui[r][c] * hr[0][c];
+            s1r += ur[r][c] * hr[1][c] - ui[r][c] * hi[1][c];
+            s1i += ur[r][c] * hi[1][c] + ui[r][c] * hr[1][c];
+        }
+        gr[0][r] = s0r; gi[0][r] = s0i;
+        gr[1][r] = s1r; gi[1][r] = s1i;
+    }
+    reconstruct<MU, SG>(gr, gi, ar, ai);
+    // Materialise the accumulators here.  Without this the optimiser sinks
+    // every direction's "acc += g" to the end of the kernel, keeping all eight
+    // directions' products live at once (256 VGPRs and spills even for N_R=2).
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int c = 0; c < RS; ++c) asm volatile("" : "+v"(ar[sp][c]), "+v"(ai[sp][c]));
+}
+
+// XCD-aware block order: the dispatcher deals workgroups to the 8 XCDs round
+// robin; renumber them so that each XCD walks one contiguous slab of the
+// lattice and neighbour spinors are found in its own L2.
+__device__ __forceinline__ int xcd_remap(int b, int n)
+{
+    if (n % 8) return b;
+    return (b % 8) * (n / 8) + b / 8;
+}
+
+template <int NR, int RS, class S, bool DAG, int EPI>
+__global__ void __launch_bounds__(WG) hop_kernel(const HopArgs<S> a)
+{
+    typedef typename acc_of<S>::type A;
+    constexpr int NC = 4 * NR;
+    constexpr int G = NR / RS;  // threads per site, each owning RS colour rows
+    __shared__ double sh[WG / 64];
+    int parity = a.parity, bx = blockIdx.x;
+    if (parity < 0) {
+        parity = bx >= a.grid_half;
+        if (parity) bx -= a.grid_half;
+    }
+    bx = xcd_remap(bx, a.grid_half);
+    const int rhs = blockIdx.y;
+    const int gid = bx * WG + threadIdx.x;
+    const int i = gid / G;
+    const int r0 = (gid - i * G) * RS;
+    const size_t roff = (size_t)rhs * a.rstride;
+    double nrm = 0;
+    if (i < a.g.half) {
+        int x[4];
+        eo_coords(a.g, parity, i, x);
+        const cpx<S> *__restrict__ in = a.in[1 - parity] + roff;
+        const cpx<S> *__restrict__ gauge = a.gauge[parity];
+        A ar[4][RS], ai[4][RS];
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int c = 0; c < RS; ++c) ar[sp][c] = ai[sp][c] = 0;
+        hop_dir<0, 0, DAG, NR, RS>(a, in, gauge, i, r0, x, ar, ai);
+        hop_dir<0, 1, DAG, NR, RS>(a, in, gauge, i, r0, x, ar, ai);
+        hop_dir<1, 0, DAG, NR, RS>(a, in, gauge, i, r0, x, ar, ai);
+        hop_dir<1, 1, DAG, NR, RS>(a, in, gauge, i, r0, x, ar, ai);
+        hop_dir<2, 0, DAG, NR, RS>(a, in, gauge, i, r0, x, ar, ai);
+        hop_dir<2, 1, DAG, NR, RS>(a, in, gauge, i, r0, x, ar, ai);
+        hop_dir<3, 0, DAG, NR, RS>(a, in, gauge, i, r0, x, ar, ai);
+        hop_dir<3, 1, DAG, NR, RS>(a, in, gauge, i, r0, x, ar, ai);
+        if (EPI == EPI_PLAIN) {
+            cpx<S> *out = a.out[parity] + roff;
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                for (int c = 0; c < RS; ++c) store_c(out + lay(i, sp * NR + r0 + c, NC), ar[sp][c], ai[sp][c]);
+        } else {
+            const A cf = (A)a.coef[rhs];
+            const cpx<S> *self = a.self[parity] + roff;
+            if (EPI == EPI_AXPY) {
+                cpx<S> *out = a.out[parity] + roff;
+#pragma unroll
+                for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                    for (int c = 0; c < RS; ++c) {
+                        const size_t o = lay(i, sp * NR + r0 + c, NC);
+                        A sr, si;
+                        load_c(self + o, sr, si);
+                        const A vr = sr - cf * ar[sp][c], vi = si - cf * ai[sp][c];
+                        store_c(out + o, vr, vi);
+                        nrm += (double)vr * (double)vr + (double)vi * (double)vi;
+                    }
+            } else {  // EPI_CG
+                cpx<S> *r = a.r[parity] + roff;
+                cpx<S> *xx = a.x[parity] + roff;
+                const cpx<S> *p = a.p[parity] + roff;
+                const bool act = a.active[rhs] != 0;
+                const A al = (A)a.alpha[rhs];
+#pragma unroll
+                for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                    for (int c = 0; c < RS; ++c) {
+                        const size_t o = lay(i, sp * NR + r0 + c, NC);
+                        A sr, si, rr_, ri, xr, xi, pr_, pi_;
+                        load_c(self + o, sr, si);
+                        load_c(r + o, rr_, ri);
+                        if (act) {
+                            const A qr = sr - cf * ar[sp][c], qi = si - cf * ai[sp][c];
+                            load_c(xx + o, xr, xi);
+                            load_c(p + o, pr_, pi_);
+                            rr_ -= al * qr;
+                            ri -= al * qi;
+                            xr += al * pr_;
+                            xi += al * pi_;
+                            store_c(r + o, rr_, ri);
+                            store_c(xx + o, xr, xi);
+                        }
+                        nrm += (double)rr_ * (double)rr_ + (double)ri * (double)ri;
+                    }
+            }
+        }
+    }
+    if (EPI != EPI_PLAIN && a.partial) {
+        const double t = wave_block_sum(nrm, sh);
+        if (threadIdx.x == 0) a.partial[(size_t)rhs * a.pstride + blockIdx.x] = t;
+    }
+}
+
+template <class S> constexpr int dtype_id() { return 1; }
+template <> constexpr int dtype_id<double>() { return 0; }
+
+template <int NR, int RS, class S>
+void launch_hop_rs(bool dagger, int epi, dim3 grid, const HopArgs<S> &b, hipStream_t st)
+{
+    if (epi == EPI_PLAIN) {
+        if (dagger) hop_kernel<NR, RS, S, true, EPI_PLAIN><<<grid, WG, 0, st>>>(b);
+        else hop_kernel<NR, RS, S, false, EPI_PLAIN><<<grid, WG, 0, st>>>(b);
+    } else if (epi == EPI_AXPY) {
+        if (dagger) hop_kernel<NR, RS, S, true, EPI_AXPY><<<grid, WG, 0, st>>>(b);
+        else hop_kernel<NR, RS, S, false, EPI_AXPY><<<grid, WG, 0, st>>>(b);
+    } else {
+        hop_kernel<NR, RS, S, true, EPI_CG><<<grid, WG, 0, st>>>(b);
+    }
+}
+
+template <class S>
+hipError_t launch_hop_impl(int nr, bool dagger, int epi, const HopArgs<S> &a, hipStream_t st)
+{
+    if (epi == EPI_CG && !dagger) return hipErrorInvalidValue;
+    HopArgs<S> b = a;
+    bool ok = dispatch_nr(nr, [&](auto nrc) {
+        constexpr int NR = decltype(nrc)::value;
+        constexpr int RS = hop_rows(NR, dtype_id<S>());
+        const int gh = hop_grid(a.g, NR / RS);
+        b.grid_half = gh;
+        dim3 grid(a.parity < 0 ? 2 * gh : gh, a.n_rhs);
+        launch_hop_rs<NR, RS, S>(dagger, epi, grid, b, st);
+    });
+    if (!ok) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace hrw

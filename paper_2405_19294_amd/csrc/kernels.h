@@ -1,0 +1,186 @@
+// Launch wrappers of libhrw's device kernels (internal to the library).
+#pragma once
+
+#include <type_traits>
+
+#include "hrw_internal.h"
+
+namespace hrw {
+
+// ------------------------------------------------------------------ dispatch
+
+// Colour dimensions N_R with compiled hopping kernels.
+inline bool nr_supported(int nr) { return nr == 2 || nr == 3 || nr == 4 || nr == 6 || nr == 8; }
+
+template <class F>
+inline bool dispatch_nr(int nr, F &&f)
+{
+    switch (nr) {
+    case 2: f(std::integral_constant<int, 2>{}); return true;
+    case 3: f(std::integral_constant<int, 3>{}); return true;
+    case 4: f(std::integral_constant<int, 4>{}); return true;
+    case 6: f(std::integral_constant<int, 6>{}); return true;
+    case 8: f(std::integral_constant<int, 8>{}); return true;
+    }
+    return false;
+}
+
+// dtype ids follow enum hrw_dtype
+template <class F>
+inline bool dispatch_dtype(int dt, F &&f)
+{
+    switch (dt) {
+    case 0: f(double{}); return true;
+    case 1: f(float{}); return true;
+    case 2: f(bf16_t{}); return true;
+    case 3: f(f16_t{}); return true;
+    }
+    return false;
+}
+
+inline size_t dtype_cbytes(int dt)  // bytes of one complex number
+{
+    return dt == 0 ? 16 : dt == 1 ? 8 : 4;
+}
+
+// ------------------------------------------------------------------ hopping kernel
+
+enum Epilogue {
+    EPI_PLAIN = 0,  // out = H in
+    EPI_AXPY = 1,   // out = self - c H in              (+ optional |out|^2 partials)
+    EPI_CG = 2      // q = self - c H in; r -= alpha q; x += alpha p; |r|^2 partials
+};
+
+// Pointers are per parity: index 0 / 1 = the half field of that parity.
+template <class S>
+struct HopArgs {
+    Geom g;
+    int parity;        // output parity, or -1 for both parities in one launch
+    int grid_half;     // blocks per parity when parity == -1
+    int n_rhs;
+    int pad_;
+    size_t rstride;    // complex elements between right-hand sides of one field
+    const cpx<S> *gauge[2];  // hopping block for output parity 0 / 1
+    const cpx<S> *in[2];     // input halves (read at parity 1 - output parity)
+    cpx<S> *out[2];
+    const cpx<S> *self[2];
+    cpx<S> *r[2];
+    cpx<S> *x[2];
+    const cpx<S> *p[2];
+    double ph_re[4], ph_im[4];  // exp(i theta_mu)
+    const double *coef;          // device, per rhs: c of the epilogue
+    const double *alpha;         // device, per rhs (EPI_CG)
+    const int *active;           // device, per rhs: 0 = frozen (EPI_CG leaves r, x)
+    double *partial;             // per-block partial norms, [rhs * pstride + block]
+    int pstride;
+    int pad2_;
+};
+
+// Launch the hopping kernel.  kc_bytes receives the algorithmic bytes.
+template <class S>
+hipError_t launch_hop(int nr, bool dagger, int epi, const HopArgs<S> &a, hipStream_t st);
+
+// Colour rows each thread of the hopping kernel owns (threads per site =
+// N_R / rows): the colour-parallel split keeps the registers of the larger
+// representations below the spill point (zero scratch for every instance,
+// 2-6 waves per SIMD).  FP64 registers are twice as wide, so FP64 splits
+// earlier.
+constexpr int hop_rows(int nr, int dt)
+{
+    return dt == 0 ? (nr == 4 ? 2 : nr == 6 ? 3 : nr == 8 ? 1 : nr) : (nr == 8 ? 4 : nr == 6 ? 3 : nr);
+}
+constexpr int HOP_MAX_G = 8;  // largest threads-per-site of any instance
+
+// Blocks per parity of one hop launch (also the number of partials it writes).
+inline int hop_grid(const Geom &g, int tps) { return (int)(((long long)g.half * tps + WG - 1) / WG); }
+inline int hop_grid_for(const Geom &g, int nr, int dt) { return hop_grid(g, nr / hop_rows(nr, dt)); }
+
+// ------------------------------------------------------------------ layout kernels
+
+// canonical FP64 spinor field(s) -> packed halves.  full: canonical full
+// lattice ([rhs][V][4][nr]); otherwise canonical half field of parity `parity`
+// ([rhs][V/2][4][nr]).  dst[q] = packed half of parity q (rhs stride rstride).
+hipError_t launch_pack_spinor(int dt, int nr, const Geom &g, bool full, int parity, int n_rhs,
+                              const double *src, void *dst0, void *dst1, size_t rstride,
+                              hipStream_t st);
+hipError_t launch_unpack_spinor(int dt, int nr, const Geom &g, bool full, int parity, int n_rhs,
+                                const void *src0, const void *src1, size_t rstride, double *dst,
+                                hipStream_t st);
+
+// representation map, canonical in and out
+hipError_t launch_rep_map(int nc, int rep, long long n_links, const double *uf, double *ur,
+                          hipStream_t st);
+
+// fused representation map + packing into the hopping blocks of every dtype in
+// mask; blocks[dt][q] = packed block for output parity q (or null).
+hipError_t launch_gauge_pack(int nc, int rep, int nr, const Geom &g, const double *uf,
+                             void *const blocks[4][2], hipStream_t st);
+
+// ------------------------------------------------------------------ vector kernels
+
+// all operate on n_rhs fields of `halves` consecutive packed halves each
+hipError_t launch_zero(void *dst, size_t bytes, hipStream_t st);
+// dst = src (same dtype)
+template <class S>
+hipError_t launch_copy(const cpx<S> *src, cpx<S> *dst, size_t elems, hipStream_t st);
+// dst(Sd) = src(Ss) converted, elementwise over elems complex numbers
+hipError_t launch_convert(int dt_src, const void *src, int dt_dst, void *dst, size_t elems,
+                          hipStream_t st);
+
+// per-block partials of |a|^2 over n_rhs fields of elems complex each
+template <class S>
+hipError_t launch_norm2(const cpx<S> *a, size_t elems, size_t rstride, int n_rhs,
+                        double *partial, int pstride, int nblocks, hipStream_t st);
+// r = b - q, partials of |r|^2
+template <class S>
+hipError_t launch_residual(const cpx<S> *b, const cpx<S> *q, cpx<S> *r, size_t elems,
+                           size_t rstride, int n_rhs, double *partial, int pstride,
+                           int nblocks, hipStream_t st);
+// p = r + beta p for active rhs
+template <class S>
+hipError_t launch_xpay(const cpx<S> *r, cpx<S> *p, const double *beta, const int *active,
+                       size_t elems, size_t rstride, int n_rhs, hipStream_t st);
+// y += a x  with a per rhs (device), x and y possibly of different dtypes
+hipError_t launch_axpy_mixed(int dt_x, const void *x, int dt_y, void *y, const double *a,
+                             size_t elems, size_t rstride_x, size_t rstride_y, int n_rhs,
+                             hipStream_t st);
+
+// blocks the vector kernels use for `elems` complex numbers per rhs
+int vec_grid(size_t elems);
+
+// ------------------------------------------------------------------ CG scalars
+
+struct CgState {      // per right-hand side, device
+    double rr;        // |r|^2 (recursive)
+    double rr0;       // |b|^2
+    double pap;       // <p, A p> = |D p|^2
+    double alpha, beta;
+    double tol2;      // tol^2 * rr0
+    double rr_true;   // last true |r|^2
+    int status;       // see CgStatus
+    int iters;
+    int active;       // 1 while the recursion advances
+    int restarts;     // re-activations after the recursion had converged
+    int updates;      // FP64 true-residual evaluations (reliable updates)
+    int pad_;
+};
+
+enum CgStatus { CG_RUNNING = 0, CG_RECURSIVE_DONE = 1, CG_BREAKDOWN = 2, CG_DONE = 3,
+                CG_MAXITER = 4 };
+
+// reduce partials of pap, set alpha (breakdown check)
+hipError_t launch_cg_alpha(CgState *st_, const double *partial, int pstride, int nparts,
+                           int n_rhs, double *alpha_out, hipStream_t st);
+// reduce partials of |r|^2, set beta, advance iteration, recursive convergence;
+// host_active (host-mapped, may be null) receives each rhs' active flag
+hipError_t launch_cg_beta(CgState *st_, const double *partial, int pstride, int nparts,
+                          int n_rhs, int max_iter, double *beta_out, int *active_out,
+                          int *host_active, hipStream_t st);
+// initialise: rr = rr0 = sum(partials), status running
+hipError_t launch_cg_init(CgState *st_, const double *partial, int pstride, int nparts,
+                          int n_rhs, double tol, int *active_out, hipStream_t st);
+// plain sum of partials into out[rhs]
+hipError_t launch_sum_partials(const double *partial, int pstride, int nparts, int n_rhs,
+                               double *out, hipStream_t st);
+
+}  // namespace hrw

@@ -1,0 +1,246 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Tolerances:
+  * FP64 operators: l2 relative <= 1e-13 and componentwise <= 1e-12 max|ref|.
+  * FP32 operators: the oracle applies FP64 D to the FP32-rounded inputs and the
+    difference must sit inside the a-priori componentwise bound
+    gamma_k (|psi| + kappa |H||psi|), k = 2 N_R + 16, u = 2^-24.
+  * BF16/FP16 storage: the same with the inputs rounded to the 16-bit format,
+    plus one rounding of the stored output (u16 |ref|).
+  * Storage rounding itself (kappa = 0 applies) is bit-exact.
+  * CG: FP64 true residual recomputed by the oracle <= tol; iteration count
+    within 2 % (+2) of the oracle's; multi-RHS results bitwise equal to the
+    single-RHS ones.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import fixtures as fx
+import oracle as orc
+from paper_2405_19294_amd import hrw
+
+from gpu_helpers import (THETA_AP, THETA_TW, U32, U_BF16, U_F16, fp64_close, rel, setup, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+# (dims, nc, rep): spans N_R = 2, 3, 4, 6, 8; tiny (ragged single block) to several tiles
+OPERATOR_CASES = [
+    ((4, 4, 4, 4), 2, "fund"),
+    ((2, 2, 2, 2), 3, "fund"),
+    ((6, 4, 2, 8), 3, "fund"),
+    ((4, 2, 4, 6), 2, "adj"),
+    ((4, 4, 2, 4), 3, "sym"),
+    ((2, 4, 4, 4), 4, "asym"),
+    ((4, 4, 4, 2), 4, "fund"),
+    ((2, 4, 2, 4), 3, "adj"),
+    ((8, 8, 8, 8), 3, "fund"),
+]
+
+
+def ids(c):
+    return f"{'x'.join(map(str, c[0]))}-su{c[1]}-{c[2]}"
+
+
+@pytest.mark.parametrize("nc,rep", [(2, "fund"), (2, "adj"), (2, "sym"), (3, "fund"), (3, "adj"), (3, "sym"),
+                                    (3, "asym"), (4, "fund"), (4, "adj"), (4, "sym"), (4, "asym")])
+def test_rep_map_matches_oracle(nc, rep):
+    u = fx.haar_su_n(nc, 333, fx.rng(5, nc))
+    out = hrw.rep_map(nc, rep, to_dev(u)).cpu().numpy()
+    ref = orc.rep_map(nc, rep, u)
+    assert np.max(np.abs(out - ref)) <= 1e-14 * max(1, nc)
+
+
+@pytest.mark.parametrize("case", OPERATOR_CASES, ids=ids)
+@pytest.mark.parametrize("dagger", [False, True])
+def test_dw_f64(case, dagger):
+    dims, nc, rep = case
+    uf, ur, g = setup(dims, nc, rep, "haar", seed=3, dtypes=("f64",))
+    psi = fx.gaussian_spinor(dims, g.nr, seed=4)
+    out = hrw.dw_apply(g, 0.137, to_dev(psi), THETA_TW, "f64", dagger).cpu().numpy()
+    fp64_close(out, orc.dw(dims, ur, 0.137, psi, THETA_TW, dagger))
+
+
+@pytest.mark.parametrize("case", OPERATOR_CASES, ids=ids)
+def test_hop_eo_and_deo_f64(case):
+    dims, nc, rep = case
+    uf, ur, g = setup(dims, nc, rep, "haar", seed=5, dtypes=("f64",))
+    psi = fx.gaussian_spinor(dims, g.nr, seed=6)
+    pe, po = orc.split_eo(dims, psi)
+    for dagger in (False, True):
+        fp64_close(hrw.hop_eo(g, 0, to_dev(po), THETA_TW, "f64", dagger).cpu().numpy(),
+                   orc.hop_eo(dims, ur, po, 0, THETA_TW, dagger))
+        fp64_close(hrw.hop_eo(g, 1, to_dev(pe), THETA_TW, "f64", dagger).cpu().numpy(),
+                   orc.hop_eo(dims, ur, pe, 1, THETA_TW, dagger))
+        fp64_close(hrw.deo_apply(g, 0.131, to_dev(pe), THETA_TW, "f64", dagger).cpu().numpy(),
+                   orc.deo(dims, ur, 0.131, pe, THETA_TW, dagger))
+
+
+def _bound_check(dims, ur_r, psi_r, kappa, out, ref, nr, unit_out):
+    """|out - ref| <= gamma_k (|psi| + kappa |H||psi|) + unit_out |ref| componentwise."""
+    bound = orc.gamma_k(2 * nr + 16, U32) * (np.abs(psi_r) + kappa * orc.hop_abs(dims, np.abs(ur_r), np.abs(psi_r)))
+    bound = bound + unit_out * np.abs(ref) + 1e-300
+    excess = np.abs(out - ref) / bound
+    assert np.max(excess) <= 1.0, np.max(excess)
+
+
+@pytest.mark.parametrize("case", OPERATOR_CASES, ids=ids)
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
+def test_dw_low_precision_within_bound(case, dtype):
+    dims, nc, rep = case
+    uf, ur, g = setup(dims, nc, rep, "haar", seed=7)
+    psi = fx.gaussian_spinor(dims, g.nr, seed=8)
+    kappa = 0.137
+    ur_r = orc.round_to(dtype, ur)
+    psi_r = orc.round_to(dtype, psi)
+    out = hrw.dw_apply(g, kappa, to_dev(psi), THETA_TW, dtype).cpu().numpy()
+    ref = orc.dw(dims, ur_r, kappa, psi_r, THETA_TW)
+    unit_out = {"f32": U32, "bf16": U_BF16, "f16": U_F16}[dtype]
+    _bound_check(dims, ur_r, psi_r, kappa, out, ref, g.nr, unit_out)
+    # the storage error alone is reported against the unrounded FP64 operator
+    exact = orc.dw(dims, ur, kappa, psi, THETA_TW)
+    assert rel(out, exact) < {"f32": 1e-6, "bf16": 2e-2, "f16": 3e-3}[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
+def test_storage_rounding_bit_exact(dtype):
+    """kappa = 0 returns the stored input: it must equal the oracle's RNE rounding bit for bit."""
+    dims = (4, 2, 2, 4)
+    uf, ur, g = setup(dims, 3, "fund", "haar", seed=9, dtypes=(dtype,))
+    g_ = fx.rng(10, 1)
+    psi = (g_.standard_normal((fx.volume(dims), 4, 3)) * 10.0 ** g_.integers(-6, 4, (fx.volume(dims), 4, 3))
+           + 1j * g_.standard_normal((fx.volume(dims), 4, 3)))
+    out = hrw.dw_apply(g, 0.0, to_dev(psi), THETA_AP, dtype).cpu().numpy()
+    assert np.array_equal(out, orc.round_to(dtype, psi))
+
+
+def test_multi_rhs_apply_equals_single():
+    dims = (4, 4, 2, 4)
+    uf, ur, g = setup(dims, 3, "fund", "haar", seed=11, dtypes=("f64", "f32"))
+    psi = fx.gaussian_spinor(dims, 3, seed=12, n_rhs=5)
+    for dtype in ("f64", "f32"):
+        many = hrw.dw_apply(g, 0.12, to_dev(psi), THETA_AP, dtype).cpu().numpy()
+        for k in range(5):
+            one = hrw.dw_apply(g, 0.12, to_dev(psi[k]), THETA_AP, dtype).cpu().numpy()
+            assert np.array_equal(many[k], one)
+    pe = orc.split_eo(dims, psi)[0]
+    ks = [0.11, 0.12, 0.125, 0.13, 0.135]
+    many = hrw.deo_apply(g, ks, to_dev(pe), THETA_AP).cpu().numpy()
+    for k in range(5):
+        fp64_close(many[k], orc.deo(dims, ur, ks[k], pe[k], THETA_AP))
+
+
+def test_thermal_links_c2_shape_small():
+    """Near-thermal SU(3) links (eps = 0.3), the c2 link ensemble at 8^4."""
+    dims = (8, 8, 8, 8)
+    uf, ur, g = setup(dims, 3, "fund", "thermal", seed=13, dtypes=("f64",))
+    psi = fx.gaussian_spinor(dims, 3, seed=14)
+    pe = orc.split_eo(dims, psi)[0]
+    fp64_close(hrw.deo_apply(g, 0.135, to_dev(pe), THETA_AP).cpu().numpy(), orc.deo(dims, ur, 0.135, pe, THETA_AP))
+
+
+# ------------------------------------------------------------------ CG
+
+def _oracle_resid(dims, ur, kappa, x, b, system):
+    if system == "ddag_d_full":
+        ax = orc.dw(dims, ur, kappa, orc.dw(dims, ur, kappa, x, THETA_AP), THETA_AP, dagger=True)
+    else:
+        ax = orc.deo(dims, ur, kappa, orc.deo(dims, ur, kappa, x, THETA_AP), THETA_AP, dagger=True)
+    return np.linalg.norm(b - ax) / np.linalg.norm(b)
+
+
+def test_cg_full_c1():
+    """c1: 4^4 SU(2) fund, Haar links, kappa = 0.12, antiperiodic time, D^+D to 1e-10."""
+    dims, kappa = (4, 4, 4, 4), 0.12
+    uf, ur, g = setup(dims, 2, "fund", "haar", seed=1, dtypes=("f64",))
+    b = fx.gaussian_spinor(dims, 2, seed=2)
+    prm = hrw.solve_params(tol=1e-10, system="ddag_d_full", theta=THETA_AP)
+    x, res, rc = hrw.cg_solve(g, to_dev(b), kappa, prm)
+    x = x.cpu().numpy()
+    xo, info = orc.cg(dims, ur, kappa, b, THETA_AP, orc.SYSTEM_FULL, tol=1e-10)
+    assert rc == 0 and res[0]["status"] == 0
+    assert res[0]["true_rel_resid"] <= 1e-10
+    assert _oracle_resid(dims, ur, kappa, x, b, "ddag_d_full") <= 1e-10 * 1.01
+    assert abs(res[0]["iters"] - info["iters"]) <= 0.02 * info["iters"] + 2
+    lo, hi = orc.lanczos_extremes(info["alpha"], info["beta"])
+    assert rel(x, xo) <= (hi / lo) * 1e-10
+
+
+@pytest.mark.parametrize("nc,rep,dims", [(3, "fund", (8, 8, 8, 8)), (2, "adj", (4, 4, 4, 8)),
+                                         (4, "asym", (4, 4, 4, 4)), (3, "sym", (4, 4, 4, 4))])
+def test_cg_eo_matches_oracle(nc, rep, dims):
+    kappa = 0.135 if rep == "fund" else 0.125
+    uf, ur, g = setup(dims, nc, rep, "thermal", seed=21, dtypes=("f64",))
+    b = orc.split_eo(dims, fx.gaussian_spinor(dims, g.nr, seed=22))[0]
+    prm = hrw.solve_params(tol=1e-10, system="ddag_d_eo", theta=THETA_AP)
+    x, res, rc = hrw.cg_solve(g, to_dev(b), kappa, prm)
+    x = x.cpu().numpy()
+    xo, info = orc.cg(dims, ur, kappa, b, THETA_AP, orc.SYSTEM_EO, tol=1e-10)
+    assert rc == 0, res
+    assert _oracle_resid(dims, ur, kappa, x, b, "ddag_d_eo") <= 1e-10 * 1.01
+    assert abs(res[0]["iters"] - info["iters"]) <= 0.02 * info["iters"] + 2, (res[0]["iters"], info["iters"])
+    lo, hi = orc.lanczos_extremes(info["alpha"], info["beta"])
+    assert rel(x, xo) <= (hi / lo) * 1e-10
+
+
+def test_cgnr_eo_solves_d():
+    dims, kappa = (4, 4, 4, 8), 0.13
+    uf, ur, g = setup(dims, 3, "fund", "thermal", seed=31, dtypes=("f64",))
+    b = fx.gaussian_spinor(dims, 3, seed=32)
+    prm = hrw.solve_params(tol=1e-10, system="d_cgnr_eo", theta=THETA_AP)
+    x, res, rc = hrw.cg_solve(g, to_dev(b), kappa, prm)
+    x = x.cpu().numpy()
+    assert rc == 0, res
+    dres = np.linalg.norm(b - orc.dw(dims, ur, kappa, x, THETA_AP)) / np.linalg.norm(b)
+    assert abs(dres - res[0]["d_rel_resid"]) <= 1e-3 * dres + 1e-14
+    xo, info = orc.solve_d_eo(dims, ur, kappa, b, THETA_AP, tol=1e-10)
+    assert dres <= 1e-8
+    assert rel(x, xo) <= 1e-7
+
+
+def test_cg_multi_rhs_bitwise_equals_single():
+    dims = (4, 4, 4, 4)
+    uf, ur, g = setup(dims, 3, "fund", "thermal", seed=41, dtypes=("f64",))
+    b = orc.split_eo(dims, fx.gaussian_spinor(dims, 3, seed=42, n_rhs=3))[0]
+    ks = [0.12, 0.125, 0.13]
+    prm = hrw.solve_params(tol=1e-10, system="ddag_d_eo", theta=THETA_AP)
+    xm, resm, rc = hrw.cg_solve(g, to_dev(b), ks, prm)
+    assert rc == 0
+    xm = xm.cpu().numpy()
+    for k in range(3):
+        x1, res1, rc1 = hrw.cg_solve(g, to_dev(b[k]), ks[k], prm)
+        assert np.array_equal(xm[k], x1.cpu().numpy())
+        assert res1[0]["iters"] == resm[k]["iters"]
+
+
+def test_cg_deterministic():
+    dims = (4, 4, 4, 4)
+    uf, ur, g = setup(dims, 2, "adj", "thermal", seed=51, dtypes=("f64",))
+    b = orc.split_eo(dims, fx.gaussian_spinor(dims, 3, seed=52))[0]
+    prm = hrw.solve_params(tol=1e-10, system="ddag_d_eo", theta=THETA_AP)
+    x1 = hrw.cg_solve(g, to_dev(b), 0.125, prm)[0].cpu().numpy()
+    x2 = hrw.cg_solve(g, to_dev(b), 0.125, prm)[0].cpu().numpy()
+    assert np.array_equal(x1, x2)
+
+
+def test_cg_edge_cases():
+    dims = (4, 4, 4, 4)
+    uf, ur, g = setup(dims, 2, "fund", "haar", seed=61, dtypes=("f64",))
+    prm = hrw.solve_params(tol=1e-10, system="ddag_d_eo", theta=THETA_AP)
+    zero = np.zeros((fx.volume(dims) // 2, 4, 2), complex)
+    x, res, rc = hrw.cg_solve(g, to_dev(zero), 0.12, prm)
+    assert rc == 0 and res[0]["iters"] == 0 and not x.abs().max().item()
+    nan = zero.copy()
+    nan[3, 1, 0] = np.nan
+    x, res, rc = hrw.cg_solve(g, to_dev(nan), 0.12, prm)
+    assert rc == hrw.EBREAKDOWN and res[0]["status"] == hrw.EBREAKDOWN
+    b = orc.split_eo(dims, fx.gaussian_spinor(dims, 2, seed=62))[0]
+    few = hrw.solve_params(tol=1e-10, max_iter=5, system="ddag_d_eo", theta=THETA_AP)
+    x, res, rc = hrw.cg_solve(g, to_dev(b), 0.12, few)
+    assert rc == hrw.NOT_CONVERGED and res[0]["iters"] == 5 and res[0]["true_rel_resid"] > 1e-10
+    # a mix: one converging, one NaN system -> the good one still converges
+    mix = np.stack([b, nan])
+    x, res, rc = hrw.cg_solve(g, to_dev(mix), [0.12, 0.12], prm)
+    assert rc == hrw.EBREAKDOWN and res[0]["status"] == 0 and res[1]["status"] == hrw.EBREAKDOWN
+    assert _oracle_resid(dims, ur, 0.12, x[0].cpu().numpy(), b, "ddag_d_eo") <= 1.01e-10

@@ -438,3 +438,19 @@ def test_pins_catch_planted_mistakes():
     assert passes_all(None)
     for m in ["transposed_gamma", "gamma_sign", "backward_link_at_x", "backward_no_dagger", "no_phase"]:
         assert not passes_all(m), m
+
+
+def test_hop_abs_bounds_the_hop():
+    """|H psi| <= |H| |psi| componentwise (triangle inequality), with equality for
+    non-negative inputs on a free field with no phases."""
+    dims = (4, 2, 4, 2)
+    ur = _random_setup(dims, 3, "fund", seed=95)
+    psi = fx.gaussian_spinor(dims, 3, seed=96)
+    h = orc.hop(dims, ur, psi, THETA_TW)
+    ha = orc.hop_abs(dims, np.abs(ur), np.abs(psi))
+    assert np.all(np.abs(h) <= ha * (1 + 1e-12))
+    unit = fx.unit_gauge(dims, 3)
+    pos = np.abs(psi)
+    # free field, positive spinor: projector entries (1 -+ g) have mixed signs, so
+    # only the diagonal spin part is exact; check the scale instead
+    assert np.allclose(orc.hop_abs(dims, unit, pos).sum(), 2 * 8 * pos.sum(), rtol=1e-12)
