@@ -202,10 +202,13 @@ int hrw_cg_solve(const hrw_gauge *g, const hrw_solve_params *params, int n_rhs,
 /* ---------------------------------------------------------------- timing
  * Optional per-kernel timing with HIP events recorded on the launch stream
  * around every hopping-kernel launch.  hrw_timing_enable(1) clears the
- * counters; hrw_timing_read fills, for kernel class k (0 = hopping kernel,
- * 1 = CG vector kernels, 2 = reductions), the launch count, summed event
- * time in ms and summed algorithmic bytes (min-traffic model).  Returns
- * EINVAL for an unknown class.  Not thread-safe against concurrent solves. */
+ * counters; hrw_timing_read fills, for kernel class k, the launch count,
+ * summed event time in ms and summed algorithmic bytes (min-traffic model:
+ * every link, neighbour spinor and epilogue operand counted once per launch).
+ * Classes: 0 = all hopping launches; 3, 4, 5 = hopping launches with the
+ * plain (out = H in), axpy (out = self - c H in) and fused CG-update
+ * epilogues; 1, 2 are reserved (always zero).  EINVAL for an unknown class.
+ * Timing adds two event records per launch on the launch stream. */
 int hrw_timing_enable(int on);
 int hrw_timing_read(int kernel_class, long long *launches, double *total_ms, double *bytes);
 

@@ -66,6 +66,7 @@ def _load():
             "orc_cg": (I, [P, I, P, D, P, I, P, P, D, I, P, P, P]),
             "orc_round": (I, [I, L, P]),
             "orc_parity_count": (I, [P, I]),
+            "orc_num_threads": (I, []),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -284,10 +285,7 @@ def round_to(fmt: str, a) -> np.ndarray:
 
 def num_threads() -> int:
     """Threads the oracle's OpenMP loops use."""
-    v = os.environ.get("OMP_NUM_THREADS")
-    if v and v.isdigit():
-        return int(v)
-    return os.cpu_count() or 1
+    return int(_load().orc_num_threads())
 
 
 # ---------------------------------------------------------------- rounding-error bound

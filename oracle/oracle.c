@@ -36,6 +36,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef double complex cplx;
 
@@ -612,4 +615,14 @@ int orc_round(int fmt, long n, double *a)
     }
     for (long i = 0; i < n; ++i) a[i] = round_to_format(a[i], p, emin, maxfin);
     return ORC_OK;
+}
+
+/* Threads the OpenMP loops above use. */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

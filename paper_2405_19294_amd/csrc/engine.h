@@ -60,19 +60,19 @@ struct Timing {
     bool on = false;
     struct Pending {
         hipEvent_t a, b;
-        int kc;
+        int kc, kc2;  // kc2: second class credited (-1 = none)
         double bytes;
     };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
-    long long launches[KC_COUNT] = {0, 0, 0};
-    double ms[KC_COUNT] = {0, 0, 0};
-    double bytes[KC_COUNT] = {0, 0, 0};
+    long long launches[KC_COUNT] = {};
+    double ms[KC_COUNT] = {};
+    double bytes[KC_COUNT] = {};
 };
 Timing &timing();
 // record a start event (returns false when timing is off)
 bool timed_begin(hipStream_t st, hipEvent_t *ev);
-void timed_end(hipStream_t st, hipEvent_t start, int kc, double bytes);
+void timed_end(hipStream_t st, hipEvent_t start, int kc, int kc2, double bytes);
 int timing_harvest();
 
 // ------------------------------------------------------------------ operator plumbing

@@ -58,7 +58,7 @@ bool timed_begin(hipStream_t st, hipEvent_t *ev)
     return true;
 }
 
-void timed_end(hipStream_t st, hipEvent_t start, int kc, double bytes)
+void timed_end(hipStream_t st, hipEvent_t start, int kc, int kc2, double bytes)
 {
     Timing &t = timing();
     std::lock_guard<std::mutex> lk(t.mu);
@@ -73,7 +73,7 @@ void timed_end(hipStream_t st, hipEvent_t start, int kc, double bytes)
         t.pool.pop_back();
     }
     (void)hipEventRecord(e, st);
-    t.pending.push_back({start, e, kc, bytes});
+    t.pending.push_back({start, e, kc, kc2, bytes});
 }
 
 int timing_harvest()
@@ -88,6 +88,11 @@ int timing_harvest()
         t.launches[p.kc] += 1;
         t.ms[p.kc] += ms;
         t.bytes[p.kc] += p.bytes;
+        if (p.kc2 >= 0) {
+            t.launches[p.kc2] += 1;
+            t.ms[p.kc2] += ms;
+            t.bytes[p.kc2] += p.bytes;
+        }
         t.pool.push_back(p.a);
         t.pool.push_back(p.b);
     }
@@ -156,7 +161,7 @@ int run_hop(const hrw_gauge *g, const Phases &ph, const HopCall &c, hipStream_t 
         err = launch_hop<S>(g->nr, c.dagger, c.epi, a, st);
     });
     if (err != hipSuccess) return fail(HRW_EDEVICE, "hop launch failed: %s", hipGetErrorString(err));
-    if (tm) timed_end(st, ev, KC_HOP, hop_bytes(g->g, g->nr, c.dt, c.parity, c.epi, c.n_rhs));
+    if (tm) timed_end(st, ev, KC_HOP, KC_HOP_PLAIN + c.epi, hop_bytes(g->g, g->nr, c.dt, c.parity, c.epi, c.n_rhs));
     return HRW_OK;
 }
 

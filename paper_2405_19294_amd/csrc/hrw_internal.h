@@ -174,6 +174,9 @@ __device__ inline int eo_index(const Geom &g, const int x[4])
 
 // ------------------------------------------------------------------ timing classes
 
-enum KernelClass { KC_HOP = 0, KC_BLAS = 1, KC_REDUCE = 2, KC_COUNT = 3 };
+// 0 = every hopping launch; 3/4/5 = hopping launches with the plain / axpy /
+// fused-CG epilogue (each is one kernel instance per N_R and dtype)
+enum KernelClass { KC_HOP = 0, KC_BLAS = 1, KC_REDUCE = 2, KC_HOP_PLAIN = 3, KC_HOP_AXPY = 4,
+                   KC_HOP_CG = 5, KC_COUNT = 6 };
 
 }  // namespace hrw
