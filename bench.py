@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "D_W GB/s & % HBM roofline; CG solves/s at 1e-10 resid vs FP64; p99 latency"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hop_traffic_su3_fund_32x4_f64.json")
 
 WORKLOAD = {
     "workload": "su3_fund_32^4_eo_cg_fp64",
@@ -131,6 +132,11 @@ def main():
     dom = classes[dom_name]
     achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9 if dom["ms"] > 0 else 0.0
     allhop = classes["hop_all"]
+    # HBM bytes per launch from the committed counter record, if it was taken
+    # with the current kernel sources (None otherwise)
+    from paper_2405_19294_amd import profsum
+    epi_tag = {"hop_plain": ", 0>", "hop_axpy": ", 1>", "hop_cg": ", 2>"}[dom_name]
+    traffic = profsum.traffic_for("hop_kernel<3, 3, double, false" + epi_tag, TRAFFIC_RECORD)
     roofline = {
         "bound": "hbm",
         "kernel": f"hop_kernel<N_R=3, RS=3, double, {dom_name[4:]} epilogue>",
@@ -138,7 +144,8 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": round(traffic) if traffic else None,
+        "traffic_unit": "bytes per launch (FETCH_SIZE x2 + WRITE_SIZE, calibrated on a 1 GiB copy)",
         "avg_launch_us": round(dom["ms"] / max(dom["launches"], 1) * 1e3, 2),
         "bytes_per_launch": round(dom["bytes"] / max(dom["launches"], 1)),
         "launches": dom["launches"],
@@ -166,9 +173,29 @@ def main():
         "solve": {"iters": r["iters"], "true_rel_resid": r["true_rel_resid"], "d_rel_resid": r["d_rel_resid"]},
     }
 
+    out["hbm_copy_reference"] = copy_reference(torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dims, uf, b, kappa, theta, r["iters"], args.cpu_iters)
     print(json.dumps(out), flush=True)
+
+
+def copy_reference(torch, dev, nbytes=1 << 30, reps=10):
+    """Device-to-device copy of 1 GiB (torch's copy kernel): the attainable
+    streaming bandwidth on this GPU, and the known-size kernel the HBM byte
+    counters are calibrated against."""
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+    bb = torch.empty_like(a)
+    bb.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        bb.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"bytes_per_copy": 2 * nbytes, "avg_us": round(ms * 1e3, 2),
+            "gbs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
 
 
 def cpu_baseline(dims, uf, b, kappa, theta, gpu_iters, cpu_iters):

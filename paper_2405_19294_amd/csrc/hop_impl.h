@@ -124,7 +124,7 @@ __device__ __forceinline__ void hop_dir(const HopArgs<S> &a, const cpx<S> *__res
 #pragma unroll
     for (int r = 0; r < RS; ++r)
 #pragma unroll
-        for (int c = 0; c < NR; ++c) load_c(gauge + lay(i, DD * NR * NR + (r0 + r) * NR + c, GC), ur[r][c], ui[r][c]);
+        for (int c = 0; c < NR; ++c) load_c_nt(gauge + lay(i, DD * NR * NR + (r0 + r) * NR + c, GC), ur[r][c], ui[r][c]);
     A hr[2][NR], hi[2][NR];
     project<MU, SG>(pr, pi, hr, hi);
     if (wrap) {
@@ -173,6 +173,21 @@ __device__ __forceinline__ int xcd_remap(int b, int n)
     return (b % 8) * (n / 8) + b / 8;
 }
 
+// Time-tiled walk: the slab an XCD owns is traversed chunk by chunk, each
+// spatial chunk of C workgroups through every time slice before the next, so
+// the +-t neighbours of a block are touched C workgroups apart instead of a
+// whole time slice apart (which exceeds an XCD's L2 at 32^4).
+__device__ __forceinline__ int tile_remap(int L, int n, int ts, int c)
+{
+    if (ts <= 0) return L;
+    const int T = n / ts;
+    const int ch = L / (c * T);
+    const int rem = L - ch * c * T;
+    const int t = rem / c;
+    const int w = rem - t * c;
+    return t * ts + ch * c + w;
+}
+
 template <int NR, int RS, class S, bool DAG, int EPI>
 __global__ void __launch_bounds__(WG) hop_kernel(const HopArgs<S> a)
 {
@@ -185,7 +200,7 @@ __global__ void __launch_bounds__(WG) hop_kernel(const HopArgs<S> a)
         parity = bx >= a.grid_half;
         if (parity) bx -= a.grid_half;
     }
-    bx = xcd_remap(bx, a.grid_half);
+    bx = tile_remap(xcd_remap(bx, a.grid_half), a.grid_half, a.tile_ts, a.tile_c);
     const int rhs = blockIdx.y;
     const int gid = bx * WG + threadIdx.x;
     const int i = gid / G;
@@ -215,7 +230,7 @@ __global__ void __launch_bounds__(WG) hop_kernel(const HopArgs<S> a)
 #pragma unroll
             for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-                for (int c = 0; c < RS; ++c) store_c(out + lay(i, sp * NR + r0 + c, NC), ar[sp][c], ai[sp][c]);
+                for (int c = 0; c < RS; ++c) store_c_nt(out + lay(i, sp * NR + r0 + c, NC), ar[sp][c], ai[sp][c]);
         } else {
             const A cf = (A)a.coef[rhs];
             const cpx<S> *self = a.self[parity] + roff;
@@ -227,9 +242,9 @@ __global__ void __launch_bounds__(WG) hop_kernel(const HopArgs<S> a)
                     for (int c = 0; c < RS; ++c) {
                         const size_t o = lay(i, sp * NR + r0 + c, NC);
                         A sr, si;
-                        load_c(self + o, sr, si);
+                        load_c_nt(self + o, sr, si);
                         const A vr = sr - cf * ar[sp][c], vi = si - cf * ai[sp][c];
-                        store_c(out + o, vr, vi);
+                        store_c_nt(out + o, vr, vi);
                         nrm += (double)vr * (double)vr + (double)vi * (double)vi;
                     }
             } else {  // EPI_CG
@@ -244,18 +259,18 @@ __global__ void __launch_bounds__(WG) hop_kernel(const HopArgs<S> a)
                     for (int c = 0; c < RS; ++c) {
                         const size_t o = lay(i, sp * NR + r0 + c, NC);
                         A sr, si, rr_, ri, xr, xi, pr_, pi_;
-                        load_c(self + o, sr, si);
-                        load_c(r + o, rr_, ri);
+                        load_c_nt(self + o, sr, si);
+                        load_c_nt(r + o, rr_, ri);
                         if (act) {
                             const A qr = sr - cf * ar[sp][c], qi = si - cf * ai[sp][c];
-                            load_c(xx + o, xr, xi);
-                            load_c(p + o, pr_, pi_);
+                            load_c_nt(xx + o, xr, xi);
+                            load_c_nt(p + o, pr_, pi_);
                             rr_ -= al * qr;
                             ri -= al * qi;
                             xr += al * pr_;
                             xi += al * pi_;
-                            store_c(r + o, rr_, ri);
-                            store_c(xx + o, xr, xi);
+                            store_c_nt(r + o, rr_, ri);
+                            store_c_nt(xx + o, xr, xi);
                         }
                         nrm += (double)rr_ * (double)rr_ + (double)ri * (double)ri;
                     }
@@ -266,6 +281,23 @@ __global__ void __launch_bounds__(WG) hop_kernel(const HopArgs<S> a)
         const double t = wave_block_sum(nrm, sh);
         if (threadIdx.x == 0) a.partial[(size_t)rhs * a.pstride + blockIdx.x] = t;
     }
+}
+
+// Tiling of the work order (see tile_remap); disabled unless every time slice
+// holds a whole number of workgroups.
+inline void hop_tiling(const Geom &g, int tps, int *ts, int *c)
+{
+    *ts = 0;
+    *c = 0;
+    const long long per_slice = (long long)g.half / g.d[0] * tps;  // threads per time slice
+    if ((long long)g.half % g.d[0] || per_slice % WG) return;
+    const int n = (int)per_slice / WG;
+    if (n < 2) return;
+    int best = 1;
+    for (int k = 1; k <= 16 && k <= n; ++k)
+        if (n % k == 0) best = k;
+    *ts = n;
+    *c = best;
 }
 
 template <class S> constexpr int dtype_id() { return 1; }
@@ -295,6 +327,7 @@ hipError_t launch_hop_impl(int nr, bool dagger, int epi, const HopArgs<S> &a, hi
         constexpr int RS = hop_rows(NR, dtype_id<S>());
         const int gh = hop_grid(a.g, NR / RS);
         b.grid_half = gh;
+        hop_tiling(a.g, NR / RS, &b.tile_ts, &b.tile_c);
         dim3 grid(a.parity < 0 ? 2 * gh : gh, a.n_rhs);
         launch_hop_rs<NR, RS, S>(dagger, epi, grid, b, st);
     });

@@ -113,6 +113,50 @@ __device__ inline void load_c(const cpx<S> *p, typename acc_of<S>::type &re,
     im = conv<S>::to_acc(v.im);
 }
 
+// Streaming (non-temporal) loads for data read exactly once per kernel, such as
+// the links of a hop: they bypass the cache-retention policy so that they do
+// not evict reusable lines (neighbour spinors) from L2.
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+
+template <class S>
+__device__ inline void load_c_nt(const cpx<S> *p, typename acc_of<S>::type &re,
+                                 typename acc_of<S>::type &im);
+template <>
+__device__ inline void load_c_nt<double>(const cpx<double> *p, double &re, double &im)
+{
+    const nt_d2 v = __builtin_nontemporal_load((const nt_d2 *)p);
+    re = v.x;
+    im = v.y;
+}
+template <>
+__device__ inline void load_c_nt<float>(const cpx<float> *p, float &re, float &im)
+{
+    const nt_f2 v = __builtin_nontemporal_load((const nt_f2 *)p);
+    re = v.x;
+    im = v.y;
+}
+template <>
+__device__ inline void load_c_nt<bf16_t>(const cpx<bf16_t> *p, float &re, float &im)
+{
+    const uint32_t w = __builtin_nontemporal_load((const uint32_t *)p);
+    bf16_t a, b;
+    a.bits = (uint16_t)(w & 0xffffu);
+    b.bits = (uint16_t)(w >> 16);
+    re = bf16_to_f32(a);
+    im = bf16_to_f32(b);
+}
+template <>
+__device__ inline void load_c_nt<f16_t>(const cpx<f16_t> *p, float &re, float &im)
+{
+    const uint32_t w = __builtin_nontemporal_load((const uint32_t *)p);
+    union { uint16_t u; f16_t h; } a, b;
+    a.u = (uint16_t)(w & 0xffffu);
+    b.u = (uint16_t)(w >> 16);
+    re = (float)a.h;
+    im = (float)b.h;
+}
+
 template <class S>
 __device__ inline void store_c(cpx<S> *p, typename acc_of<S>::type re, typename acc_of<S>::type im)
 {
@@ -120,6 +164,37 @@ __device__ inline void store_c(cpx<S> *p, typename acc_of<S>::type re, typename 
     v.re = conv<S>::from_acc(re);
     v.im = conv<S>::from_acc(im);
     *p = v;
+}
+
+// streaming store (written once, not re-read by this kernel)
+template <class S>
+__device__ inline void store_c_nt(cpx<S> *p, typename acc_of<S>::type re, typename acc_of<S>::type im);
+template <>
+__device__ inline void store_c_nt<double>(cpx<double> *p, double re, double im)
+{
+    nt_d2 v = {re, im};
+    __builtin_nontemporal_store(v, (nt_d2 *)p);
+}
+template <>
+__device__ inline void store_c_nt<float>(cpx<float> *p, float re, float im)
+{
+    nt_f2 v = {re, im};
+    __builtin_nontemporal_store(v, (nt_f2 *)p);
+}
+template <>
+__device__ inline void store_c_nt<bf16_t>(cpx<bf16_t> *p, float re, float im)
+{
+    const uint32_t w = (uint32_t)f32_to_bf16(re).bits | ((uint32_t)f32_to_bf16(im).bits << 16);
+    __builtin_nontemporal_store(w, (uint32_t *)p);
+}
+template <>
+__device__ inline void store_c_nt<f16_t>(cpx<f16_t> *p, float re, float im)
+{
+    union { uint16_t u; f16_t h; } a, b;
+    a.h = (f16_t)re;
+    b.h = (f16_t)im;
+    const uint32_t w = (uint32_t)a.u | ((uint32_t)b.u << 16);
+    __builtin_nontemporal_store(w, (uint32_t *)p);
 }
 
 // ------------------------------------------------------------------ geometry

@@ -73,6 +73,8 @@ struct HopArgs {
     const int *active;           // device, per rhs: 0 = frozen (EPI_CG leaves r, x)
     double *partial;             // per-block partial norms, [rhs * pstride + block]
     int pstride;
+    int tile_ts;                 // workgroups per time slice (0 = no tiling)
+    int tile_c;                  // workgroups per spatial chunk of the walk
     int pad2_;
 };
 
