@@ -222,6 +222,105 @@ hipError_t launch_axpy_mixed(int dt_x, const void *x, int dt_y, void *y, const d
     return hipGetLastError();
 }
 
+template <class Sl>
+__global__ void __launch_bounds__(WG) fold_kernel(cpx<Sl> *__restrict__ xl, cpx<double> *__restrict__ x64,
+                                                   const int *due, const CgState *cs, size_t n, size_t rstride)
+{
+    const int rhs = blockIdx.y;
+    if (!due[rhs]) return;
+    const double inv = 1.0 / cs[rhs].scale;
+    const size_t ro = (size_t)rhs * rstride;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+        typename acc_of<Sl>::type lr, li;
+        load_c(xl + ro + t, lr, li);
+        double hr, hi;
+        load_c(x64 + ro + t, hr, hi);
+        store_c(x64 + ro + t, hr + (double)lr * inv, hi + (double)li * inv);
+        store_c(xl + ro + t, (typename acc_of<Sl>::type)0, (typename acc_of<Sl>::type)0);
+    }
+}
+
+hipError_t launch_fold(int dt_lo, void *x_lo, double *x64, const int *due, const CgState *cs, size_t elems,
+                       size_t rstride, int n_rhs, hipStream_t st)
+{
+    bool ok = dispatch_dtype(dt_lo, [&](auto sv) {
+        typedef decltype(sv) Sl;
+        fold_kernel<Sl><<<dim3(vec_grid(elems), n_rhs), WG, 0, st>>>((cpx<Sl> *)x_lo, (cpx<double> *)x64, due,
+                                                                     cs, elems, rstride);
+    });
+    if (!ok) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <class Sl>
+__global__ void __launch_bounds__(WG) reseed_kernel(const cpx<double> *__restrict__ r64, cpx<Sl> *__restrict__ rl,
+                                                     cpx<Sl> *__restrict__ pl, const int *due, const CgState *cs,
+                                                     size_t n, size_t rstride)
+{
+    const int rhs = blockIdx.y;
+    if (!due[rhs]) return;
+    const double sn = cs[rhs].scale, so = 1.0 / cs[rhs].scale_prev;
+    const size_t ro = (size_t)rhs * rstride;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+        const cpx<double> v = r64[ro + t];
+        typename acc_of<Sl>::type orr, ori, opr, opi;
+        load_c(rl + ro + t, orr, ori);
+        load_c(pl + ro + t, opr, opi);
+        cpx<Sl> w, q;
+        w.re = conv<Sl>::from_f64(sn * v.re);
+        w.im = conv<Sl>::from_f64(sn * v.im);
+        q.re = conv<Sl>::from_f64(sn * ((double)opr * so + (v.re - (double)orr * so)));
+        q.im = conv<Sl>::from_f64(sn * ((double)opi * so + (v.im - (double)ori * so)));
+        rl[ro + t] = w;
+        pl[ro + t] = q;
+    }
+}
+
+hipError_t launch_reseed(int dt_lo, const double *r64, void *r_lo, void *p_lo, const int *due, const CgState *cs,
+                         size_t elems, size_t rstride, int n_rhs, hipStream_t st)
+{
+    bool ok = dispatch_dtype(dt_lo, [&](auto sv) {
+        typedef decltype(sv) Sl;
+        reseed_kernel<Sl><<<dim3(vec_grid(elems), n_rhs), WG, 0, st>>>((const cpx<double> *)r64, (cpx<Sl> *)r_lo,
+                                                                       (cpx<Sl> *)p_lo, due, cs, elems, rstride);
+    });
+    if (!ok) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <class Sl>
+__global__ void __launch_bounds__(WG) seed_kernel(const cpx<double> *__restrict__ b64, cpx<Sl> *__restrict__ rl,
+                                                   cpx<Sl> *__restrict__ pl, const CgState *cs, size_t n,
+                                                   size_t rstride)
+{
+    const int rhs = blockIdx.y;
+    const double sc = cs[rhs].scale;
+    const size_t ro = (size_t)rhs * rstride;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+        const cpx<double> v = b64[ro + t];
+        cpx<Sl> w;
+        w.re = conv<Sl>::from_f64(sc * v.re);
+        w.im = conv<Sl>::from_f64(sc * v.im);
+        rl[ro + t] = w;
+        pl[ro + t] = w;
+    }
+}
+
+hipError_t launch_seed(int dt_lo, const double *b64, void *r_lo, void *p_lo, const CgState *cs, size_t elems,
+                       size_t rstride, int n_rhs, hipStream_t st)
+{
+    bool ok = dispatch_dtype(dt_lo, [&](auto sv) {
+        typedef decltype(sv) Sl;
+        seed_kernel<Sl><<<dim3(vec_grid(elems), n_rhs), WG, 0, st>>>((const cpx<double> *)b64, (cpx<Sl> *)r_lo,
+                                                                     (cpx<Sl> *)p_lo, cs, elems, rstride);
+    });
+    if (!ok) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ second stage + CG scalars
 
 // sum of nparts partials of one rhs, in a fixed order; valid in thread 0
@@ -249,24 +348,27 @@ hipError_t launch_sum_partials(const double *partial, int pstride, int nparts, i
 }
 
 __global__ void __launch_bounds__(WG) cg_init_kernel(CgState *cs, const double *partial, int pstride,
-                                                      int nparts, double tol, int *active_out)
+                                                      int nparts, double tol, double scale_numer, int *active_out)
 {
     __shared__ double sh[WG / 64];
     const int rhs = blockIdx.x;
     const double s = sum_parts(partial + (size_t)rhs * pstride, nparts, sh);
     if (threadIdx.x == 0) {
         CgState c;
-        c.rr = s;
+        c.scale = (scale_numer > 0 && s > 0 && !isinf(s)) ? sqrt(scale_numer / s) : 1.0;
+        c.scale_prev = c.scale;
+        c.rr = s * c.scale * c.scale;
         c.rr0 = s;
         c.pap = 0;
         c.alpha = 0;
         c.beta = 0;
         c.tol2 = tol * tol * s;
         c.rr_true = s;
+        c.rr_last = c.rr;
         c.iters = 0;
         c.restarts = 0;
         c.updates = 0;
-        c.pad_ = 0;
+        c.since = 0;
         if (!(s == s) || isinf(s)) {
             c.status = CG_BREAKDOWN;
             c.active = 0;
@@ -283,9 +385,9 @@ __global__ void __launch_bounds__(WG) cg_init_kernel(CgState *cs, const double *
 }
 
 hipError_t launch_cg_init(CgState *cs, const double *partial, int pstride, int nparts, int n_rhs,
-                          double tol, int *active_out, hipStream_t st)
+                          double tol, double scale_numer, int *active_out, hipStream_t st)
 {
-    cg_init_kernel<<<n_rhs, WG, 0, st>>>(cs, partial, pstride, nparts, tol, active_out);
+    cg_init_kernel<<<n_rhs, WG, 0, st>>>(cs, partial, pstride, nparts, tol, scale_numer, active_out);
     return hipGetLastError();
 }
 
@@ -322,26 +424,33 @@ hipError_t launch_cg_alpha(CgState *cs, const double *partial, int pstride, int 
 }
 
 __global__ void __launch_bounds__(WG) cg_beta_kernel(CgState *cs, const double *partial, int pstride,
-                                                      int nparts, int max_iter, double *beta_out,
-                                                      int *active_out, volatile int *host_active)
+                                                      int nparts, int max_iter, ReliableSchedule sched,
+                                                      double *beta_out, int *active_out, int *advanced_out,
+                                                      volatile int *host_active)
 {
     __shared__ double sh[WG / 64];
     const int rhs = blockIdx.x;
     const double rr_new = sum_parts(partial + (size_t)rhs * pstride, nparts, sh);
     if (threadIdx.x == 0) {
         CgState c = cs[rhs];
+        advanced_out[rhs] = c.active;
         if (c.active) {
             c.iters += 1;
+            c.since += 1;
             c.beta = rr_new / c.rr;
             c.rr = rr_new;
             if (!(rr_new == rr_new) || isinf(rr_new)) {
                 c.status = CG_BREAKDOWN;
                 c.active = 0;
-            } else if (rr_new <= c.tol2) {
+            } else if (rr_new <= c.tol2 * c.scale * c.scale) {
                 c.status = CG_RECURSIVE_DONE;
                 c.active = 0;
             } else if (c.iters >= max_iter) {
                 c.status = CG_MAXITER;
+                c.active = 0;
+            } else if ((sched.every > 0 && c.since >= sched.every) ||
+                       (sched.delta2 > 0 && rr_new < sched.delta2 * c.rr_last)) {
+                c.status = CG_UPDATE_DUE;
                 c.active = 0;
             }
         } else {
@@ -350,16 +459,17 @@ __global__ void __launch_bounds__(WG) cg_beta_kernel(CgState *cs, const double *
         cs[rhs] = c;
         beta_out[rhs] = c.beta;
         active_out[rhs] = c.active;
-        if (host_active) host_active[rhs] = c.active;
+        // host flag: 1 running, 2 waiting for a reliable update, 0 otherwise
+        if (host_active) host_active[rhs] = c.active ? 1 : (c.status == CG_UPDATE_DUE ? 2 : 0);
     }
 }
 
 hipError_t launch_cg_beta(CgState *cs, const double *partial, int pstride, int nparts, int n_rhs,
-                          int max_iter, double *beta_out, int *active_out, int *host_active,
-                          hipStream_t st)
+                          int max_iter, ReliableSchedule sched, double *beta_out, int *active_out,
+                          int *advanced_out, int *host_active, hipStream_t st)
 {
-    cg_beta_kernel<<<n_rhs, WG, 0, st>>>(cs, partial, pstride, nparts, max_iter, beta_out, active_out,
-                                         host_active);
+    cg_beta_kernel<<<n_rhs, WG, 0, st>>>(cs, partial, pstride, nparts, max_iter, sched, beta_out, active_out,
+                                         advanced_out, host_active);
     return hipGetLastError();
 }
 

@@ -175,6 +175,7 @@ static int check_params(const hrw_solve_params *p)
     if (p->system < 0 || p->system > 2) return fail(HRW_EINVAL, "bad system %d", p->system);
     if (p->inner_dtype < 0 || p->inner_dtype > 3) return fail(HRW_EINVAL, "bad inner dtype %d", p->inner_dtype);
     if (p->reliable_every < 0) return fail(HRW_EINVAL, "reliable_every must be >= 0");
+    if (!(p->reliable_delta >= 0 && p->reliable_delta < 1)) return fail(HRW_EINVAL, "reliable_delta must be in [0, 1)");
     return HRW_OK;
 }
 
@@ -247,7 +248,6 @@ int hrw_cg_solve(const hrw_gauge *g, const hrw_solve_params *params, int n_rhs, 
         if ((rc = check_params(params)) || (rc = check_rhs(n_rhs))) return rc;
         if (!kappa_per_rhs || !b || !x || !res || !workspace) return fail(HRW_EINVAL, "null pointer");
         if (b == x) return fail(HRW_EINVAL, "b and x must not overlap");
-        if (params->reliable_delta != 0) return fail(HRW_EUNSUPPORTED, "reliable_delta is not implemented (use 0)");
         if (!g->blocks[0][0]) return fail(HRW_EUNSUPPORTED, "CG needs FP64 links (HRW_STORE_F64)");
         if (!g->blocks[params->inner_dtype][0]) return fail(HRW_EUNSUPPORTED, "gauge field lacks links in the inner dtype");
         return cg_solve(g, params, n_rhs, kappa_per_rhs, b, x, res, workspace, ws_bytes, (hipStream_t)stream);

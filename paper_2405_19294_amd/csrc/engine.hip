@@ -464,7 +464,7 @@ static int plan_cg(Arena &ar, const Geom &g, int nr, int n_rhs, const hrw_solve_
     pl.coef_k2 = (double *)ar.take(sizeof(double) * MAX_RHS);
     pl.coef_mk = (double *)ar.take(sizeof(double) * MAX_RHS);
     pl.scal = (double *)ar.take(sizeof(double) * 4 * MAX_RHS);
-    pl.active = (int *)ar.take(sizeof(int) * MAX_RHS);
+    pl.active = (int *)ar.take(sizeof(int) * 3 * MAX_RHS);  // active, due, advanced flags
     pl.pstride = partial_stride(g, nr);
     pl.pa = (double *)ar.take(sizeof(double) * (size_t)pl.pstride * n_rhs);
     pl.pb = (double *)ar.take(sizeof(double) * (size_t)pl.pstride * n_rhs);
@@ -544,7 +544,7 @@ static int apply_A(CgRun &R, const Fld &x, const Fld &s, const Fld &t, const Fld
 }
 
 // one CG iteration on the inner fields
-static int cg_iteration(CgRun &R, int max_iter, int *host_active)
+static int cg_iteration(CgRun &R, int max_iter, ReliableSchedule sched, int *host_active)
 {
     CgPlan &P = *R.pl;
     const int dt = P.dl;
@@ -627,12 +627,13 @@ static int cg_iteration(CgRun &R, int max_iter, int *host_active)
         b.pstride = P.pstride;
         if ((rc = run_hop(R.g, R.ph, b, R.st))) return rc;
     }
-    HRW_HIP(launch_cg_beta(P.cs, P.pb, P.pstride, R.nparts_hop(), R.n_rhs, max_iter, P.beta, P.active,
-                           host_active, R.st));
+    int *advanced = P.active + 2 * MAX_RHS;
+    HRW_HIP(launch_cg_beta(P.cs, P.pb, P.pstride, R.nparts_hop(), R.n_rhs, max_iter, sched, P.beta, P.active,
+                           advanced, host_active, R.st));
     int err = HRW_OK;
     dispatch_dtype(dt, [&](auto sv) {
         typedef decltype(sv) S;
-        if (launch_xpay<S>((const cpx<S> *)P.r.h(0), (cpx<S> *)P.p.h(0), P.beta, P.active, R.elems(), P.RS,
+        if (launch_xpay<S>((const cpx<S> *)P.r.h(0), (cpx<S> *)P.p.h(0), P.beta, advanced, R.elems(), P.RS,
                            R.n_rhs, R.st) != hipSuccess)
             err = fail(HRW_EDEVICE, "xpay launch failed");
     });
@@ -659,10 +660,21 @@ __global__ void flags_to_host_kernel(const int *active, int *host, int n)
     if ((int)threadIdx.x < n) host[threadIdx.x] = active[threadIdx.x];
 }
 
-// reliable-update decision: like the true-residual check, but a running rhs
-// keeps its search direction and only its residual norm is replaced
+// due[rhs] = 1 for the systems a reliable pass must treat (all of them when `all`)
+__global__ void mark_due_kernel(const CgState *cs, int *due, int n, int all)
+{
+    const int rhs = threadIdx.x;
+    if (rhs < n) due[rhs] = all || cs[rhs].status == CG_UPDATE_DUE || cs[rhs].status == CG_RECURSIVE_DONE;
+}
+
+// Decision after an FP64 true residual: a due system that meets the
+// tolerance is done; otherwise it resumes from the true residual (keeping
+// its search direction in mixed precision; plain CG restarts with p = r).
+// `record_all` also stores the true residual of systems that are not due
+// (the final pass, after every system was folded).
 __global__ void __launch_bounds__(WG) cg_reliable_kernel(CgState *cs, const double *partial, int pstride,
-                                                          int nparts, int *active_out, int max_restarts)
+                                                          int nparts, const int *due, int *active_out,
+                                                          int max_restarts, int record_all, double scale_numer)
 {
     __shared__ double sh[WG / 64];
     const int rhs = blockIdx.x;
@@ -675,9 +687,12 @@ __global__ void __launch_bounds__(WG) cg_reliable_kernel(CgState *cs, const doub
         double rt = 0;
         for (int k = 0; k < WG / 64; ++k) rt += sh[k];
         CgState c = cs[rhs];
-        c.rr_true = rt;
-        if (c.status == CG_RUNNING || c.status == CG_RECURSIVE_DONE) {
+        c.scale_prev = c.scale;
+        if (record_all) c.rr_true = rt;
+        if (due[rhs] && (c.status == CG_UPDATE_DUE || c.status == CG_RECURSIVE_DONE)) {
+            c.rr_true = rt;
             c.updates += 1;
+            c.since = 0;
             if (rt <= c.tol2) {
                 c.status = CG_DONE;
                 c.active = 0;
@@ -692,7 +707,9 @@ __global__ void __launch_bounds__(WG) cg_reliable_kernel(CgState *cs, const doub
                 } else {
                     c.status = CG_RUNNING;
                     c.active = 1;
-                    c.rr = rt;
+                    c.scale = scale_numer > 0 ? sqrt(scale_numer / rt) : 1.0;
+                    c.rr = rt * c.scale * c.scale;
+                    c.rr_last = c.rr;
                 }
             }
         }
@@ -701,11 +718,18 @@ __global__ void __launch_bounds__(WG) cg_reliable_kernel(CgState *cs, const doub
     }
 }
 
-static int any_active(const int *host, int n)
+// host flags: 1 running, 2 waiting for a reliable update, 0 otherwise
+static bool any_running(const int *host, int n)
 {
-    int a = 0;
-    for (int j = 0; j < n; ++j) a |= host[j];
-    return a;
+    for (int j = 0; j < n; ++j)
+        if (host[j] == 1) return true;
+    return false;
+}
+static bool any_due(const int *host, int n)
+{
+    for (int j = 0; j < n; ++j)
+        if (host[j] == 2) return true;
+    return false;
 }
 
 int cg_solve(const hrw_gauge *g, const hrw_solve_params *prm, int n_rhs, const double *kappa,
@@ -778,11 +802,13 @@ int cg_solve(const hrw_gauge *g, const hrw_solve_params *prm, int n_rhs, const d
 
     // ---- initial state: r = p = b (x = 0), |b|^2
     HRW_HIP(launch_norm2<double>((const cpx<double> *)P.b.h(0), E, P.RS, n_rhs, P.pa, P.pstride, nbv, st));
-    HRW_HIP(launch_cg_init(P.cs, P.pa, P.pstride, nbv, n_rhs, prm->tol, P.active, st));
+    // FP16 storage keeps each system at RMS ~1 (its range ends near 6e-8); CG
+    // is linear, so the inner recursion runs on scaled vectors
+    const double scale_numer = P.dl == 3 ? 2.0 * (double)E : 0.0;
+    HRW_HIP(launch_cg_init(P.cs, P.pa, P.pstride, nbv, n_rhs, prm->tol, scale_numer, P.active, st));
     const size_t felems = P.RS * n_rhs;  // complex elements of one field, all rhs
     if (P.mixed) {
-        HRW_HIP(launch_convert(0, P.b.base, P.dl, P.r.base, felems, st));
-        HRW_HIP(launch_convert(0, P.b.base, P.dl, P.p.base, felems, st));
+        HRW_HIP(launch_seed(P.dl, (const double *)P.b.base, P.r.base, P.p.base, P.cs, E, P.RS, n_rhs, st));
     } else {
         HRW_HIP(launch_copy<double>((const cpx<double> *)P.b.base, (cpx<double> *)P.r.base, felems, st));
         HRW_HIP(launch_copy<double>((const cpx<double> *)P.b.base, (cpx<double> *)P.p.base, felems, st));
@@ -804,54 +830,61 @@ int cg_solve(const hrw_gauge *g, const hrw_solve_params *prm, int n_rhs, const d
     for (int j = 0; j < n_rhs; ++j) hf.host[j] = 1;
 
     const int max_iter = prm->max_iter > 0 ? prm->max_iter : 1;
-    const int K = prm->reliable_every > 0 ? prm->reliable_every : 50;
+    ReliableSchedule sched;
+    sched.every = P.mixed ? (prm->reliable_every > 0 ? prm->reliable_every : 50) : 0;
+    sched.delta2 = P.mixed ? prm->reliable_delta * prm->reliable_delta : 0.0;
     const int max_restarts = 20;
-    int it_since = 0;
     long long enq = 0;
-    for (;;) {
-        // ---- iterate until nothing is active (or, mixed, K iterations passed)
-        bool stop = false;
-        while (!stop) {
-            if ((rc = cg_iteration(R, max_iter, hf.dev))) return rc;
-            HRW_HIP(hipEventRecord(guard.ev[enq % 3], st));
-            ++enq;
-            ++it_since;
-            if (enq >= 2) {
-                HRW_HIP(hipEventSynchronize(guard.ev[(enq - 2) % 3]));
-                if (!any_active(hf.host, n_rhs)) stop = true;
-            }
-            if (P.mixed && it_since >= K) stop = true;
-        }
-        HRW_HIP(hipStreamSynchronize(st));
-        // ---- check in FP64
+    // one reliable pass (or, plain CG, true-residual check) on the due systems;
+    // final = fold everything and record every system's true residual
+    auto reliable_pass = [&](bool final) -> int {
+        int rc2;
+        mark_due_kernel<<<1, 64, 0, st>>>(P.cs, P.active + MAX_RHS, n_rhs, final ? 1 : 0);
+        HRW_HIP(hipGetLastError());
+        const int *due = P.active + MAX_RHS;
         if (P.mixed) {
-            // x64 += x_lo; x_lo = 0; r64 = b - A64 x64; reseed r_lo; keep p
-            double one[MAX_RHS];
-            for (int j = 0; j < n_rhs; ++j) one[j] = 1.0;
-            if ((rc = set_device_doubles(P.scal, one, n_rhs, st))) return rc;
-            HRW_HIP(launch_axpy_mixed(P.dl, P.x.base, 0, P.x64.base, P.scal, felems, 0, 0, 1, st));
-            HRW_HIP(launch_zero(P.x.base, felems * dtype_cbytes(P.dl), st));
-            if ((rc = true_residual(R, P.x64, P.r64, P.s64, P.t64, P.u64, P.q64))) return rc;
-            cg_reliable_kernel<<<n_rhs, WG, 0, st>>>(P.cs, P.pb, P.pstride, nbv, P.active, max_restarts);
+            // x64 += x_lo; x_lo = 0; r64 = b - A64 x64; decide; p_lo += r64 - r_lo; r_lo = r64
+            // (due systems only)
+            HRW_HIP(launch_fold(P.dl, P.x.base, (double *)P.x64.base, due, P.cs, E, P.RS, n_rhs, st));
+            if ((rc2 = true_residual(R, P.x64, P.r64, P.s64, P.t64, P.u64, P.q64))) return rc2;
+            cg_reliable_kernel<<<n_rhs, WG, 0, st>>>(P.cs, P.pb, P.pstride, nbv, due, P.active, max_restarts,
+                                                     final ? 1 : 0, scale_numer);
             HRW_HIP(hipGetLastError());
-            HRW_HIP(launch_convert(0, P.r64.base, P.dl, P.r.base, felems, st));
+            HRW_HIP(launch_reseed(P.dl, (const double *)P.r64.base, P.r.base, P.p.base, due, P.cs, E, P.RS, n_rhs,
+                                  st));
         } else {
-            // the search direction is dead here: reuse p as the output of A x
-            if ((rc = true_residual(R, P.x, P.r, P.s, P.t, P.u, P.p))) return rc;
-            cg_reliable_kernel<<<n_rhs, WG, 0, st>>>(P.cs, P.pb, P.pstride, nbv, P.active, max_restarts);
+            // no system is running here, so the search direction is free to hold A x
+            if ((rc2 = true_residual(R, P.x, P.r, P.s, P.t, P.u, P.p))) return rc2;
+            cg_reliable_kernel<<<n_rhs, WG, 0, st>>>(P.cs, P.pb, P.pstride, nbv, due, P.active, max_restarts,
+                                                     final ? 1 : 0, 0.0);
             HRW_HIP(hipGetLastError());
-            // restarted rhs: p = r (beta = 0)
+            // restarted systems: p = r (beta = 0)
             double zero[MAX_RHS] = {0};
-            if ((rc = set_device_doubles(P.beta, zero, n_rhs, st))) return rc;
+            if ((rc2 = set_device_doubles(P.beta, zero, n_rhs, st))) return rc2;
             HRW_HIP(launch_xpay<double>((const cpx<double> *)P.r.h(0), (cpx<double> *)P.p.h(0), P.beta,
                                         P.active, E, P.RS, n_rhs, st));
         }
         flags_to_host_kernel<<<1, 64, 0, st>>>(P.active, hf.dev, n_rhs);
         HRW_HIP(hipGetLastError());
         HRW_HIP(hipStreamSynchronize(st));
-        it_since = 0;
-        if (!any_active(hf.host, n_rhs)) break;
+        return HRW_OK;
+    };
+    for (;;) {
+        // ---- iterate until nothing runs or some system waits for its reliable update
+        for (;;) {
+            if ((rc = cg_iteration(R, max_iter, sched, hf.dev))) return rc;
+            HRW_HIP(hipEventRecord(guard.ev[enq % 3], st));
+            ++enq;
+            if (enq >= 2) {
+                HRW_HIP(hipEventSynchronize(guard.ev[(enq - 2) % 3]));
+                if (!any_running(hf.host, n_rhs) || any_due(hf.host, n_rhs)) break;
+            }
+        }
+        HRW_HIP(hipStreamSynchronize(st));
+        if ((rc = reliable_pass(false))) return rc;
+        if (!any_running(hf.host, n_rhs)) break;
     }
+    if ((rc = reliable_pass(true))) return rc;
 
     // ---- solution out
     const Fld &X = P.mixed ? P.x64 : P.x;
@@ -908,7 +941,7 @@ int cg_solve(const hrw_gauge *g, const hrw_solve_params *prm, int n_rhs, const d
         o.reliable_updates = P.mixed ? c.updates : 0;
         o.restarts = c.restarts;
         o.true_rel_resid = c.rr0 > 0 ? sqrt(c.rr_true / c.rr0) : 0.0;
-        o.recursive_rel_resid = c.rr0 > 0 ? sqrt(c.rr / c.rr0) : 0.0;
+        o.recursive_rel_resid = c.rr0 > 0 ? sqrt(c.rr / (c.rr0 * c.scale * c.scale)) : 0.0;
         o.d_rel_resid = (P.sys == HRW_SYS_D_CGNR_EO && dres[MAX_RHS + j] > 0)
                             ? sqrt(dres[j] / dres[MAX_RHS + j]) : 0.0;
         o.seconds = secs;

@@ -159,28 +159,55 @@ struct CgState {      // per right-hand side, device
     double alpha, beta;
     double tol2;      // tol^2 * rr0
     double rr_true;   // last true |r|^2
+    double rr_last;   // |r|^2 right after the last reliable update
+    double scale;     // inner fields hold scale * (true vectors); 1 unless FP16 storage
+    double scale_prev;// scale before the last reliable decision (used by the reseed)
     int status;       // see CgStatus
     int iters;
     int active;       // 1 while the recursion advances
     int restarts;     // re-activations after the recursion had converged
     int updates;      // FP64 true-residual evaluations (reliable updates)
-    int pad_;
+    int since;        // iterations since the last reliable update
 };
 
 enum CgStatus { CG_RUNNING = 0, CG_RECURSIVE_DONE = 1, CG_BREAKDOWN = 2, CG_DONE = 3,
-                CG_MAXITER = 4 };
+                CG_MAXITER = 4, CG_UPDATE_DUE = 5 };
+
+// Reliable-update schedule of one right-hand side: due after `every`
+// iterations of its own (0 = never) or once |r| fell below delta |r_last|
+// (delta = 0: off).  Each system keeps its own schedule, so its arithmetic
+// does not depend on which other systems share the batch.
+struct ReliableSchedule {
+    int every;
+    double delta2;
+};
 
 // reduce partials of pap, set alpha (breakdown check)
 hipError_t launch_cg_alpha(CgState *st_, const double *partial, int pstride, int nparts,
                            int n_rhs, double *alpha_out, hipStream_t st);
 // reduce partials of |r|^2, set beta, advance iteration, recursive convergence;
 // host_active (host-mapped, may be null) receives each rhs' active flag
+// advanced_out[rhs] = 1 for the systems that took this iteration's step: they
+// still complete it with p = r + beta p, even when this kernel stops them.
 hipError_t launch_cg_beta(CgState *st_, const double *partial, int pstride, int nparts,
-                          int n_rhs, int max_iter, double *beta_out, int *active_out,
-                          int *host_active, hipStream_t st);
-// initialise: rr = rr0 = sum(partials), status running
+                          int n_rhs, int max_iter, ReliableSchedule sched, double *beta_out,
+                          int *active_out, int *advanced_out, int *host_active, hipStream_t st);
+// mixed precision, per rhs with due[rhs] != 0: x64 += x_lo / scale, x_lo = 0
+hipError_t launch_fold(int dt_lo, void *x_lo, double *x64, const int *due, const CgState *cs,
+                       size_t elems, size_t rstride, int n_rhs, hipStream_t st);
+// mixed precision, per rhs with due[rhs] != 0 (true vectors: v = v_lo / scale):
+// p += r64 - r, then r = r64, both stored in the new scale.  Shifting p by the
+// residual correction keeps p = r + beta p_prev valid for the replaced residual.
+hipError_t launch_reseed(int dt_lo, const double *r64, void *r_lo, void *p_lo, const int *due,
+                         const CgState *cs, size_t elems, size_t rstride, int n_rhs, hipStream_t st);
+// initialise: rr0 = sum(partials), status running; scale_numer > 0 picks
+// scale = sqrt(scale_numer / rr0) (inner fields of RMS ~1), else scale = 1;
+// the recursion's rr is kept in scaled units
 hipError_t launch_cg_init(CgState *st_, const double *partial, int pstride, int nparts,
-                          int n_rhs, double tol, int *active_out, hipStream_t st);
+                          int n_rhs, double tol, double scale_numer, int *active_out, hipStream_t st);
+// mixed precision start: r_lo = p_lo = round(scale * b)
+hipError_t launch_seed(int dt_lo, const double *b64, void *r_lo, void *p_lo, const CgState *cs,
+                       size_t elems, size_t rstride, int n_rhs, hipStream_t st);
 // plain sum of partials into out[rhs]
 hipError_t launch_sum_partials(const double *partial, int pstride, int nparts, int n_rhs,
                                double *out, hipStream_t st);

@@ -242,10 +242,10 @@ def deo_apply(g: Gauge, kappa, psi_e: torch.Tensor, theta=(0, 0, 0, 0), dtype="f
 
 
 def solve_params(tol=1e-10, max_iter=10000, system="ddag_d_eo", inner_dtype="f64", reliable_every=50,
-                 theta=(0, 0, 0, 0)) -> SolveParams:
+                 theta=(0, 0, 0, 0), reliable_delta=0.0) -> SolveParams:
     p = SolveParams()
     p.tol, p.max_iter, p.system = tol, max_iter, SYSTEMS[system]
-    p.inner_dtype, p.reliable_every, p.reliable_delta = DTYPES[inner_dtype], reliable_every, 0.0
+    p.inner_dtype, p.reliable_every, p.reliable_delta = DTYPES[inner_dtype], reliable_every, float(reliable_delta)
     for k in range(4):
         p.theta[k] = float(theta[k])
     return p

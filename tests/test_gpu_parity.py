@@ -244,3 +244,75 @@ def test_cg_edge_cases():
     x, res, rc = hrw.cg_solve(g, to_dev(mix), [0.12, 0.12], prm)
     assert rc == hrw.EBREAKDOWN and res[0]["status"] == 0 and res[1]["status"] == hrw.EBREAKDOWN
     assert _oracle_resid(dims, ur, 0.12, x[0].cpu().numpy(), b, "ddag_d_eo") <= 1.01e-10
+
+
+# ------------------------------------------------------------------ mixed precision (reliable updates)
+
+MIXED_CASES = [(2, "adj", (8, 8, 8, 8)), (4, "asym", (4, 4, 4, 8)), (3, "fund", (8, 8, 8, 8))]
+
+
+@pytest.mark.parametrize("inner", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("nc,rep,dims", MIXED_CASES, ids=lambda c: str(c))
+def test_mixed_cg_reaches_fp64_tolerance(inner, nc, rep, dims):
+    """Inner CG in FP32 or 16-bit storage, FP64 reliable updates every 50 iterations:
+    the FP64 true residual recomputed by the oracle meets 1e-10 and the error
+    against the FP64 oracle solution stays within cond(A) * tol."""
+    kappa = 0.135
+    uf, ur, g = setup(dims, nc, rep, "thermal", seed=71, dtypes=("f64", inner))
+    b = orc.split_eo(dims, fx.gaussian_spinor(dims, g.nr, seed=72))[0]
+    prm = hrw.solve_params(tol=1e-10, max_iter=20000, system="ddag_d_eo", inner_dtype=inner,
+                           reliable_every=50, theta=THETA_AP)
+    x, res, rc = hrw.cg_solve(g, to_dev(b), kappa, prm)
+    x = x.cpu().numpy()
+    assert rc == 0, res
+    assert res[0]["true_rel_resid"] <= 1e-10 and res[0]["reliable_updates"] >= 1
+    assert _oracle_resid(dims, ur, kappa, x, b, "ddag_d_eo") <= 1.01e-10
+    xo, info = orc.cg(dims, ur, kappa, b, THETA_AP, orc.SYSTEM_EO, tol=1e-12)
+    lo, hi = orc.lanczos_extremes(info["alpha"], info["beta"])
+    assert rel(x, xo) <= (hi / lo) * 1e-10
+
+
+@pytest.mark.parametrize("system", ["ddag_d_full", "d_cgnr_eo"])
+def test_mixed_cg_other_systems(system):
+    dims, kappa = (4, 4, 4, 8), 0.135
+    uf, ur, g = setup(dims, 3, "fund", "thermal", seed=73, dtypes=("f64", "f32"))
+    b = fx.gaussian_spinor(dims, 3, seed=74)
+    prm = hrw.solve_params(tol=1e-10, max_iter=5000, system=system, inner_dtype="f32", theta=THETA_AP)
+    x, res, rc = hrw.cg_solve(g, to_dev(b), kappa, prm)
+    x = x.cpu().numpy()
+    assert rc == 0, res
+    if system == "ddag_d_full":
+        assert _oracle_resid(dims, ur, kappa, x, b, system) <= 1.01e-10
+    else:
+        xo, _ = orc.solve_d_eo(dims, ur, kappa, b, THETA_AP, tol=1e-12)
+        assert rel(x, xo) <= 1e-7
+
+
+def test_mixed_multi_rhs_bitwise_equals_single():
+    """Reliable-update schedules are per system, so a batched solve reproduces each
+    single solve bit for bit, also when the systems converge at different speeds."""
+    dims = (4, 4, 4, 8)
+    uf, ur, g = setup(dims, 2, "adj", "thermal", seed=75, dtypes=("f64", "f32"))
+    b = orc.split_eo(dims, fx.gaussian_spinor(dims, 3, seed=76, n_rhs=3))[0]
+    b[2] *= 1e-3  # a differently scaled source
+    ks = [0.12, 0.135, 0.128]
+    prm = hrw.solve_params(tol=1e-10, max_iter=5000, system="ddag_d_eo", inner_dtype="f32",
+                           reliable_every=20, theta=THETA_AP)
+    xm, resm, rc = hrw.cg_solve(g, to_dev(b), ks, prm)
+    assert rc == 0
+    xm = xm.cpu().numpy()
+    for k in range(3):
+        x1, res1, _ = hrw.cg_solve(g, to_dev(b[k]), ks[k], prm)
+        assert np.array_equal(xm[k], x1.cpu().numpy()), k
+        assert res1[0]["iters"] == resm[k]["iters"] and res1[0]["reliable_updates"] == resm[k]["reliable_updates"]
+
+
+def test_reliable_delta_trigger():
+    dims = (8, 8, 8, 8)
+    uf, ur, g = setup(dims, 3, "fund", "thermal", seed=77, dtypes=("f64", "f32"))
+    b = orc.split_eo(dims, fx.gaussian_spinor(dims, 3, seed=78))[0]
+    prm = hrw.solve_params(tol=1e-10, max_iter=5000, system="ddag_d_eo", inner_dtype="f32",
+                           reliable_every=0, reliable_delta=0.1, theta=THETA_AP)
+    x, res, rc = hrw.cg_solve(g, to_dev(b), 0.135, prm)
+    assert rc == 0 and res[0]["reliable_updates"] >= 5  # ten decades, one update per decade
+    assert _oracle_resid(dims, ur, 0.135, x.cpu().numpy(), b, "ddag_d_eo") <= 1.01e-10
