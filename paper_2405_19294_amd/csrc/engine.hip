@@ -236,7 +236,7 @@ static size_t half_elems(const Geom &g, int nr) { return spinor_elems(g, nr); }
 
 static int partial_stride(const Geom &g, int nr)
 {
-    const int a = 2 * hop_grid(g, HOP_MAX_G);
+    const int a = 2 * hop_groups(g);
     const int b = vec_grid(2 * half_elems(g, nr));
     return a > b ? a : b;
 }
@@ -487,7 +487,7 @@ struct CgRun {
     int n_rhs;
     hipStream_t st;
     bool full() const { return pl->sys == HRW_SYS_DDAG_D_FULL; }
-    int nparts_hop() const { return (full() ? 2 : 1) * hop_grid_for(g->g, g->nr, pl->dl); }
+    int nparts_hop() const { return (full() ? 2 : 1) * hop_groups(g->g); }
     size_t elems() const { return full() ? 2 * pl->H : pl->H; }  // active elements per rhs
 };
 

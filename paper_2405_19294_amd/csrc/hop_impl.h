@@ -90,16 +90,40 @@ __device__ __forceinline__ void reconstruct(const A (&gr)[2][NR], const A (&gi)[
     }
 }
 
+// Where a thread reads its links from: the packed field in HBM (streamed past
+// L2, each link is read once per launch) or a workgroup's LDS copy (the
+// multi-source kernel).  The arithmetic is the same either way.
+template <class S, int NR>
+struct GlobalLinks {
+    const cpx<S> *__restrict__ g;
+    int i;
+    __device__ __forceinline__ void load(int comp, typename acc_of<S>::type &re,
+                                         typename acc_of<S>::type &im) const
+    {
+        load_c_nt(g + lay(i, comp, 8 * NR * NR), re, im);
+    }
+};
+
+template <class S>
+struct LdsLinks {
+    const cpx<S> *l;  // [comp][MR_SITES]
+    int s;
+    __device__ __forceinline__ void load(int comp, typename acc_of<S>::type &re,
+                                         typename acc_of<S>::type &im) const
+    {
+        load_c(l + comp * MR_SITES + s, re, im);
+    }
+};
+
 // one direction (forward or backward) of one mu, for colour rows r0 .. r0+RS-1
-template <int MU, int DIR, bool DAG, int NR, int RS, class S>
+template <int MU, int DIR, bool DAG, int NR, int RS, class S, class LS>
 __device__ __forceinline__ void hop_dir(const HopArgs<S> &a, const cpx<S> *__restrict__ in,
-                                        const cpx<S> *__restrict__ gauge, int i, int r0, const int (&x)[4],
+                                        const LS &links, int r0, const int (&x)[4],
                                         typename acc_of<S>::type (&ar)[4][RS],
                                         typename acc_of<S>::type (&ai)[4][RS])
 {
     typedef typename acc_of<S>::type A;
     constexpr int NC = 4 * NR;
-    constexpr int GC = 8 * NR * NR;
     // projector sign: forward (1 - g) for H, backward (1 + g); H^+ swaps
     constexpr int SG = (DIR == 0) ? (DAG ? 1 : -1) : (DAG ? -1 : 1);
     int y[4] = {x[0], x[1], x[2], x[3]};
@@ -124,7 +148,7 @@ __device__ __forceinline__ void hop_dir(const HopArgs<S> &a, const cpx<S> *__res
 #pragma unroll
     for (int r = 0; r < RS; ++r)
 #pragma unroll
-        for (int c = 0; c < NR; ++c) load_c_nt(gauge + lay(i, DD * NR * NR + (r0 + r) * NR + c, GC), ur[r][c], ui[r][c]);
+        for (int c = 0; c < NR; ++c) links.load(DD * NR * NR + (r0 + r) * NR + c, ur[r][c], ui[r][c]);
     A hr[2][NR], hi[2][NR];
     project<MU, SG>(pr, pi, hr, hi);
     if (wrap) {
@@ -188,11 +212,109 @@ __device__ __forceinline__ int tile_remap(int L, int n, int ts, int c)
     return t * ts + ch * c + w;
 }
 
-template <int NR, int RS, class S, bool DAG, int EPI>
-__global__ void __launch_bounds__(WG) hop_kernel(const HopArgs<S> a)
+// FP64 sum over the 16*G lanes (16 sites x G row threads) of one partial-sum
+// group, in a fixed tree; the result is valid in the group's first lane.
+// Groups wider than a wavefront (G = 8) combine their two halves through LDS.
+template <int G>
+__device__ __forceinline__ double group_sum(double v, double *sh)
+{
+    constexpr int SEG = PG_SITES * G;
+    constexpr int W = SEG < 64 ? SEG : 64;
+    for (int off = W / 2; off > 0; off >>= 1) v += __shfl_down(v, off, W);
+    if (SEG > 64) {
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) sh[w] = v;
+        __syncthreads();
+        if ((threadIdx.x & (SEG - 1)) == 0)
+            for (int k = 1; k < SEG / 64; ++k) v += sh[w + k];
+        __syncthreads();
+    }
+    return v;
+}
+
+// the per-site body shared by both kernels: hop of site i for one source,
+// then the epilogue; returns this thread's |.|^2 contribution
+template <int NR, int RS, class S, bool DAG, int EPI, class LS>
+__device__ __forceinline__ double site_hop(const HopArgs<S> &a, int parity, int i, int r0, int rhs,
+                                           const LS &links)
 {
     typedef typename acc_of<S>::type A;
     constexpr int NC = 4 * NR;
+    const size_t roff = (size_t)rhs * a.rstride;
+    double nrm = 0;
+    int x[4];
+    eo_coords(a.g, parity, i, x);
+    const cpx<S> *__restrict__ in = a.in[1 - parity] + roff;
+    A ar[4][RS], ai[4][RS];
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int c = 0; c < RS; ++c) ar[sp][c] = ai[sp][c] = 0;
+    hop_dir<0, 0, DAG, NR, RS>(a, in, links, r0, x, ar, ai);
+    hop_dir<0, 1, DAG, NR, RS>(a, in, links, r0, x, ar, ai);
+    hop_dir<1, 0, DAG, NR, RS>(a, in, links, r0, x, ar, ai);
+    hop_dir<1, 1, DAG, NR, RS>(a, in, links, r0, x, ar, ai);
+    hop_dir<2, 0, DAG, NR, RS>(a, in, links, r0, x, ar, ai);
+    hop_dir<2, 1, DAG, NR, RS>(a, in, links, r0, x, ar, ai);
+    hop_dir<3, 0, DAG, NR, RS>(a, in, links, r0, x, ar, ai);
+    hop_dir<3, 1, DAG, NR, RS>(a, in, links, r0, x, ar, ai);
+    if (EPI == EPI_PLAIN) {
+        cpx<S> *out = a.out[parity] + roff;
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int c = 0; c < RS; ++c) store_c_nt(out + lay(i, sp * NR + r0 + c, NC), ar[sp][c], ai[sp][c]);
+    } else {
+        const A cf = (A)a.coef[rhs];
+        const cpx<S> *self = a.self[parity] + roff;
+        if (EPI == EPI_AXPY) {
+            cpx<S> *out = a.out[parity] + roff;
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                for (int c = 0; c < RS; ++c) {
+                    const size_t o = lay(i, sp * NR + r0 + c, NC);
+                    A sr, si;
+                    load_c_nt(self + o, sr, si);
+                    const A vr = sr - cf * ar[sp][c], vi = si - cf * ai[sp][c];
+                    store_c_nt(out + o, vr, vi);
+                    nrm += (double)vr * (double)vr + (double)vi * (double)vi;
+                }
+        } else {  // EPI_CG
+            cpx<S> *r = a.r[parity] + roff;
+            cpx<S> *xx = a.x[parity] + roff;
+            const cpx<S> *p = a.p[parity] + roff;
+            const bool act = a.active[rhs] != 0;
+            const A al = (A)a.alpha[rhs];
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                for (int c = 0; c < RS; ++c) {
+                    const size_t o = lay(i, sp * NR + r0 + c, NC);
+                    A sr, si, rr_, ri, xr, xi, pr_, pi_;
+                    load_c_nt(self + o, sr, si);
+                    load_c_nt(r + o, rr_, ri);
+                    if (act) {
+                        const A qr = sr - cf * ar[sp][c], qi = si - cf * ai[sp][c];
+                        load_c_nt(xx + o, xr, xi);
+                        load_c_nt(p + o, pr_, pi_);
+                        rr_ -= al * qr;
+                        ri -= al * qi;
+                        xr += al * pr_;
+                        xi += al * pi_;
+                        store_c_nt(r + o, rr_, ri);
+                        store_c_nt(xx + o, xr, xi);
+                    }
+                    nrm += (double)rr_ * (double)rr_ + (double)ri * (double)ri;
+                }
+        }
+    }
+    return nrm;
+}
+
+template <int NR, int RS, class S, bool DAG, int EPI>
+__global__ void __launch_bounds__(WG) hop_kernel(const HopArgs<S> a)
+{
     constexpr int G = NR / RS;  // threads per site, each owning RS colour rows
     __shared__ double sh[WG / 64];
     int parity = a.parity, bx = blockIdx.x;
@@ -205,93 +327,83 @@ __global__ void __launch_bounds__(WG) hop_kernel(const HopArgs<S> a)
     const int gid = bx * WG + threadIdx.x;
     const int i = gid / G;
     const int r0 = (gid - i * G) * RS;
-    const size_t roff = (size_t)rhs * a.rstride;
     double nrm = 0;
     if (i < a.g.half) {
-        int x[4];
-        eo_coords(a.g, parity, i, x);
-        const cpx<S> *__restrict__ in = a.in[1 - parity] + roff;
-        const cpx<S> *__restrict__ gauge = a.gauge[parity];
-        A ar[4][RS], ai[4][RS];
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-            for (int c = 0; c < RS; ++c) ar[sp][c] = ai[sp][c] = 0;
-        hop_dir<0, 0, DAG, NR, RS>(a, in, gauge, i, r0, x, ar, ai);
-        hop_dir<0, 1, DAG, NR, RS>(a, in, gauge, i, r0, x, ar, ai);
-        hop_dir<1, 0, DAG, NR, RS>(a, in, gauge, i, r0, x, ar, ai);
-        hop_dir<1, 1, DAG, NR, RS>(a, in, gauge, i, r0, x, ar, ai);
-        hop_dir<2, 0, DAG, NR, RS>(a, in, gauge, i, r0, x, ar, ai);
-        hop_dir<2, 1, DAG, NR, RS>(a, in, gauge, i, r0, x, ar, ai);
-        hop_dir<3, 0, DAG, NR, RS>(a, in, gauge, i, r0, x, ar, ai);
-        hop_dir<3, 1, DAG, NR, RS>(a, in, gauge, i, r0, x, ar, ai);
-        if (EPI == EPI_PLAIN) {
-            cpx<S> *out = a.out[parity] + roff;
-#pragma unroll
-            for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-                for (int c = 0; c < RS; ++c) store_c_nt(out + lay(i, sp * NR + r0 + c, NC), ar[sp][c], ai[sp][c]);
-        } else {
-            const A cf = (A)a.coef[rhs];
-            const cpx<S> *self = a.self[parity] + roff;
-            if (EPI == EPI_AXPY) {
-                cpx<S> *out = a.out[parity] + roff;
-#pragma unroll
-                for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-                    for (int c = 0; c < RS; ++c) {
-                        const size_t o = lay(i, sp * NR + r0 + c, NC);
-                        A sr, si;
-                        load_c_nt(self + o, sr, si);
-                        const A vr = sr - cf * ar[sp][c], vi = si - cf * ai[sp][c];
-                        store_c_nt(out + o, vr, vi);
-                        nrm += (double)vr * (double)vr + (double)vi * (double)vi;
-                    }
-            } else {  // EPI_CG
-                cpx<S> *r = a.r[parity] + roff;
-                cpx<S> *xx = a.x[parity] + roff;
-                const cpx<S> *p = a.p[parity] + roff;
-                const bool act = a.active[rhs] != 0;
-                const A al = (A)a.alpha[rhs];
-#pragma unroll
-                for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-                    for (int c = 0; c < RS; ++c) {
-                        const size_t o = lay(i, sp * NR + r0 + c, NC);
-                        A sr, si, rr_, ri, xr, xi, pr_, pi_;
-                        load_c_nt(self + o, sr, si);
-                        load_c_nt(r + o, rr_, ri);
-                        if (act) {
-                            const A qr = sr - cf * ar[sp][c], qi = si - cf * ai[sp][c];
-                            load_c_nt(xx + o, xr, xi);
-                            load_c_nt(p + o, pr_, pi_);
-                            rr_ -= al * qr;
-                            ri -= al * qi;
-                            xr += al * pr_;
-                            xi += al * pi_;
-                            store_c_nt(r + o, rr_, ri);
-                            store_c_nt(xx + o, xr, xi);
-                        }
-                        nrm += (double)rr_ * (double)rr_ + (double)ri * (double)ri;
-                    }
-            }
-        }
+        GlobalLinks<S, NR> links{a.gauge[parity], i};
+        nrm = site_hop<NR, RS, S, DAG, EPI>(a, parity, i, r0, rhs, links);
     }
     if (EPI != EPI_PLAIN && a.partial) {
-        const double t = wave_block_sum(nrm, sh);
-        if (threadIdx.x == 0) a.partial[(size_t)rhs * a.pstride + blockIdx.x] = t;
+        const double t = group_sum<G>(nrm, sh);
+        const int grp = i / PG_SITES;
+        if ((threadIdx.x & (PG_SITES * G - 1)) == 0 && grp < a.ngroups)
+            a.partial[(size_t)rhs * a.pstride + (a.parity < 0 ? parity * a.ngroups : 0) + grp] = t;
+    }
+}
+
+// Multi-source kernel: a workgroup owns MR_SITES sites and every source.  It
+// copies the sites' links (all 8 directions) into LDS once, then its threads
+// run the per-site hop for RT sources at a time, reading links from LDS: each
+// link crosses HBM once per launch however many sources there are.
+template <int NR, int RS, class S, bool DAG, int EPI>
+__global__ void __launch_bounds__(WG) hop_mrhs_kernel(const HopArgs<S> a)
+{
+    constexpr int G = NR / RS;
+    constexpr int GC = 8 * NR * NR;
+    constexpr int RT = WG / (MR_SITES * G);  // sources in flight per workgroup
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<S> *lk = (cpx<S> *)smem_raw;
+    __shared__ double sh[WG / 64];
+    int parity = a.parity, bx = blockIdx.x;
+    if (parity < 0) {
+        parity = bx >= a.grid_half;
+        if (parity) bx -= a.grid_half;
+    }
+    bx = tile_remap(xcd_remap(bx, a.grid_half), a.grid_half, a.tile_ts, a.tile_c);
+    const int i0 = bx * MR_SITES;
+    const cpx<S> *__restrict__ gauge = a.gauge[parity];
+    for (int e = threadIdx.x; e < GC * MR_SITES; e += WG) {
+        const int comp = e / MR_SITES, s = e - comp * MR_SITES;
+        const int i = i0 + s;
+        cpx<S> v;
+        if (i < a.g.half) {
+            typename acc_of<S>::type re, im;
+            load_c_nt(gauge + lay(i, comp, GC), re, im);
+            v.re = conv<S>::from_acc(re);
+            v.im = conv<S>::from_acc(im);
+        } else {
+            v.re = conv<S>::from_acc(0);
+            v.im = conv<S>::from_acc(0);
+        }
+        lk[e] = v;
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    const int rg = t % G;
+    const int s = (t / G) % MR_SITES;
+    const int jl = t / (MR_SITES * G);
+    const int i = i0 + s;
+    LdsLinks<S> links{lk, s};
+    for (int j0 = 0; j0 < a.n_rhs; j0 += RT) {
+        const int rhs = j0 + jl;
+        double nrm = 0;
+        if (i < a.g.half && rhs < a.n_rhs) nrm = site_hop<NR, RS, S, DAG, EPI>(a, parity, i, rg * RS, rhs, links);
+        if (EPI != EPI_PLAIN && a.partial) {
+            const double tt = group_sum<G>(nrm, sh);
+            if ((t & (PG_SITES * G - 1)) == 0 && rhs < a.n_rhs)
+                a.partial[(size_t)rhs * a.pstride + (a.parity < 0 ? parity * a.ngroups : 0) + bx] = tt;
+        }
     }
 }
 
 // Tiling of the work order (see tile_remap); disabled unless every time slice
 // holds a whole number of workgroups.
-inline void hop_tiling(const Geom &g, int tps, int *ts, int *c)
+inline void hop_tiling(const Geom &g, int sites_per_wg, int *ts, int *c)
 {
     *ts = 0;
     *c = 0;
-    const long long per_slice = (long long)g.half / g.d[0] * tps;  // threads per time slice
-    if ((long long)g.half % g.d[0] || per_slice % WG) return;
-    const int n = (int)per_slice / WG;
+    const long long per_slice = (long long)g.half / g.d[0];  // sites per time slice
+    if ((long long)g.half % g.d[0] || per_slice % sites_per_wg) return;
+    const int n = (int)(per_slice / sites_per_wg);
     if (n < 2) return;
     int best = 1;
     for (int k = 1; k <= 16 && k <= n; ++k)
@@ -303,18 +415,43 @@ inline void hop_tiling(const Geom &g, int tps, int *ts, int *c)
 template <class S> constexpr int dtype_id() { return 1; }
 template <> constexpr int dtype_id<double>() { return 0; }
 
-template <int NR, int RS, class S>
-void launch_hop_rs(bool dagger, int epi, dim3 grid, const HopArgs<S> &b, hipStream_t st)
+template <int NR, int RS, class S, bool MRK>
+void launch_hop_rs(bool dagger, int epi, dim3 grid, size_t lds, const HopArgs<S> &b, hipStream_t st)
 {
+#define HRW_LAUNCH(D, E)                                                               \
+    do {                                                                               \
+        if (MRK) hop_mrhs_kernel<NR, RS, S, D, E><<<grid, WG, lds, st>>>(b);           \
+        else hop_kernel<NR, RS, S, D, E><<<grid, WG, 0, st>>>(b);                      \
+    } while (0)
     if (epi == EPI_PLAIN) {
-        if (dagger) hop_kernel<NR, RS, S, true, EPI_PLAIN><<<grid, WG, 0, st>>>(b);
-        else hop_kernel<NR, RS, S, false, EPI_PLAIN><<<grid, WG, 0, st>>>(b);
+        if (dagger) HRW_LAUNCH(true, EPI_PLAIN);
+        else HRW_LAUNCH(false, EPI_PLAIN);
     } else if (epi == EPI_AXPY) {
-        if (dagger) hop_kernel<NR, RS, S, true, EPI_AXPY><<<grid, WG, 0, st>>>(b);
-        else hop_kernel<NR, RS, S, false, EPI_AXPY><<<grid, WG, 0, st>>>(b);
+        if (dagger) HRW_LAUNCH(true, EPI_AXPY);
+        else HRW_LAUNCH(false, EPI_AXPY);
     } else {
-        hop_kernel<NR, RS, S, true, EPI_CG><<<grid, WG, 0, st>>>(b);
+        HRW_LAUNCH(true, EPI_CG);
     }
+#undef HRW_LAUNCH
+}
+
+template <int NR, int RS, class S>
+hipError_t allow_lds(size_t lds)
+{
+    // the multi-source instances may need more than the default 64 KB of LDS
+    static bool done = false;
+    if (done || lds <= 65536) return hipSuccess;
+    hipError_t e = hipSuccess;
+    auto set = [&](const void *f) {
+        if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    };
+    set((const void *)hop_mrhs_kernel<NR, RS, S, true, EPI_PLAIN>);
+    set((const void *)hop_mrhs_kernel<NR, RS, S, false, EPI_PLAIN>);
+    set((const void *)hop_mrhs_kernel<NR, RS, S, true, EPI_AXPY>);
+    set((const void *)hop_mrhs_kernel<NR, RS, S, false, EPI_AXPY>);
+    set((const void *)hop_mrhs_kernel<NR, RS, S, true, EPI_CG>);
+    done = e == hipSuccess;
+    return e;
 }
 
 template <class S>
@@ -322,16 +459,31 @@ hipError_t launch_hop_impl(int nr, bool dagger, int epi, const HopArgs<S> &a, hi
 {
     if (epi == EPI_CG && !dagger) return hipErrorInvalidValue;
     HopArgs<S> b = a;
+    hipError_t err = hipSuccess;
     bool ok = dispatch_nr(nr, [&](auto nrc) {
         constexpr int NR = decltype(nrc)::value;
         constexpr int RS = hop_rows(NR, dtype_id<S>());
-        const int gh = hop_grid(a.g, NR / RS);
-        b.grid_half = gh;
-        hop_tiling(a.g, NR / RS, &b.tile_ts, &b.tile_c);
-        dim3 grid(a.parity < 0 ? 2 * gh : gh, a.n_rhs);
-        launch_hop_rs<NR, RS, S>(dagger, epi, grid, b, st);
+        constexpr int G = NR / RS;
+        b.ngroups = hop_groups(a.g);
+        if (a.n_rhs > 1 && G * MR_SITES <= WG / 2) {
+            const int gh = b.ngroups;  // one workgroup per 16-site group
+            b.grid_half = gh;
+            hop_tiling(a.g, MR_SITES, &b.tile_ts, &b.tile_c);
+            const size_t lds = sizeof(cpx<S>) * 8 * NR * NR * MR_SITES;
+            err = allow_lds<NR, RS, S>(lds);
+            if (err != hipSuccess) return;
+            dim3 grid(a.parity < 0 ? 2 * gh : gh, 1);
+            launch_hop_rs<NR, RS, S, true>(dagger, epi, grid, lds, b, st);
+        } else {
+            const int gh = hop_grid(a.g, G);
+            b.grid_half = gh;
+            hop_tiling(a.g, WG / G, &b.tile_ts, &b.tile_c);
+            dim3 grid(a.parity < 0 ? 2 * gh : gh, a.n_rhs);
+            launch_hop_rs<NR, RS, S, false>(dagger, epi, grid, 0, b, st);
+        }
     });
     if (!ok) return hipErrorInvalidValue;
+    if (err != hipSuccess) return err;
     return hipGetLastError();
 }
 

@@ -75,7 +75,7 @@ struct HopArgs {
     int pstride;
     int tile_ts;                 // workgroups per time slice (0 = no tiling)
     int tile_c;                  // workgroups per spatial chunk of the walk
-    int pad2_;
+    int ngroups;                 // 16-site partial-sum groups per parity
 };
 
 // Launch the hopping kernel.  kc_bytes receives the algorithmic bytes.
@@ -92,6 +92,13 @@ constexpr int hop_rows(int nr, int dt)
     return dt == 0 ? (nr == 4 ? 2 : nr == 6 ? 3 : nr == 8 ? 1 : nr) : (nr == 8 ? 4 : nr == 6 ? 3 : nr);
 }
 constexpr int HOP_MAX_G = 8;  // largest threads-per-site of any instance
+constexpr int PG_SITES = 16;  // sites per FP64 partial-sum group of the hopping kernels
+constexpr int MR_SITES = 16;  // sites per workgroup of the multi-source hopping kernel
+
+// Partial sums per parity written by one hopping launch: one per 16-site
+// group and source, in the same order for any number of sources, so a
+// batched solve reduces exactly like a single one.
+inline int hop_groups(const Geom &g) { return (g.half + PG_SITES - 1) / PG_SITES; }
 
 // Blocks per parity of one hop launch (also the number of partials it writes).
 inline int hop_grid(const Geom &g, int tps) { return (int)(((long long)g.half * tps + WG - 1) / WG); }
