@@ -199,6 +199,45 @@ int hrw_cg_solve(const hrw_gauge *g, const hrw_solve_params *params, int n_rhs,
                  const double *kappa_per_rhs, const double *b, double *x, hrw_solve_result *res,
                  void *workspace, size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------- solver sessions
+ * A session is a CG solver with n_slots slots (n_slots <= 64) that share one
+ * resident gauge field, one set of parameters and one caller workspace
+ * (hrw_workspace_size with n_rhs = n_slots).  Systems are loaded into free
+ * slots and read out when finished at any step boundary, while the other
+ * slots keep iterating: this is the continuous-batching engine of the serving
+ * loop.  Each slot runs its own recurrence (own kappa, alpha, beta, reliable-
+ * update schedule and convergence test), so a system's result does not depend
+ * on what else shares the session; hrw_cg_solve is create + load + step until
+ * done + read.  A session belongs to one host thread at a time; sessions on
+ * different streams may run concurrently.  Sec. 3.3 (CG), Sec. 3.1. */
+typedef struct hrw_cg_session hrw_cg_session;
+
+/* Create a session on `stream`; the workspace must stay alive until destroy. */
+int hrw_cg_session_create(const hrw_gauge *g, const hrw_solve_params *params, int n_slots,
+                          void *workspace, size_t ws_bytes, void *stream, hrw_cg_session **out);
+
+/* Load n systems into the free slots [slot, slot + n): b is n stacked canonical
+ * device fields (even half for HRW_SYS_DDAG_D_EO, full lattice otherwise),
+ * kappa a host double[n].  Synchronous: returns when the slots are set up. */
+int hrw_cg_session_load(hrw_cg_session *s, int slot, int n, const double *kappa, const double *b);
+
+/* Advance every loaded slot by up to max_iters CG iterations (with the FP64
+ * reliable updates / true-residual checks that fall due); *running receives
+ * the number of slots still iterating.  Returns after the work is complete. */
+int hrw_cg_session_step(hrw_cg_session *s, int max_iters, int *running);
+
+/* state[n_slots]: 0 free, 1 iterating, 2 finished (ready to read). */
+int hrw_cg_session_slots(hrw_cg_session *s, int *state);
+
+/* Read the finished (or stopped) slots [slot, slot + n): FP64 true residual,
+ * odd-site reconstruction for HRW_SYS_D_CGNR_EO, solution into x (n stacked
+ * canonical device fields), results into res[n] (seconds = time since load);
+ * the slots become free.  Returns the worst status as hrw_cg_solve does. */
+int hrw_cg_session_read(hrw_cg_session *s, int slot, int n, double *x, hrw_solve_result *res);
+
+/* Destroy the host part of a session (NULL accepted); the caller frees the workspace. */
+int hrw_cg_session_destroy(hrw_cg_session *s);
+
 /* ---------------------------------------------------------------- timing
  * Optional per-kernel timing with HIP events recorded on the launch stream
  * around every hopping-kernel launch.  hrw_timing_enable(1) clears the

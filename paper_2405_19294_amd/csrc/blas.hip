@@ -321,6 +321,31 @@ hipError_t launch_seed(int dt_lo, const double *b64, void *r_lo, void *p_lo, con
     return hipGetLastError();
 }
 
+// plain CG restart of the systems a true-residual check re-activated
+// (due[rhs] && active[rhs]): r = p = r64
+__global__ void __launch_bounds__(WG) restart_kernel(const cpx<double> *__restrict__ r64, cpx<double> *__restrict__ r,
+                                                      cpx<double> *__restrict__ p, const int *due, const int *active,
+                                                      size_t n, size_t rstride)
+{
+    const int rhs = blockIdx.y;
+    if (!due[rhs] || !active[rhs]) return;
+    const size_t ro = (size_t)rhs * rstride;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+        const cpx<double> v = r64[ro + t];
+        r[ro + t] = v;
+        p[ro + t] = v;
+    }
+}
+
+hipError_t launch_restart(const double *r64, double *r, double *p, const int *due, const int *active, size_t elems,
+                          size_t rstride, int n_rhs, hipStream_t st)
+{
+    restart_kernel<<<dim3(vec_grid(elems), n_rhs), WG, 0, st>>>((const cpx<double> *)r64, (cpx<double> *)r,
+                                                                (cpx<double> *)p, due, active, elems, rstride);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ second stage + CG scalars
 
 // sum of nparts partials of one rhs, in a fixed order; valid in thread 0
@@ -459,8 +484,10 @@ __global__ void __launch_bounds__(WG) cg_beta_kernel(CgState *cs, const double *
         cs[rhs] = c;
         beta_out[rhs] = c.beta;
         active_out[rhs] = c.active;
-        // host flag: 1 running, 2 waiting for a reliable update, 0 otherwise
-        if (host_active) host_active[rhs] = c.active ? 1 : (c.status == CG_UPDATE_DUE ? 2 : 0);
+        // host flag: 1 running, 2 waiting for a reliable update or true-residual
+        // check (recursion converged), 0 otherwise
+        if (host_active)
+            host_active[rhs] = c.active ? 1 : (c.status == CG_UPDATE_DUE || c.status == CG_RECURSIVE_DONE ? 2 : 0);
     }
 }
 

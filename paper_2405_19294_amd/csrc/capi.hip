@@ -254,6 +254,56 @@ int hrw_cg_solve(const hrw_gauge *g, const hrw_solve_params *params, int n_rhs, 
     });
 }
 
+int hrw_cg_session_create(const hrw_gauge *g, const hrw_solve_params *params, int n_slots, void *workspace,
+                          size_t ws_bytes, void *stream, hrw_cg_session **out)
+{
+    return guarded([&] {
+        int rc;
+        if (!g || !out || !workspace) return fail(HRW_EINVAL, "null pointer");
+        if ((rc = check_params(params)) || (rc = check_rhs(n_slots))) return rc;
+        if (!g->blocks[0][0]) return fail(HRW_EUNSUPPORTED, "CG needs FP64 links (HRW_STORE_F64)");
+        if (!g->blocks[params->inner_dtype][0]) return fail(HRW_EUNSUPPORTED, "gauge field lacks links in the inner dtype");
+        return session_create(g, params, n_slots, workspace, ws_bytes, (hipStream_t)stream, out);
+    });
+}
+
+int hrw_cg_session_load(hrw_cg_session *s, int slot, int n, const double *kappa, const double *b)
+{
+    return guarded([&] {
+        if (!s || !kappa || !b) return fail(HRW_EINVAL, "null pointer");
+        return session_load(s, slot, n, kappa, b);
+    });
+}
+
+int hrw_cg_session_step(hrw_cg_session *s, int max_iters, int *running)
+{
+    return guarded([&] {
+        if (!s || max_iters < 1) return fail(HRW_EINVAL, "null session or max_iters < 1");
+        return session_step(s, max_iters, running);
+    });
+}
+
+int hrw_cg_session_slots(hrw_cg_session *s, int *state)
+{
+    return guarded([&] {
+        if (!s || !state) return fail(HRW_EINVAL, "null pointer");
+        return session_slot_state(s, state);
+    });
+}
+
+int hrw_cg_session_read(hrw_cg_session *s, int slot, int n, double *x, hrw_solve_result *res)
+{
+    return guarded([&] {
+        if (!s || !x || !res) return fail(HRW_EINVAL, "null pointer");
+        return session_read(s, slot, n, x, res);
+    });
+}
+
+int hrw_cg_session_destroy(hrw_cg_session *s)
+{
+    return guarded([&] { return session_destroy(s); });
+}
+
 int hrw_timing_enable(int on)
 {
     Timing &t = timing();

@@ -134,5 +134,12 @@ int deo_apply(const hrw_gauge *g, const double *kappa, const double theta[4], in
 int cg_solve(const hrw_gauge *g, const hrw_solve_params *p, int n_rhs, const double *kappa,
              const double *b, double *x, hrw_solve_result *res, void *ws, size_t ws_bytes,
              hipStream_t st);
+int session_create(const hrw_gauge *g, const hrw_solve_params *prm, int n_slots, void *ws, size_t ws_bytes,
+                   hipStream_t st, hrw_cg_session **out);
+int session_destroy(hrw_cg_session *s);
+int session_load(hrw_cg_session *s, int slot, int n, const double *kappa, const double *b);
+int session_step(hrw_cg_session *s, int max_iters, int *running);
+int session_slot_state(hrw_cg_session *s, int *state);
+int session_read(hrw_cg_session *s, int slot, int n, double *x, hrw_solve_result *res);
 
 }  // namespace hrw

@@ -442,11 +442,13 @@ static int plan_cg(Arena &ar, const Geom &g, int nr, int n_rhs, const hrw_solve_
         pl.t = mk(di, two);
         pl.u = mk(di, two);
     }
+    // FP64 true residual and operator output: scratch of the checks, so a check
+    // never touches the state of systems that are still iterating
+    pl.r64 = mk(0, two);
+    pl.q64 = mk(0, two);
     if (pl.mixed) {
         pl.x64 = mk(0, two);
-        pl.r64 = mk(0, two);
         pl.s64 = mk(0, two);
-        pl.q64 = mk(0, two);
         if (!full) {
             pl.t64 = mk(0, two);
             pl.u64 = mk(0, two);
@@ -455,7 +457,6 @@ static int plan_cg(Arena &ar, const Geom &g, int nr, int n_rhs, const hrw_solve_
     if (cgnr) {
         pl.bfull = mk(0, true);
         pl.dfull = mk(0, true);
-        if (!pl.mixed) pl.q64 = mk(0, true);
     }
     pl.cs = (CgState *)ar.take(sizeof(CgState) * MAX_RHS);
     pl.alpha = (double *)ar.take(sizeof(double) * MAX_RHS);
@@ -732,231 +733,455 @@ static bool any_due(const int *host, int n)
     return false;
 }
 
-int cg_solve(const hrw_gauge *g, const hrw_solve_params *prm, int n_rhs, const double *kappa,
-             const double *b_in, double *x_out, hrw_solve_result *res, void *ws, size_t ws_bytes,
-             hipStream_t st)
+// ------------------------------------------------------------------ sessions
+
+// A view of the plan restricted to slots [slot, slot + n): every field base and
+// per-system array is offset, so the routines above run on that range alone.
+static CgPlan plan_view(const CgPlan &P, int slot)
 {
-    const auto t0 = std::chrono::steady_clock::now();
+    CgPlan v = P;
+    auto off = [&](Fld &f) {
+        if (f.base) f.base += (size_t)slot * P.RS * dtype_cbytes(f.dt);
+    };
+    for (Fld *f : {&v.x, &v.r, &v.p, &v.s, &v.t, &v.u, &v.b, &v.x64, &v.r64, &v.s64, &v.t64, &v.u64, &v.q64,
+                   &v.bfull, &v.dfull})
+        off(*f);
+    v.cs += slot;
+    v.alpha += slot;
+    v.beta += slot;
+    v.coef_k += slot;
+    v.coef_k2 += slot;
+    v.coef_mk += slot;
+    v.scal += slot;
+    v.active += slot;
+    v.pa += (size_t)slot * P.pstride;
+    v.pb += (size_t)slot * P.pstride;
+    return v;
+}
+
+__global__ void mark_range_kernel(int *due, int n, int lo, int hi)
+{
+    const int j = threadIdx.x;
+    if (j < n) due[j] = j >= lo && j < hi;
+}
+
+// a free slot: inactive, never due, excluded from the running count
+__global__ void free_slots_kernel(CgState *cs, int *active, int n)
+{
+    const int j = threadIdx.x;
+    if (j < n) {
+        CgState c;
+        memset(&c, 0, sizeof c);
+        c.status = CG_DONE;
+        c.scale = 1.0;
+        c.scale_prev = 1.0;
+        cs[j] = c;
+        active[j] = 0;
+    }
+}
+
+}  // namespace hrw
+
+struct hrw_cg_session {
+    const hrw_gauge *g;
+    hrw_solve_params prm;
+    int n_slots;
+    hipStream_t st;
+    hrw::CgPlan P;
+    hrw::Phases ph;
+    hrw::HostFlags hf;
+    hipEvent_t ev[3];
+    long long enq;
+    hrw::ReliableSchedule sched;
+    double scale_numer;
+    size_t E;
+    int nbv;
+    int used[hrw::MAX_RHS];          // 1 while a slot holds a request
+    double kappa[hrw::MAX_RHS];
+    hrw::CgState host_state[hrw::MAX_RHS];
+    std::chrono::steady_clock::time_point t_load[hrw::MAX_RHS];
+};
+
+namespace hrw {
+
+static int hi_used(const hrw_cg_session *s)
+{
+    int h = 0;
+    for (int j = 0; j < s->n_slots; ++j)
+        if (s->used[j]) h = j + 1;
+    return h;
+}
+
+static CgRun run_of(hrw_cg_session *s, CgPlan &P, int n)
+{
+    return CgRun{s->g, &P, s->ph, n, s->st};
+}
+
+int session_create(const hrw_gauge *g, const hrw_solve_params *prm, int n_slots, void *ws, size_t ws_bytes,
+                   hipStream_t st, hrw_cg_session **out)
+{
     Arena ar(ws, ws_bytes);
     CgPlan P;
-    plan_cg(ar, g->g, g->nr, n_rhs, prm, P);
+    plan_cg(ar, g->g, g->nr, n_slots, prm, P);
     int rc = check_ws(ar, ws_bytes);
     if (rc) return rc;
     if (!g->blocks[P.dl][0] || !g->blocks[0][0])
         return fail(HRW_EUNSUPPORTED, "gauge field lacks FP64 links or links in the inner dtype");
-    // all workspace fields start at zero: padding lanes stay finite and x starts at 0
-    HRW_HIP(launch_zero(ar.base, ar.off, st));
-    CgRun R{g, &P, make_phases(prm->theta), n_rhs, st};
-    const size_t H = P.H;
+    hrw_cg_session *s = new hrw_cg_session;
+    s->g = g;
+    s->prm = *prm;
+    s->n_slots = n_slots;
+    s->st = st;
+    s->P = P;
+    s->ph = make_phases(prm->theta);
+    s->enq = 0;
+    for (auto &e : s->ev) e = nullptr;
+    s->hf = HostFlags();
+    s->sched.every = P.mixed ? (prm->reliable_every > 0 ? prm->reliable_every : 50) : 0;
+    s->sched.delta2 = P.mixed ? prm->reliable_delta * prm->reliable_delta : 0.0;
+    CgRun R = run_of(s, s->P, n_slots);
+    s->E = R.elems();
+    s->nbv = vec_grid(s->E);
+    // FP16 storage keeps each system at RMS ~1 (its range ends near 6e-8); CG is
+    // linear, so the inner recursion runs on scaled vectors
+    s->scale_numer = P.dl == 3 ? 2.0 * (double)s->E : 0.0;
+    for (int j = 0; j < MAX_RHS; ++j) {
+        s->used[j] = 0;
+        s->kappa[j] = 0;
+        memset(&s->host_state[j], 0, sizeof(CgState));
+    }
+    auto cleanup = [&](int code) {
+        for (auto &e : s->ev)
+            if (e) (void)hipEventDestroy(e);
+        host_flags_release(&s->hf);
+        delete s;
+        return code;
+    };
+    if ((rc = host_flags_acquire(&s->hf))) return cleanup(rc);
+    for (auto &e : s->ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return cleanup(fail(HRW_EDEVICE, "event creation failed"));
+    // all fields start at zero: padding lanes stay finite, x starts at 0
+    if (launch_zero(ar.base, ar.off, st) != hipSuccess) return cleanup(fail(HRW_EDEVICE, "workspace clear failed"));
+    free_slots_kernel<<<1, 64, 0, st>>>(P.cs, P.active, n_slots);
+    if (hipGetLastError() != hipSuccess) return cleanup(fail(HRW_EDEVICE, "slot init failed"));
+    for (int j = 0; j < n_slots; ++j) s->hf.host[j] = 0;
+    *out = s;
+    return HRW_OK;
+}
+
+int session_destroy(hrw_cg_session *s)
+{
+    if (!s) return HRW_OK;
+    (void)hipStreamSynchronize(s->st);
+    for (auto &e : s->ev)
+        if (e) (void)hipEventDestroy(e);
+    host_flags_release(&s->hf);
+    delete s;
+    return HRW_OK;
+}
+
+// Load n systems (stacked canonical sources b, one kappa each) into slots
+// [slot, slot + n): pack, Schur prologue (CGNR), |b|^2, state and r = p = b.
+int session_load(hrw_cg_session *s, int slot, int n, const double *kappa, const double *b_in)
+{
+    if (slot < 0 || n < 1 || slot + n > s->n_slots) return fail(HRW_EINVAL, "slot range outside the session");
+    for (int j = slot; j < slot + n; ++j)
+        if (s->used[j]) return fail(HRW_EINVAL, "slot %d is in use", j);
+    const hrw_gauge *g = s->g;
+    const hipStream_t st = s->st;
+    CgPlan V = plan_view(s->P, slot);
+    CgRun R = run_of(s, V, n);
     const int nr = g->nr;
+    int rc;
     double kv[MAX_RHS], k2[MAX_RHS], mk[MAX_RHS];
-    for (int j = 0; j < n_rhs; ++j) {
+    for (int j = 0; j < n; ++j) {
         kv[j] = kappa[j];
         k2[j] = kappa[j] * kappa[j];
         mk[j] = -kappa[j];
+        s->kappa[slot + j] = kappa[j];
     }
-    if ((rc = set_device_doubles(P.coef_k, kv, n_rhs, st))) return rc;
-    if ((rc = set_device_doubles(P.coef_k2, k2, n_rhs, st))) return rc;
-    if ((rc = set_device_doubles(P.coef_mk, mk, n_rhs, st))) return rc;
-
-    // ---- source
-    if (P.sys == HRW_SYS_DDAG_D_EO) {
-        HRW_HIP(launch_pack_spinor(0, nr, g->g, false, 0, n_rhs, b_in, P.b.h(0), nullptr, P.RS, st));
-    } else if (P.sys == HRW_SYS_DDAG_D_FULL) {
-        HRW_HIP(launch_pack_spinor(0, nr, g->g, true, 0, n_rhs, b_in, P.b.h(0), P.b.h(1), P.RS, st));
+    if ((rc = set_device_doubles(V.coef_k, kv, n, st))) return rc;
+    if ((rc = set_device_doubles(V.coef_k2, k2, n, st))) return rc;
+    if ((rc = set_device_doubles(V.coef_mk, mk, n, st))) return rc;
+    // fresh solution and residual state for these slots
+    for (Fld *f : {&V.x, &V.x64}) {
+        if (!f->base) continue;
+        HRW_HIP(launch_zero(f->base, (size_t)n * V.RS * dtype_cbytes(f->dt), st));
+    }
+    if (V.sys == HRW_SYS_DDAG_D_EO) {
+        HRW_HIP(launch_pack_spinor(0, nr, g->g, false, 0, n, b_in, V.b.h(0), nullptr, V.RS, st));
+    } else if (V.sys == HRW_SYS_DDAG_D_FULL) {
+        HRW_HIP(launch_pack_spinor(0, nr, g->g, true, 0, n, b_in, V.b.h(0), V.b.h(1), V.RS, st));
     } else {
         // b'_e = b_e + kappa H_eo b_o, then eta = D_hat^+ b'_e
-        HRW_HIP(launch_pack_spinor(0, nr, g->g, true, 0, n_rhs, b_in, P.bfull.h(0), P.bfull.h(1), P.RS, st));
+        HRW_HIP(launch_pack_spinor(0, nr, g->g, true, 0, n, b_in, V.bfull.h(0), V.bfull.h(1), V.RS, st));
         HopCall c;
         c.dt = 0;
-        c.n_rhs = n_rhs;
-        c.rstride = P.RS;
+        c.n_rhs = n;
+        c.rstride = V.RS;
         c.parity = 0;
         c.epi = EPI_AXPY;
-        c.coef = P.coef_mk;
-        c.in[1] = P.bfull.h(1);
-        c.self[0] = P.bfull.h(0);
-        c.out[0] = P.dfull.h(0);
-        if ((rc = run_hop(g, R.ph, c, st))) return rc;
+        c.coef = V.coef_mk;
+        c.in[1] = V.bfull.h(1);
+        c.self[0] = V.bfull.h(0);
+        c.out[0] = V.dfull.h(0);
+        if ((rc = run_hop(g, s->ph, c, st))) return rc;
         HopCall a;
         a.dt = 0;
-        a.n_rhs = n_rhs;
-        a.rstride = P.RS;
+        a.n_rhs = n;
+        a.rstride = V.RS;
         a.parity = 1;
         a.dagger = true;
         a.epi = EPI_PLAIN;
-        a.in[0] = P.dfull.h(0);
-        a.out[1] = P.dfull.h(1);
-        if ((rc = run_hop(g, R.ph, a, st))) return rc;
+        a.in[0] = V.dfull.h(0);
+        a.out[1] = V.dfull.h(1);
+        if ((rc = run_hop(g, s->ph, a, st))) return rc;
         HopCall d = a;
         d.parity = 0;
         d.epi = EPI_AXPY;
-        d.coef = P.coef_k2;
-        d.in[1] = P.dfull.h(1);
-        d.self[0] = P.dfull.h(0);
-        d.out[0] = P.b.h(0);
-        if ((rc = run_hop(g, R.ph, d, st))) return rc;
+        d.coef = V.coef_k2;
+        d.in[1] = V.dfull.h(1);
+        d.self[0] = V.dfull.h(0);
+        d.out[0] = V.b.h(0);
+        if ((rc = run_hop(g, s->ph, d, st))) return rc;
     }
-    const size_t E = R.elems();
-    const int nbv = vec_grid(E);
-
-    // ---- initial state: r = p = b (x = 0), |b|^2
-    HRW_HIP(launch_norm2<double>((const cpx<double> *)P.b.h(0), E, P.RS, n_rhs, P.pa, P.pstride, nbv, st));
-    // FP16 storage keeps each system at RMS ~1 (its range ends near 6e-8); CG
-    // is linear, so the inner recursion runs on scaled vectors
-    const double scale_numer = P.dl == 3 ? 2.0 * (double)E : 0.0;
-    HRW_HIP(launch_cg_init(P.cs, P.pa, P.pstride, nbv, n_rhs, prm->tol, scale_numer, P.active, st));
-    const size_t felems = P.RS * n_rhs;  // complex elements of one field, all rhs
-    if (P.mixed) {
-        HRW_HIP(launch_seed(P.dl, (const double *)P.b.base, P.r.base, P.p.base, P.cs, E, P.RS, n_rhs, st));
+    const size_t E = s->E;
+    HRW_HIP(launch_norm2<double>((const cpx<double> *)V.b.h(0), E, V.RS, n, V.pa, V.pstride, s->nbv, st));
+    HRW_HIP(launch_cg_init(V.cs, V.pa, V.pstride, s->nbv, n, s->prm.tol, s->scale_numer, V.active, st));
+    if (V.mixed) {
+        HRW_HIP(launch_zero(V.x.base, (size_t)n * V.RS * dtype_cbytes(V.dl), st));
+        HRW_HIP(launch_seed(V.dl, (const double *)V.b.base, V.r.base, V.p.base, V.cs, E, V.RS, n, st));
     } else {
-        HRW_HIP(launch_copy<double>((const cpx<double> *)P.b.base, (cpx<double> *)P.r.base, felems, st));
-        HRW_HIP(launch_copy<double>((const cpx<double> *)P.b.base, (cpx<double> *)P.p.base, felems, st));
+        HRW_HIP(launch_copy<double>((const cpx<double> *)V.b.base, (cpx<double> *)V.r.base, (size_t)n * V.RS, st));
+        HRW_HIP(launch_copy<double>((const cpx<double> *)V.b.base, (cpx<double> *)V.p.base, (size_t)n * V.RS, st));
     }
+    HRW_HIP(hipStreamSynchronize(st));
+    const auto now = std::chrono::steady_clock::now();
+    for (int j = slot; j < slot + n; ++j) {
+        s->used[j] = 1;
+        s->t_load[j] = now;
+        s->hf.host[j] = 1;
+    }
+    (void)R;
+    return HRW_OK;
+}
 
-    HostFlags hf;
-    if ((rc = host_flags_acquire(&hf))) return rc;
-    struct Guard {
-        HostFlags *f;
-        hipEvent_t ev[3];
-        ~Guard()
-        {
-            for (auto &e : ev)
-                if (e) (void)hipEventDestroy(e);
-            host_flags_release(f);
-        }
-    } guard{&hf, {nullptr, nullptr, nullptr}};
-    for (auto &e : guard.ev) HRW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    for (int j = 0; j < n_rhs; ++j) hf.host[j] = 1;
-
-    const int max_iter = prm->max_iter > 0 ? prm->max_iter : 1;
-    ReliableSchedule sched;
-    sched.every = P.mixed ? (prm->reliable_every > 0 ? prm->reliable_every : 50) : 0;
-    sched.delta2 = P.mixed ? prm->reliable_delta * prm->reliable_delta : 0.0;
+// One reliable pass (plain CG: true-residual check) over the slots [0, n) that are due.
+static int reliable_pass(hrw_cg_session *s, int n)
+{
+    CgPlan &P = s->P;
+    CgRun R = run_of(s, P, n);
+    const hipStream_t st = s->st;
     const int max_restarts = 20;
-    long long enq = 0;
-    // one reliable pass (or, plain CG, true-residual check) on the due systems;
-    // final = fold everything and record every system's true residual
-    auto reliable_pass = [&](bool final) -> int {
-        int rc2;
-        mark_due_kernel<<<1, 64, 0, st>>>(P.cs, P.active + MAX_RHS, n_rhs, final ? 1 : 0);
+    int rc;
+    mark_due_kernel<<<1, 64, 0, st>>>(P.cs, P.active + MAX_RHS, n, 0);
+    HRW_HIP(hipGetLastError());
+    const int *due = P.active + MAX_RHS;
+    if (P.mixed) {
+        // x64 += x_lo; x_lo = 0; r64 = b - A64 x64; decide; p_lo += r64 - r_lo; r_lo = r64
+        HRW_HIP(launch_fold(P.dl, P.x.base, (double *)P.x64.base, due, P.cs, s->E, P.RS, n, st));
+        if ((rc = true_residual(R, P.x64, P.r64, P.s64, P.t64, P.u64, P.q64))) return rc;
+        cg_reliable_kernel<<<n, WG, 0, st>>>(P.cs, P.pb, P.pstride, s->nbv, due, P.active, max_restarts, 0,
+                                             s->scale_numer);
         HRW_HIP(hipGetLastError());
-        const int *due = P.active + MAX_RHS;
-        if (P.mixed) {
-            // x64 += x_lo; x_lo = 0; r64 = b - A64 x64; decide; p_lo += r64 - r_lo; r_lo = r64
-            // (due systems only)
-            HRW_HIP(launch_fold(P.dl, P.x.base, (double *)P.x64.base, due, P.cs, E, P.RS, n_rhs, st));
-            if ((rc2 = true_residual(R, P.x64, P.r64, P.s64, P.t64, P.u64, P.q64))) return rc2;
-            cg_reliable_kernel<<<n_rhs, WG, 0, st>>>(P.cs, P.pb, P.pstride, nbv, due, P.active, max_restarts,
-                                                     final ? 1 : 0, scale_numer);
-            HRW_HIP(hipGetLastError());
-            HRW_HIP(launch_reseed(P.dl, (const double *)P.r64.base, P.r.base, P.p.base, due, P.cs, E, P.RS, n_rhs,
-                                  st));
-        } else {
-            // no system is running here, so the search direction is free to hold A x
-            if ((rc2 = true_residual(R, P.x, P.r, P.s, P.t, P.u, P.p))) return rc2;
-            cg_reliable_kernel<<<n_rhs, WG, 0, st>>>(P.cs, P.pb, P.pstride, nbv, due, P.active, max_restarts,
-                                                     final ? 1 : 0, 0.0);
-            HRW_HIP(hipGetLastError());
-            // restarted systems: p = r (beta = 0)
-            double zero[MAX_RHS] = {0};
-            if ((rc2 = set_device_doubles(P.beta, zero, n_rhs, st))) return rc2;
-            HRW_HIP(launch_xpay<double>((const cpx<double> *)P.r.h(0), (cpx<double> *)P.p.h(0), P.beta,
-                                        P.active, E, P.RS, n_rhs, st));
-        }
-        flags_to_host_kernel<<<1, 64, 0, st>>>(P.active, hf.dev, n_rhs);
+        HRW_HIP(launch_reseed(P.dl, (const double *)P.r64.base, P.r.base, P.p.base, due, P.cs, s->E, P.RS, n, st));
+    } else {
+        // the iteration's temporaries are free between iterations; r64, q64 are scratch
+        if ((rc = true_residual(R, P.x, P.r64, P.s, P.t, P.u, P.q64))) return rc;
+        cg_reliable_kernel<<<n, WG, 0, st>>>(P.cs, P.pb, P.pstride, s->nbv, due, P.active, max_restarts, 0, 0.0);
         HRW_HIP(hipGetLastError());
-        HRW_HIP(hipStreamSynchronize(st));
-        return HRW_OK;
+        // re-activated systems restart from their true residual: r = p = r64
+        HRW_HIP(launch_restart((const double *)P.r64.h(0), (double *)P.r.h(0), (double *)P.p.h(0), due, P.active,
+                               s->E, P.RS, n, st));
+    }
+    flags_to_host_kernel<<<1, 64, 0, st>>>(P.active, s->hf.dev, n);
+    HRW_HIP(hipGetLastError());
+    HRW_HIP(hipStreamSynchronize(st));
+    return HRW_OK;
+}
+
+static int refresh_states(hrw_cg_session *s)
+{
+    HRW_HIP(hipMemcpyAsync(s->host_state, s->P.cs, sizeof(CgState) * s->n_slots, hipMemcpyDeviceToHost, s->st));
+    HRW_HIP(hipStreamSynchronize(s->st));
+    return HRW_OK;
+}
+
+// Advance every loaded slot by up to max_iters CG iterations (stopping early
+// when nothing runs), with the reliable passes that fall due.  *running
+// receives the number of slots still iterating.
+int session_step(hrw_cg_session *s, int max_iters, int *running)
+{
+    const int n = hi_used(s);
+    int rc;
+    auto count = [&]() {
+        int c = 0;
+        for (int j = 0; j < n; ++j) c += s->used[j] && s->hf.host[j] != 0;
+        return c;
     };
-    for (;;) {
-        // ---- iterate until nothing runs or some system waits for its reliable update
-        for (;;) {
-            if ((rc = cg_iteration(R, max_iter, sched, hf.dev))) return rc;
-            HRW_HIP(hipEventRecord(guard.ev[enq % 3], st));
-            ++enq;
-            if (enq >= 2) {
-                HRW_HIP(hipEventSynchronize(guard.ev[(enq - 2) % 3]));
-                if (!any_running(hf.host, n_rhs) || any_due(hf.host, n_rhs)) break;
+    if (n == 0 || !any_running(s->hf.host, n) && !any_due(s->hf.host, n)) {
+        if (running) *running = 0;
+        return refresh_states(s);
+    }
+    CgRun R = run_of(s, s->P, n);
+    const int max_iter = s->prm.max_iter > 0 ? s->prm.max_iter : 1;
+    int done_iters = 0;
+    while (done_iters < max_iters) {
+        // iterate until nothing runs, some slot waits for its reliable update, or the budget is spent
+        bool need_pass = false;
+        int k = 0;
+        const long long e0 = s->enq;
+        for (; done_iters + k < max_iters; ++k) {
+            if (!any_running(s->hf.host, n)) break;
+            if ((rc = cg_iteration(R, max_iter, s->sched, s->hf.dev))) return rc;
+            HRW_HIP(hipEventRecord(s->ev[s->enq % 3], s->st));
+            ++s->enq;
+            if (s->enq - e0 >= 2) {
+                HRW_HIP(hipEventSynchronize(s->ev[(s->enq - 2) % 3]));
+                if (!any_running(s->hf.host, n) || any_due(s->hf.host, n)) {
+                    ++k;
+                    break;
+                }
             }
         }
-        HRW_HIP(hipStreamSynchronize(st));
-        if ((rc = reliable_pass(false))) return rc;
-        if (!any_running(hf.host, n_rhs)) break;
+        done_iters += k;
+        HRW_HIP(hipStreamSynchronize(s->st));
+        need_pass = any_due(s->hf.host, n) || !any_running(s->hf.host, n);
+        if (need_pass) {
+            if ((rc = reliable_pass(s, n))) return rc;
+        }
+        if (!any_running(s->hf.host, n) || k == 0) break;
     }
-    if ((rc = reliable_pass(true))) return rc;
+    if ((rc = refresh_states(s))) return rc;
+    if (running) *running = count();
+    return HRW_OK;
+}
 
-    // ---- solution out
-    const Fld &X = P.mixed ? P.x64 : P.x;
-    if (P.sys == HRW_SYS_DDAG_D_EO) {
-        HRW_HIP(launch_unpack_spinor(0, nr, g->g, false, 0, n_rhs, X.h(0), nullptr, P.RS, x_out, st));
-    } else if (P.sys == HRW_SYS_DDAG_D_FULL) {
-        HRW_HIP(launch_unpack_spinor(0, nr, g->g, true, 0, n_rhs, X.h(0), X.h(1), P.RS, x_out, st));
+int session_slot_state(hrw_cg_session *s, int *state)
+{
+    for (int j = 0; j < s->n_slots; ++j) {
+        if (!s->used[j]) state[j] = 0;
+        else state[j] = (s->hf.host[j] != 0) ? 1 : 2;
+    }
+    return HRW_OK;
+}
+
+// Read slots [slot, slot + n): fold, FP64 residual, (CGNR) reconstruction and
+// |b - D x|, unpack into x_out, fill res, and free the slots.
+int session_read(hrw_cg_session *s, int slot, int n, double *x_out, hrw_solve_result *res)
+{
+    if (slot < 0 || n < 1 || slot + n > s->n_slots) return fail(HRW_EINVAL, "slot range outside the session");
+    for (int j = slot; j < slot + n; ++j)
+        if (!s->used[j]) return fail(HRW_EINVAL, "slot %d holds no request", j);
+    const hrw_gauge *g = s->g;
+    const hipStream_t st = s->st;
+    CgPlan V = plan_view(s->P, slot);
+    CgRun R = run_of(s, V, n);
+    const int nr = g->nr;
+    const size_t H = V.H;
+    int rc;
+    mark_range_kernel<<<1, 64, 0, st>>>(V.active + MAX_RHS, n, 0, n);
+    HRW_HIP(hipGetLastError());
+    const int *due = V.active + MAX_RHS;
+    if (V.mixed) {
+        HRW_HIP(launch_fold(V.dl, V.x.base, (double *)V.x64.base, due, V.cs, s->E, V.RS, n, st));
+        if ((rc = true_residual(R, V.x64, V.r64, V.s64, V.t64, V.u64, V.q64))) return rc;
+    } else {
+        if ((rc = true_residual(R, V.x, V.r64, V.s, V.t, V.u, V.q64))) return rc;
+    }
+    // record the FP64 residual of every read slot without changing decisions
+    cg_reliable_kernel<<<n, WG, 0, st>>>(V.cs, V.pb, V.pstride, s->nbv, due, V.active, 0, 1, 0.0);
+    HRW_HIP(hipGetLastError());
+    const Fld &X = V.mixed ? V.x64 : V.x;
+    if (V.sys == HRW_SYS_DDAG_D_EO) {
+        HRW_HIP(launch_unpack_spinor(0, nr, g->g, false, 0, n, X.h(0), nullptr, V.RS, x_out, st));
+    } else if (V.sys == HRW_SYS_DDAG_D_FULL) {
+        HRW_HIP(launch_unpack_spinor(0, nr, g->g, true, 0, n, X.h(0), X.h(1), V.RS, x_out, st));
     } else {
         // x_o = b_o + kappa H_oe x_e; then |b - D x| over the full lattice
         HopCall c;
         c.dt = 0;
-        c.n_rhs = n_rhs;
-        c.rstride = P.RS;
+        c.n_rhs = n;
+        c.rstride = V.RS;
         c.parity = 1;
         c.epi = EPI_AXPY;
-        c.coef = P.coef_mk;
+        c.coef = V.coef_mk;
         c.in[0] = X.h(0);
-        c.self[1] = P.bfull.h(1);
+        c.self[1] = V.bfull.h(1);
         c.out[1] = X.h(1);
-        if ((rc = run_hop(g, R.ph, c, st))) return rc;
-        HRW_HIP(launch_unpack_spinor(0, nr, g->g, true, 0, n_rhs, X.h(0), X.h(1), P.RS, x_out, st));
+        if ((rc = run_hop(g, s->ph, c, st))) return rc;
+        HRW_HIP(launch_unpack_spinor(0, nr, g->g, true, 0, n, X.h(0), X.h(1), V.RS, x_out, st));
         HopCall d;
         d.dt = 0;
-        d.n_rhs = n_rhs;
-        d.rstride = P.RS;
+        d.n_rhs = n;
+        d.rstride = V.RS;
         d.parity = -1;
         d.epi = EPI_AXPY;
-        d.coef = P.coef_k;
+        d.coef = V.coef_k;
         for (int k = 0; k < 2; ++k) {
             d.in[k] = X.h(k);
             d.self[k] = X.h(k);
-            d.out[k] = P.dfull.h(k);
+            d.out[k] = V.dfull.h(k);
         }
-        if ((rc = run_hop(g, R.ph, d, st))) return rc;
+        if ((rc = run_hop(g, s->ph, d, st))) return rc;
         const int nb2 = vec_grid(2 * H);
-        HRW_HIP(launch_residual<double>((const cpx<double> *)P.bfull.h(0), (const cpx<double> *)P.dfull.h(0),
-                                        (cpx<double> *)P.q64.h(0), 2 * H, P.RS, n_rhs, P.pa, P.pstride, nb2, st));
-        HRW_HIP(launch_sum_partials(P.pa, P.pstride, nb2, n_rhs, P.scal, st));
-        HRW_HIP(launch_norm2<double>((const cpx<double> *)P.bfull.h(0), 2 * H, P.RS, n_rhs, P.pb, P.pstride, nb2, st));
-        HRW_HIP(launch_sum_partials(P.pb, P.pstride, nb2, n_rhs, P.scal + MAX_RHS, st));
+        HRW_HIP(launch_residual<double>((const cpx<double> *)V.bfull.h(0), (const cpx<double> *)V.dfull.h(0),
+                                        (cpx<double> *)V.q64.h(0), 2 * H, V.RS, n, V.pa, V.pstride, nb2, st));
+        HRW_HIP(launch_sum_partials(V.pa, V.pstride, nb2, n, V.scal, st));
+        HRW_HIP(launch_norm2<double>((const cpx<double> *)V.bfull.h(0), 2 * H, V.RS, n, V.pb, V.pstride, nb2, st));
+        HRW_HIP(launch_sum_partials(V.pb, V.pstride, nb2, n, V.scal + MAX_RHS, st));
     }
-    std::vector<CgState> hs(n_rhs);
-    HRW_HIP(hipMemcpyAsync(hs.data(), P.cs, sizeof(CgState) * n_rhs, hipMemcpyDeviceToHost, st));
+    std::vector<CgState> hs(n);
+    HRW_HIP(hipMemcpyAsync(hs.data(), V.cs, sizeof(CgState) * n, hipMemcpyDeviceToHost, st));
     double dres[2 * MAX_RHS] = {0};
-    if (P.sys == HRW_SYS_D_CGNR_EO)
-        HRW_HIP(hipMemcpyAsync(dres, P.scal, sizeof(double) * 2 * MAX_RHS, hipMemcpyDeviceToHost, st));
+    if (V.sys == HRW_SYS_D_CGNR_EO) {
+        HRW_HIP(hipMemcpyAsync(dres, V.scal, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+        HRW_HIP(hipMemcpyAsync(dres + MAX_RHS, V.scal + MAX_RHS, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    }
+    // the slots are free again: inactive and never due
+    free_slots_kernel<<<1, 64, 0, st>>>(V.cs, V.active, n);
+    HRW_HIP(hipGetLastError());
     HRW_HIP(hipStreamSynchronize(st));
-    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    const auto now = std::chrono::steady_clock::now();
     int overall = HRW_OK;
-    for (int j = 0; j < n_rhs; ++j) {
+    for (int j = 0; j < n; ++j) {
         const CgState &c = hs[j];
         hrw_solve_result &o = res[j];
         o.iters = c.iters;
-        o.reliable_updates = P.mixed ? c.updates : 0;
+        o.reliable_updates = V.mixed ? c.updates : 0;
         o.restarts = c.restarts;
         o.true_rel_resid = c.rr0 > 0 ? sqrt(c.rr_true / c.rr0) : 0.0;
         o.recursive_rel_resid = c.rr0 > 0 ? sqrt(c.rr / (c.rr0 * c.scale * c.scale)) : 0.0;
-        o.d_rel_resid = (P.sys == HRW_SYS_D_CGNR_EO && dres[MAX_RHS + j] > 0)
-                            ? sqrt(dres[j] / dres[MAX_RHS + j]) : 0.0;
-        o.seconds = secs;
-        if (c.status == CG_DONE) {
-            o.status = HRW_OK;
-        } else if (c.status == CG_BREAKDOWN) {
-            o.status = HRW_EBREAKDOWN;
-        } else {
-            o.status = HRW_NOT_CONVERGED;
-        }
+        o.d_rel_resid = (V.sys == HRW_SYS_D_CGNR_EO && dres[MAX_RHS + j] > 0) ? sqrt(dres[j] / dres[MAX_RHS + j])
+                                                                            : 0.0;
+        o.seconds = std::chrono::duration<double>(now - s->t_load[slot + j]).count();
+        o.status = c.status == CG_DONE ? HRW_OK : c.status == CG_BREAKDOWN ? HRW_EBREAKDOWN : HRW_NOT_CONVERGED;
         if (o.status == HRW_EBREAKDOWN) overall = HRW_EBREAKDOWN;
         else if (o.status == HRW_NOT_CONVERGED && overall == HRW_OK) overall = HRW_NOT_CONVERGED;
+        s->used[slot + j] = 0;
+        s->hf.host[slot + j] = 0;
     }
     if (timing().on) timing_harvest();
     return overall;
+}
+
+int cg_solve(const hrw_gauge *g, const hrw_solve_params *prm, int n_rhs, const double *kappa,
+             const double *b_in, double *x_out, hrw_solve_result *res, void *ws, size_t ws_bytes,
+             hipStream_t st)
+{
+    hrw_cg_session *s = nullptr;
+    int rc = session_create(g, prm, n_rhs, ws, ws_bytes, st, &s);
+    if (rc) return rc;
+    struct Close {
+        hrw_cg_session *s;
+        ~Close() { session_destroy(s); }
+    } close{s};
+    if ((rc = session_load(s, 0, n_rhs, kappa, b_in))) return rc;
+    int running = 1;
+    while (running > 0)
+        if ((rc = session_step(s, 1 << 30, &running))) return rc;
+    return session_read(s, 0, n_rhs, x_out, res);
 }
 
 }  // namespace hrw

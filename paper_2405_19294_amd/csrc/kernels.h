@@ -212,6 +212,9 @@ hipError_t launch_reseed(int dt_lo, const double *r64, void *r_lo, void *p_lo, c
 // the recursion's rr is kept in scaled units
 hipError_t launch_cg_init(CgState *st_, const double *partial, int pstride, int nparts,
                           int n_rhs, double tol, double scale_numer, int *active_out, hipStream_t st);
+// plain CG: r = p = r64 for the systems with due[rhs] && active[rhs]
+hipError_t launch_restart(const double *r64, double *r, double *p, const int *due, const int *active,
+                          size_t elems, size_t rstride, int n_rhs, hipStream_t st);
 // mixed precision start: r_lo = p_lo = round(scale * b)
 hipError_t launch_seed(int dt_lo, const double *b64, void *r_lo, void *p_lo, const CgState *cs,
                        size_t elems, size_t rstride, int n_rhs, hipStream_t st);

@@ -65,6 +65,12 @@ SIGNATURES = {
     "hrw_hop_eo": (I, [P, I, DP, I, I, I, P, P, P, SZ, P]),
     "hrw_deo_apply": (I, [P, DP, DP, I, I, I, P, P, P, SZ, P]),
     "hrw_cg_solve": (I, [P, ctypes.POINTER(SolveParams), I, DP, P, P, ctypes.POINTER(SolveResult), P, SZ, P]),
+    "hrw_cg_session_create": (I, [P, ctypes.POINTER(SolveParams), I, P, SZ, P, ctypes.POINTER(P)]),
+    "hrw_cg_session_load": (I, [P, I, I, DP, P]),
+    "hrw_cg_session_step": (I, [P, I, IP]),
+    "hrw_cg_session_slots": (I, [P, IP]),
+    "hrw_cg_session_read": (I, [P, I, I, P, ctypes.POINTER(SolveResult)]),
+    "hrw_cg_session_destroy": (I, [P]),
     "hrw_timing_enable": (I, [I]),
     "hrw_timing_read": (I, [I, ctypes.POINTER(ctypes.c_longlong), DP, DP]),
 }
@@ -269,6 +275,61 @@ def cg_solve(g: Gauge, b: torch.Tensor, kappa, params: SolveParams, x=None, ws: 
     if rc < 0 and rc != EBREAKDOWN:
         _check(rc)
     return x, [r.as_dict() for r in res], rc
+
+
+class Session:
+    """A CG session of n_slots slots over one resident gauge field (continuous batching).
+
+    Systems are loaded into free slots and read out when finished, between
+    steps, while the other slots keep iterating; each slot's result is the
+    same as a standalone solve of that system.
+    """
+
+    def __init__(self, g: Gauge, params: SolveParams, n_slots: int, stream=None):
+        self.g, self.params, self.n_slots = g, params, int(n_slots)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.ws = cg_workspace(g, params, n_slots)
+        h = ctypes.c_void_p()
+        _check(load().hrw_cg_session_create(g.handle, ctypes.byref(params), self.n_slots, self.ws.buf.data_ptr(),
+                                            self.ws.nbytes, self.stream.cuda_stream, ctypes.byref(h)))
+        self.handle = h
+        per = (g.volume // 2 if params.system == SYSTEMS["ddag_d_eo"] else g.volume) * 4 * g.nr
+        self.field_elems = per
+
+    def load(self, slot: int, b: torch.Tensor, kappa):
+        n = _n_rhs(b, self.field_elems)
+        ks = [kappa] * n if isinstance(kappa, (int, float)) else list(kappa)
+        _check(load().hrw_cg_session_load(self.handle, slot, n, _doubles(ks), _dev_field(b, "b")))
+
+    def step(self, max_iters: int) -> int:
+        running = ctypes.c_int()
+        _check(load().hrw_cg_session_step(self.handle, int(max_iters), ctypes.byref(running)))
+        return running.value
+
+    def slots(self):
+        st = (ctypes.c_int * self.n_slots)()
+        _check(load().hrw_cg_session_slots(self.handle, st))
+        return list(st)
+
+    def read(self, slot: int, n: int, x: torch.Tensor | None = None):
+        shape = (n, self.field_elems // (4 * self.g.nr), 4, self.g.nr)
+        x = torch.empty(shape, dtype=torch.complex128, device=self.g.device) if x is None else x
+        res = (SolveResult * n)()
+        rc = load().hrw_cg_session_read(self.handle, slot, n, _dev_field(x, "x"), res)
+        if rc < 0 and rc != EBREAKDOWN:
+            _check(rc)
+        return x, [r.as_dict() for r in res], rc
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().hrw_cg_session_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def timing_enable(on: bool = True):
