@@ -13,6 +13,12 @@ hopping-kernel instance measured with HIP events inside the timed steps, and
 the CPU oracle timed on a bounded sample as ``cpu_baseline``.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--workload c2|c1|c3|c4|c5]
+
+The default workload (c2) is the one the headline numbers are quoted on; the
+others print the same kind of JSON line for the remaining configurations:
+c1 SU(2) fund 4^4 (latency-bound), c3 SU(2) adj / SU(4) asym 24^3x48 mixed
+precision, c4 SU(3) sym 32^4 multi-source, c5 the serving stream.
 """
 
 from __future__ import annotations
@@ -67,11 +73,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=0, help="oracle CG iterations in the CPU sample (0 = auto)")
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is not part of it",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload != "c2":
+        out = {"c1": workload_c1, "c3": workload_c3, "c4": workload_c4, "c5": workload_c5}[args.workload](args)
+        print(json.dumps(out), flush=True)
+        return
 
     import torch
 
@@ -177,6 +188,230 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dims, uf, b, kappa, theta, r["iters"], args.cpu_iters)
     print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------- other workloads
+
+def _line(metric_value, unit, steps, warmup, ms_per_step, dtype, config, roofline, **extra):
+    out = {"metric": METRIC, "value": metric_value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+           "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": dtype, "data": "synthetic", "config": config, "roofline": roofline}
+    out.update(extra)
+    return out
+
+
+def _hop_roofline(hrw, kernel_label):
+    """Roofline of the hopping-kernel class with the most summed time since timing_enable."""
+    classes = {n: hrw.timing_read(k) for k, n in [(3, "plain"), (4, "axpy"), (5, "cg")]}
+    name = max(classes, key=lambda n: classes[n]["ms"])
+    c = classes[name]
+    if not c["ms"]:
+        return None
+    ach = c["bytes"] / (c["ms"] * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": f"{kernel_label}, {name} epilogue", "achieved": round(ach, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_launch_us": round(c["ms"] / c["launches"] * 1e3, 2),
+            "bytes_per_launch": round(c["bytes"] / c["launches"]), "launches": c["launches"]}
+
+
+def _even_part(dims, full):
+    x = np.indices(tuple(dims)).reshape(4, -1)
+    return np.ascontiguousarray(full[..., (x.sum(axis=0) & 1) == 0, :, :])
+
+
+def _solve_timed(hrw, torch, g, b, kappa, prm, steps, warmup):
+    for _ in range(warmup):
+        hrw.cg_solve(g, b, kappa, prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat = []
+    for _ in range(steps):
+        ts = time.perf_counter()
+        x, res, rc = hrw.cg_solve(g, b, kappa, prm)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+        if rc != 0:
+            raise RuntimeError(f"solve failed: {res}")
+    return x, res, (time.perf_counter() - t0) / steps, lat
+
+
+def workload_c1(args):
+    """SU(2) fund 4^4, Haar links, kappa 0.12, antiperiodic: D_W apply + FP64 CG on D^+D (full lattice)."""
+    import torch
+
+    import fixtures as fx
+    from paper_2405_19294_amd import hrw
+    dev = torch.device("cuda:0")
+    dims, kappa, theta = (4, 4, 4, 4), 0.12, (np.pi, 0, 0, 0)
+    uf = torch.from_numpy(fx.gauge_field(dims, 2, "haar", seed=1)).to(dev)
+    psi = torch.from_numpy(fx.gaussian_spinor(dims, 2, seed=2)).to(dev)
+    g = hrw.Gauge(dims, 2, "fund", uf, dtypes=("f64",))
+    ws = hrw.Workspace.for_apply(g, 1)
+    out = torch.empty_like(psi)
+    for _ in range(10):
+        hrw.dw_apply(g, kappa, psi, theta, out=out, ws=ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(200):
+        hrw.dw_apply(g, kappa, psi, theta, out=out, ws=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    apply_us = e0.elapsed_time(e1) / 200 * 1e3
+    prm = hrw.solve_params(tol=1e-10, system="ddag_d_full", theta=theta)
+    hrw.timing_enable(True)
+    x, res, per, lat = _solve_timed(hrw, torch, g, psi, kappa, prm, max(args.steps, 20), args.warmup)
+    roof = _hop_roofline(hrw, "hop_kernel<N_R=2, double>")
+    hrw.timing_enable(False)
+    return _line(round(1.0 / per, 2), "solves/s", max(args.steps, 20), args.warmup, round(per * 1e3, 3), "f64",
+                 {"workload": "su2_fund_4^4_cg_fp64_full", "lattice": list(dims), "kappa": kappa,
+                  "gauge": "Haar SU(2)", "system": "D^+D x = b, full lattice", "tol": 1e-10},
+                 roof, dw_apply_us=round(apply_us, 2),
+                 note="latency-bound: 256 sites (0.13 MB per apply), so no GB/s claim; the apply time includes "
+                      "packing and unpacking of the canonical fields",
+                 latency_ms={"p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                             "p99": round(float(np.percentile(lat, 99)) * 1e3, 3)},
+                 solve={"iters": res[0]["iters"], "true_rel_resid": res[0]["true_rel_resid"]})
+
+
+def workload_c3(args):
+    """24^3x48 SU(2) adj and SU(4) asym, U_R built on the device: FP64 / FP32 / BF16 / FP16-storage CG."""
+    import torch
+
+    import fixtures as fx
+    from paper_2405_19294_amd import hrw
+    dev = torch.device("cuda:0")
+    dims, kappa, theta = (48, 24, 24, 24), 0.135, (np.pi, 0, 0, 0)
+    cases, roof, main = [], None, None
+    for nc, rep in [(2, "adj"), (4, "asym")]:
+        t0 = time.time()
+        uf = torch.from_numpy(fx.gauge_field(dims, nc, "thermal", seed=3, eps=0.3)).to(dev)
+        log(f"c3 SU({nc}) links in {time.time() - t0:.1f}s")
+        g = hrw.Gauge(dims, nc, rep, uf, dtypes=("f64", "f32", "bf16", "f16"))
+        del uf
+        b = torch.from_numpy(_even_part(dims, fx.gaussian_spinor(dims, g.nr, seed=4))).to(dev)
+        ref = None
+        for inner in ["f64", "f32", "bf16", "f16"]:
+            prm = hrw.solve_params(tol=1e-10, max_iter=20000, system="ddag_d_eo", inner_dtype=inner,
+                                   reliable_every=50, theta=theta)
+            hrw.timing_enable(True)
+            x, res, per, lat = _solve_timed(hrw, torch, g, b, kappa, prm, args.steps, args.warmup)
+            r = _hop_roofline(hrw, f"hop_kernel<N_R={g.nr}, {inner}>")
+            hrw.timing_enable(False)
+            if inner == "f64":
+                ref = x.clone()
+            err = float((torch.linalg.vector_norm(x - ref) / torch.linalg.vector_norm(ref)).item())
+            case = {"rep": f"SU({nc}) {rep}", "n_r": g.nr, "inner": inner, "solves_per_s": round(1.0 / per, 3),
+                    "ms_per_solve": round(per * 1e3, 2), "iters": res[0]["iters"],
+                    "reliable_updates": res[0]["reliable_updates"], "true_rel_resid": res[0]["true_rel_resid"],
+                    "rel_error_vs_fp64": err, "hop_roofline": r}
+            cases.append(case)
+            log(f"c3 {case}")
+            if nc == 4 and inner == "f32":
+                main, roof = case, r
+        # D_W (full lattice) apply bandwidth in FP64 and FP32 on this representation
+        psi = torch.from_numpy(fx.gaussian_spinor(dims, g.nr, seed=5)).to(dev)
+        ws = hrw.Workspace.for_apply(g, 1)
+        out_ = torch.empty_like(psi)
+        for dt in ["f64", "f32"]:
+            hrw.dw_apply(g, kappa, psi, theta, dt, out=out_, ws=ws)
+            torch.cuda.synchronize()
+            hrw.timing_enable(True)
+            for _ in range(10):
+                hrw.dw_apply(g, kappa, psi, theta, dt, out=out_, ws=ws)
+            torch.cuda.synchronize()
+            c = hrw.timing_read(4)
+            hrw.timing_enable(False)
+            cases.append({"rep": f"SU({nc}) {rep}", "dw_apply_hop_" + dt: {
+                "us": round(c["ms"] / c["launches"] * 1e3, 1),
+                "GBs_dup_link_model": round(c["bytes"] / (c["ms"] * 1e-3) / 1e9, 1)}})
+        del g, b, psi, ws, out_
+        torch.cuda.empty_cache()
+    return _line(main["solves_per_s"], "solves/s", args.steps, args.warmup, main["ms_per_solve"], "f32",
+                 {"workload": "su4_asym_24^3x48_mixed_cg", "lattice": list(dims), "kappa": kappa,
+                  "reps": ["SU(2) adj", "SU(4) asym"], "inner": ["f64", "f32", "bf16", "f16"],
+                  "reliable_every": 50, "tol": 1e-10}, roof, cases=cases)
+
+
+def workload_c4(args):
+    """SU(3) sym 32^4, 12 and 24 point-smeared sources: multi-source mixed CG vs plain FP64 CG."""
+    import torch
+
+    import fixtures as fx
+    from paper_2405_19294_amd import hrw
+    dev = torch.device("cuda:0")
+    dims, kappa, theta = (32, 32, 32, 32), 0.135, (np.pi, 0, 0, 0)
+    t0 = time.time()
+    uf = torch.from_numpy(fx.gauge_field(dims, 3, "thermal", seed=6, eps=0.3)).to(dev)
+    g = hrw.Gauge(dims, 3, "sym", uf, dtypes=("f64", "f32"))
+    del uf
+    nmax = 24
+    srcs = torch.empty((nmax, fx.volume(dims) // 2, 4, g.nr), dtype=torch.complex128, device=dev)
+    for k in range(nmax):
+        full = fx.point_smeared_sources(dims, g.nr, nmax, seed=7, which=[k])
+        srcs[k] = torch.from_numpy(_even_part(dims, full)[0])
+    log(f"c4 inputs in {time.time() - t0:.1f}s")
+    # plain FP64 CG, one source at a time (the reference rate)
+    prm64 = hrw.solve_params(tol=1e-10, max_iter=20000, system="ddag_d_eo", inner_dtype="f64", theta=theta)
+    x64, res64, per64, _ = _solve_timed(hrw, torch, g, srcs[0:1].contiguous(), kappa, prm64, max(1, args.steps // 2), 1)
+    fp64_rate = 1.0 / per64
+    out = {}
+    roof = None
+    for n in (12, 24):
+        prm = hrw.solve_params(tol=1e-10, max_iter=20000, system="ddag_d_eo", inner_dtype="f32",
+                               reliable_every=50, theta=theta)
+        b = srcs[:n].contiguous()
+        hrw.timing_enable(True)
+        x, res, per, lat = _solve_timed(hrw, torch, g, b, kappa, prm, max(1, args.steps // 2), 1)
+        r = _hop_roofline(hrw, f"hop_mrhs_kernel<N_R=6, float, {n} sources>")
+        hrw.timing_enable(False)
+        err0 = float((torch.linalg.vector_norm(x[0] - x64[0]) / torch.linalg.vector_norm(x64[0])).item())
+        out[n] = {"rhs_solves_per_s": round(n / per, 3), "ms_per_batch": round(per * 1e3, 1),
+                  "speedup_vs_fp64_cg": round(n / per / fp64_rate, 2),
+                  "max_iters": max(q["iters"] for q in res),
+                  "max_true_rel_resid": max(q["true_rel_resid"] for q in res),
+                  "rel_error_vs_fp64_source0": err0, "hop_roofline": r}
+        log(f"c4 n={n}: {out[n]}")
+        roof = r
+    return _line(out[24]["rhs_solves_per_s"], "rhs-solves/s", max(1, args.steps // 2), 1, out[24]["ms_per_batch"],
+                 "f32", {"workload": "su3_sym_32^4_multi_source_mixed_cg", "lattice": list(dims), "kappa": kappa,
+                         "sources": "point-smeared (Gaussian spatial profile, width 2), 12 and 24",
+                         "inner": "f32", "reliable_every": 50, "tol": 1e-10}, roof,
+                 fp64_cg={"solves_per_s": round(fp64_rate, 3), "iters": res64[0]["iters"]}, multi_source=out)
+
+
+def workload_c5(args):
+    """Serving: Poisson stream (20/s, seed 5) of CG requests over 5 volumes x 4 reps, continuous batching."""
+    import torch
+
+    from paper_2405_19294_amd import serve
+    be = serve.GpuBackend(inner_dtype="f32", tol=1e-10)
+    reqs = serve.poisson_stream(400, rate=20.0, seed=5)
+    free, total = torch.cuda.mem_get_info()
+    budget = int(min(free * 0.8, 200e9))
+    t0 = time.time()
+    for key in sorted({r.key for r in reqs}):
+        be.gauge(key)
+    log(f"c5: {len({r.key for r in reqs})} resident gauge fields in {time.time() - t0:.1f}s")
+    srv = serve.Server(be, hbm_budget=budget, n_slots=12, step_iters=20)
+    last = [0.0]
+
+    def progress(done, n):
+        if time.time() - last[0] > 10:
+            last[0] = time.time()
+            log(f"c5: {done}/{n} requests done")
+    rep = srv.run(reqs, realtime=True, on_progress=progress)
+    lat = rep["latency_s"]
+    return _line(round(rep["rhs_solves_per_s"], 3), "rhs-solves/s", len(reqs), 0,
+                 round(rep["wall_s"] * 1e3 / max(rep["done"], 1), 3), "f32",
+                 {"workload": "serving_poisson_20hz_400req", "rate_per_s": 20.0, "requests": len(reqs),
+                  "volumes": ["8^4", "16^4", "16^3x32", "24^3x48", "32^3x64"],
+                  "reps": ["SU(2) fund", "SU(2) adj", "SU(3) fund", "SU(4) asym"], "kappa": [0.12, 0.135],
+                  "rhs_per_request": [1, 12], "slots_per_session": 12, "inner": "f32", "tol": 1e-10}, None,
+                 latency_ms={"p50": round(lat["p50"] * 1e3, 1), "p99": round(lat["p99"] * 1e3, 1),
+                             "max": round(lat["max"] * 1e3, 1)},
+                 service_ms={k: round(v * 1e3, 1) for k, v in rep["service_s"].items()},
+                 report={k: v for k, v in rep.items() if k not in ("latency_s", "service_s")})
 
 
 def copy_reference(torch, dev, nbytes=1 << 30, reps=10):

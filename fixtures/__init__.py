@@ -182,22 +182,26 @@ def gaussian_spinor(dims, nr: int, seed: int = 2, n_rhs: int | None = None) -> n
     return _complex_normal(g, shape, 1.0)
 
 
-def point_smeared_sources(dims, nr: int, n_rhs: int, seed: int = 4, width: float = 2.0) -> np.ndarray:
+def point_smeared_sources(dims, nr: int, n_rhs: int, seed: int = 4, width: float = 2.0,
+                          which=None) -> np.ndarray:
     """Point sources at seeded sites, smeared with a spatial Gaussian profile.
 
     Source k sits at a seeded site x_k, in spin k mod 4 and colour
     (k // 4) mod nr; on the time slice of x_k it carries the weight
     exp(-|x - x_k|^2 / (2 width^2)) with the spatial distance taken with
     periodic wrap, and zero elsewhere; each source is normalised to unit
-    2-norm.  Shape [n_rhs][V][4][nr].
+    2-norm.  Shape [n_rhs][V][4][nr]; with ``which`` (indices below n_rhs)
+    only those sources are returned, identical to the full set's entries.
     """
     d = tuple(int(v) for v in dims)
     v = volume(d)
     g = rng(seed, _STREAM_SOURCE)
-    out = np.zeros((n_rhs, v, 4, nr), dtype=np.complex128)
+    ks = list(range(n_rhs)) if which is None else [int(k) for k in which]
+    out = np.zeros((len(ks), v, 4, nr), dtype=np.complex128)
     x = np.indices(d).reshape(4, -1)  # coordinates of every site
-    for k in range(n_rhs):
-        src = [int(g.integers(0, n)) for n in d]
+    pos = [[int(g.integers(0, n)) for n in d] for _ in range(n_rhs)]
+    for o, k in enumerate(ks):
+        src = pos[k]
         on_slice = x[0] == src[0]
         r2 = np.zeros(v)
         for mu in (1, 2, 3):
@@ -205,8 +209,8 @@ def point_smeared_sources(dims, nr: int, n_rhs: int, seed: int = 4, width: float
             dx = np.minimum(dx, d[mu] - dx)
             r2 += dx.astype(np.float64) ** 2
         w = np.where(on_slice, np.exp(-r2 / (2.0 * width * width)), 0.0)
-        out[k, :, k % 4, (k // 4) % nr] = w
-        out[k] /= np.sqrt(np.sum(np.abs(out[k]) ** 2))
+        out[o, :, k % 4, (k // 4) % nr] = w
+        out[o] /= np.sqrt(np.sum(np.abs(out[o]) ** 2))
     return out
 
 

@@ -119,11 +119,13 @@ double hop_bytes(const Geom &g, int nr, int dt, int parity, int epi, int n_rhs)
     const double cb = (double)dtype_cbytes(dt);
     const double links = 8.0 * nr * nr * cb;
     const double sp = 4.0 * nr * cb;
-    double per = links + sp;  // links + neighbour spinors (each input spinor once)
+    double per = sp;  // neighbour spinors (each input spinor once)
     if (epi == EPI_PLAIN) per += sp;            // out
     else if (epi == EPI_AXPY) per += 2 * sp;    // self + out
     else per += 6 * sp;                         // self, r, x, p read; r, x written
-    return per * sites * n_rhs;
+    // the multi-source kernel reads each link once for all sources
+    const double link_reads = hop_uses_mrhs(nr, dt, n_rhs) ? 1.0 : (double)n_rhs;
+    return (per * n_rhs + links * link_reads) * sites;
 }
 
 int run_hop(const hrw_gauge *g, const Phases &ph, const HopCall &c, hipStream_t st)

@@ -465,7 +465,7 @@ hipError_t launch_hop_impl(int nr, bool dagger, int epi, const HopArgs<S> &a, hi
         constexpr int RS = hop_rows(NR, dtype_id<S>());
         constexpr int G = NR / RS;
         b.ngroups = hop_groups(a.g);
-        if (a.n_rhs > 1 && G * MR_SITES <= WG / 2) {
+        if (hop_uses_mrhs(NR, dtype_id<S>(), a.n_rhs)) {
             const int gh = b.ngroups;  // one workgroup per 16-site group
             b.grid_half = gh;
             hop_tiling(a.g, MR_SITES, &b.tile_ts, &b.tile_c);

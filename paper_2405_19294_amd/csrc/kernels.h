@@ -95,6 +95,13 @@ constexpr int HOP_MAX_G = 8;  // largest threads-per-site of any instance
 constexpr int PG_SITES = 16;  // sites per FP64 partial-sum group of the hopping kernels
 constexpr int MR_SITES = 16;  // sites per workgroup of the multi-source hopping kernel
 
+// Whether a launch with n_rhs sources runs the multi-source kernel (links
+// shared through LDS); else one grid row per source re-reads the links.
+constexpr bool hop_uses_mrhs(int nr, int dt, int n_rhs)
+{
+    return n_rhs > 1 && (nr / hop_rows(nr, dt)) * MR_SITES <= WG / 2;
+}
+
 // Partial sums per parity written by one hopping launch: one per 16-site
 // group and source, in the same order for any number of sources, so a
 // batched solve reduces exactly like a single one.

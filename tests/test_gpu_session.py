@@ -94,3 +94,20 @@ def test_session_failure_isolated():
     x3, r3, rc3 = s.read(1, 1)
     assert rc3 == 0 and np.array_equal(x3.cpu().numpy(), x0.cpu().numpy())
     s.close()
+
+
+def test_served_stream_results_equal_standalone():
+    """A small Poisson stream through the continuous-batching server on the GPU:
+    each request's solution equals its standalone solve bit for bit."""
+    from paper_2405_19294_amd import serve
+    be = serve.GpuBackend(inner_dtype="f32", tol=1e-10)
+    reqs = serve.poisson_stream(10, rate=100.0, seed=9, volumes=[(4, 4, 4, 8), (8, 4, 4, 4)],
+                                reps=[(2, "fund"), (2, "adj"), (3, "fund"), (4, "asym")], max_rhs=4)
+    srv = serve.Server(be, hbm_budget=8 << 30, n_slots=6, step_iters=10, keep_x=True)
+    rep = srv.run(reqs, realtime=True)
+    assert rep["done"] == len(reqs), rep
+    for r in reqs:
+        x, res, rc = be.solve_alone(r)
+        assert rc == 0
+        assert np.array_equal(r.x.cpu().numpy(), x.cpu().numpy()), r.rid
+        assert max(r.true_rel_resid) <= 1e-10
