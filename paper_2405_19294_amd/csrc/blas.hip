@@ -351,9 +351,7 @@ hipError_t launch_restart(const double *r64, double *r, double *p, const int *du
 // sum of nparts partials of one rhs, in a fixed order; valid in thread 0
 static __device__ double sum_parts(const double *partial, int nparts, double *sh)
 {
-    double s = 0;
-    for (int k = threadIdx.x; k < nparts; k += blockDim.x) s += partial[k];
-    return block_sum(s, sh);
+    return block_sum(strided_sum(partial, threadIdx.x, nparts, blockDim.x), sh);
 }
 
 __global__ void __launch_bounds__(WG) sum_partials_kernel(const double *partial, int pstride, int nparts,

@@ -681,8 +681,7 @@ __global__ void __launch_bounds__(WG) cg_reliable_kernel(CgState *cs, const doub
 {
     __shared__ double sh[WG / 64];
     const int rhs = blockIdx.x;
-    double s = 0;
-    for (int k = threadIdx.x; k < nparts; k += blockDim.x) s += partial[(size_t)rhs * pstride + k];
+    double s = strided_sum(partial + (size_t)rhs * pstride, threadIdx.x, nparts, blockDim.x);
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
     __syncthreads();

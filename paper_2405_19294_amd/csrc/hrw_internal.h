@@ -197,6 +197,27 @@ __device__ inline void store_c_nt<f16_t>(cpx<f16_t> *p, float re, float im)
     __builtin_nontemporal_store(w, (uint32_t *)p);
 }
 
+// ------------------------------------------------------------------ reductions
+
+// Sum of p[k] for k = first, first + step, ... below n, added in increasing k.
+// Loads are issued eight at a time before the additions, so a thread keeps
+// eight requests in flight; the order of the additions (and so the result) is
+// that of the plain one-at-a-time loop.
+__device__ inline double strided_sum(const double *p, int first, int n, int step)
+{
+    double s = 0;
+    int k = first;
+    for (; k + 7 * step < n; k += 8 * step) {
+        double v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = p[k + j * step];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s += v[j];
+    }
+    for (; k < n; k += step) s += p[k];
+    return s;
+}
+
 // ------------------------------------------------------------------ geometry
 
 struct Geom {
