@@ -293,7 +293,7 @@ def workload_c3(args):
         ref = None
         for inner in ["f64", "f32", "bf16", "f16"]:
             prm = hrw.solve_params(tol=1e-10, max_iter=20000, system="ddag_d_eo", inner_dtype=inner,
-                                   reliable_every=50, theta=theta)
+                                   reliable_every=50, reliable_delta=hrw.RELIABLE_DELTA[inner], theta=theta)
             hrw.timing_enable(True)
             x, res, per, lat = _solve_timed(hrw, torch, g, b, kappa, prm, args.steps, args.warmup)
             r = _hop_roofline(hrw, f"hop_kernel<N_R={g.nr}, {inner}>")
@@ -330,7 +330,7 @@ def workload_c3(args):
     return _line(main["solves_per_s"], "solves/s", args.steps, args.warmup, main["ms_per_solve"], "f32",
                  {"workload": "su4_asym_24^3x48_mixed_cg", "lattice": list(dims), "kappa": kappa,
                   "reps": ["SU(2) adj", "SU(4) asym"], "inner": ["f64", "f32", "bf16", "f16"],
-                  "reliable_every": 50, "tol": 1e-10}, roof, cases=cases)
+                  "reliable_every": 50, "reliable_delta": hrw.RELIABLE_DELTA, "tol": 1e-10}, roof, cases=cases)
 
 
 def workload_c4(args):
@@ -355,11 +355,13 @@ def workload_c4(args):
     prm64 = hrw.solve_params(tol=1e-10, max_iter=20000, system="ddag_d_eo", inner_dtype="f64", theta=theta)
     x64, res64, per64, _ = _solve_timed(hrw, torch, g, srcs[0:1].contiguous(), kappa, prm64, max(1, args.steps // 2), 1)
     fp64_rate = 1.0 / per64
+    # the same FP64 CG batched over all sources (links shared): context only
+    _, res64b, per64b, _ = _solve_timed(hrw, torch, g, srcs, kappa, prm64, 1, 0)
     out = {}
     roof = None
     for n in (12, 24):
         prm = hrw.solve_params(tol=1e-10, max_iter=20000, system="ddag_d_eo", inner_dtype="f32",
-                               reliable_every=50, theta=theta)
+                               reliable_every=50, reliable_delta=hrw.RELIABLE_DELTA["f32"], theta=theta)
         b = srcs[:n].contiguous()
         hrw.timing_enable(True)
         x, res, per, lat = _solve_timed(hrw, torch, g, b, kappa, prm, max(1, args.steps // 2), 1)
@@ -376,8 +378,12 @@ def workload_c4(args):
     return _line(out[24]["rhs_solves_per_s"], "rhs-solves/s", max(1, args.steps // 2), 1, out[24]["ms_per_batch"],
                  "f32", {"workload": "su3_sym_32^4_multi_source_mixed_cg", "lattice": list(dims), "kappa": kappa,
                          "sources": "point-smeared (Gaussian spatial profile, width 2), 12 and 24",
-                         "inner": "f32", "reliable_every": 50, "tol": 1e-10}, roof,
-                 fp64_cg={"solves_per_s": round(fp64_rate, 3), "iters": res64[0]["iters"]}, multi_source=out)
+                         "inner": "f32", "reliable_every": 50, "reliable_delta": hrw.RELIABLE_DELTA["f32"],
+                         "tol": 1e-10}, roof,
+                 fp64_cg={"solves_per_s": round(fp64_rate, 3), "iters": res64[0]["iters"],
+                          "batched_24_rhs_solves_per_s": round(nmax / per64b, 3),
+                          "batched_max_iters": max(q["iters"] for q in res64b)},
+                 multi_source=out)
 
 
 def workload_c5(args):

@@ -90,11 +90,54 @@ __device__ __forceinline__ void reconstruct(const A (&gr)[2][NR], const A (&gi)[
     }
 }
 
+// reconstruction for one colour row (the same table as reconstruct)
+template <int MU, int SG, class A>
+__device__ __forceinline__ void reconstruct_row(A g0r, A g0i, A g1r, A g1i, A &a0r, A &a0i, A &a1r, A &a1i,
+                                                A &a2r, A &a2i, A &a3r, A &a3i)
+{
+    const A s = (A)SG;
+    a0r += g0r; a0i += g0i;
+    a1r += g1r; a1i += g1i;
+    if (MU == 0) {
+        a2r -= s * g0r; a2i -= s * g0i;
+        a3r -= s * g1r; a3i -= s * g1i;
+    } else if (MU == 1) {
+        a2r -= s * g1i; a2i += s * g1r;
+        a3r -= s * g0i; a3i += s * g0r;
+    } else if (MU == 2) {
+        a2r += s * g1r; a2i += s * g1i;
+        a3r -= s * g0r; a3i -= s * g0i;
+    } else {
+        a2r -= s * g0i; a2i += s * g0r;
+        a3r += s * g1i; a3i -= s * g1r;
+    }
+}
+
+// g = U h for one link row (ur, ui) and both half-spinor components, as
+// chains of fused multiply-adds (four per complex product)
+template <class A, int NR>
+__device__ __forceinline__ void link_row(const A (&ur)[NR], const A (&ui)[NR], const A (&hr)[2][NR],
+                                         const A (&hi)[2][NR], A &s0r, A &s0i, A &s1r, A &s1i)
+{
+    s0r = ur[0] * hr[0][0]; s0i = ur[0] * hi[0][0];
+    s1r = ur[0] * hr[1][0]; s1i = ur[0] * hi[1][0];
+    s0r = fmac(-ui[0], hi[0][0], s0r); s0i = fmac(ui[0], hr[0][0], s0i);
+    s1r = fmac(-ui[0], hi[1][0], s1r); s1i = fmac(ui[0], hr[1][0], s1i);
+#pragma unroll
+    for (int c = 1; c < NR; ++c) {
+        s0r = fmac(ur[c], hr[0][c], s0r); s0r = fmac(-ui[c], hi[0][c], s0r);
+        s0i = fmac(ur[c], hi[0][c], s0i); s0i = fmac(ui[c], hr[0][c], s0i);
+        s1r = fmac(ur[c], hr[1][c], s1r); s1r = fmac(-ui[c], hi[1][c], s1r);
+        s1i = fmac(ur[c], hi[1][c], s1i); s1i = fmac(ui[c], hr[1][c], s1i);
+    }
+}
+
 // Where a thread reads its links from: the packed field in HBM (streamed past
 // L2, each link is read once per launch) or a workgroup's LDS copy (the
 // multi-source kernel).  The arithmetic is the same either way.
 template <class S, int NR>
 struct GlobalLinks {
+    static constexpr bool ROWWISE = false;  // all rows' loads issued up front (HBM latency)
     const cpx<S> *__restrict__ g;
     int i;
     __device__ __forceinline__ void load(int comp, typename acc_of<S>::type &re,
@@ -106,6 +149,7 @@ struct GlobalLinks {
 
 template <class S>
 struct LdsLinks {
+    static constexpr bool ROWWISE = true;  // one row at a time: fewer live registers
     const cpx<S> *l;  // [comp][MR_SITES]
     int s;
     __device__ __forceinline__ void load(int comp, typename acc_of<S>::type &re,
@@ -144,11 +188,15 @@ __device__ __forceinline__ void hop_dir(const HopArgs<S> &a, const cpx<S> *__res
 #pragma unroll
         for (int c = 0; c < NR; ++c) load_c(in + lay(j, sp * NR + c, NC), pr[sp][c], pi[sp][c]);
     constexpr int DD = MU + 4 * DIR;
-    A ur[RS][NR], ui[RS][NR];
+    // links from HBM: every row's loads are issued together with the spinor's,
+    // before any arithmetic waits on them (unused when links come from LDS)
+    A ur[LS::ROWWISE ? 1 : RS][NR], ui[LS::ROWWISE ? 1 : RS][NR];
+    if (!LS::ROWWISE) {
 #pragma unroll
-    for (int r = 0; r < RS; ++r)
+        for (int r = 0; r < RS; ++r)
 #pragma unroll
-        for (int c = 0; c < NR; ++c) links.load(DD * NR * NR + (r0 + r) * NR + c, ur[r][c], ui[r][c]);
+            for (int c = 0; c < NR; ++c) links.load(DD * NR * NR + (r0 + r) * NR + c, ur[r][c], ui[r][c]);
+    }
     A hr[2][NR], hi[2][NR];
     project<MU, SG>(pr, pi, hr, hi);
     if (wrap) {
@@ -164,21 +212,24 @@ __device__ __forceinline__ void hop_dir(const HopArgs<S> &a, const cpx<S> *__res
                 hi[k][c] = ti;
             }
     }
-    A gr[2][RS], gi[2][RS];
+    if (LS::ROWWISE) {
+        // links from LDS: fetch, multiply and reconstruct one row at a time
 #pragma unroll
-    for (int r = 0; r < RS; ++r) {
-        A s0r = 0, s0i = 0, s1r = 0, s1i = 0;
+        for (int r = 0; r < RS; ++r) {
+            A lr[NR], li[NR];
 #pragma unroll
-        for (int c = 0; c < NR; ++c) {
-            s0r += ur[r][c] * hr[0][c] - ui[r][c] * hi[0][c];
-            s0i += ur[r][c] * hi[0][c] + ui[r][c] * hr[0][c];
-            s1r += ur[r][c] * hr[1][c] - ui[r][c] * hi[1][c];
-            s1i += ur[r][c] * hi[1][c] + ui[r][c] * hr[1][c];
+            for (int c = 0; c < NR; ++c) links.load(DD * NR * NR + (r0 + r) * NR + c, lr[c], li[c]);
+            A s0r, s0i, s1r, s1i;
+            link_row(lr, li, hr, hi, s0r, s0i, s1r, s1i);
+            reconstruct_row<MU, SG>(s0r, s0i, s1r, s1i, ar[0][r], ai[0][r], ar[1][r], ai[1][r], ar[2][r],
+                                    ai[2][r], ar[3][r], ai[3][r]);
         }
-        gr[0][r] = s0r; gi[0][r] = s0i;
-        gr[1][r] = s1r; gi[1][r] = s1i;
+    } else {
+        A gr[2][RS], gi[2][RS];
+#pragma unroll
+        for (int r = 0; r < RS; ++r) link_row(ur[r], ui[r], hr, hi, gr[0][r], gi[0][r], gr[1][r], gi[1][r]);
+        reconstruct<MU, SG>(gr, gi, ar, ai);
     }
-    reconstruct<MU, SG>(gr, gi, ar, ai);
     // Materialise the accumulators here.  Without this the optimiser sinks
     // every direction's "acc += g" to the end of the kernel, keeping all eight
     // directions' products live at once (256 VGPRs and spills even for N_R=2).

