@@ -383,7 +383,7 @@ def workload_c4(args):
                  fp64_cg={"solves_per_s": round(fp64_rate, 3), "iters": res64[0]["iters"],
                           "batched_24_rhs_solves_per_s": round(nmax / per64b, 3),
                           "batched_max_iters": max(q["iters"] for q in res64b)},
-                 multi_source=out)
+                 multi_source=out, hbm_copy_reference=copy_reference(torch, dev))
 
 
 def workload_c5(args):
