@@ -26,6 +26,8 @@
 // backward hop s = +1; H^+ swaps them.
 #pragma once
 
+#include <mutex>
+
 #include "kernels.h"
 
 namespace hrw {
@@ -393,17 +395,24 @@ __global__ void __launch_bounds__(WG) hop_kernel(const HopArgs<S> a)
 
 // Multi-source kernel: a workgroup owns MR_SITES sites and every source.  It
 // copies the sites' links (all 8 directions) into LDS once, then its threads
-// run the per-site hop for RT sources at a time, reading links from LDS: each
-// link crosses HBM once per launch however many sources there are.
+// run the per-site hop reading links from LDS: each link crosses HBM once per
+// launch however many sources there are.  The workgroup has as many threads as
+// (source, site, row group) items, up to MR_MAX_THREADS per round (see
+// mr_threads), so a round is never partly idle.  Thread t keeps its site and
+// row group in every round; only the source advances.
+template <class S, int NR> struct MRW { static constexpr int value = NR <= 6 ? 3 : 2; };
+template <int NR> struct MRW<double, NR> { static constexpr int value = 2; };
+
 template <int NR, int RS, class S, bool DAG, int EPI>
-__global__ void __launch_bounds__(WG) hop_mrhs_kernel(const HopArgs<S> a)
+__global__ void __launch_bounds__(MR_MAX_THREADS) __attribute__((amdgpu_waves_per_eu(MRW<S, NR>::value)))
+hop_mrhs_kernel(const HopArgs<S> a)
 {
     constexpr int G = NR / RS;
     constexpr int GC = 8 * NR * NR;
-    constexpr int RT = WG / (MR_SITES * G);  // sources in flight per workgroup
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<S> *lk = (cpx<S> *)smem_raw;
-    __shared__ double sh[WG / 64];
+    __shared__ double sh[MR_MAX_THREADS / 64];
+    const int nt = blockDim.x;  // a multiple of 64 and of PG_SITES * G
     int parity = a.parity, bx = blockIdx.x;
     if (parity < 0) {
         parity = bx >= a.grid_half;
@@ -412,7 +421,7 @@ __global__ void __launch_bounds__(WG) hop_mrhs_kernel(const HopArgs<S> a)
     bx = tile_remap(xcd_remap(bx, a.grid_half), a.grid_half, a.tile_ts, a.tile_c);
     const int i0 = bx * MR_SITES;
     const cpx<S> *__restrict__ gauge = a.gauge[parity];
-    for (int e = threadIdx.x; e < GC * MR_SITES; e += WG) {
+    for (int e = threadIdx.x; e < GC * MR_SITES; e += nt) {
         const int comp = e / MR_SITES, s = e - comp * MR_SITES;
         const int i = i0 + s;
         cpx<S> v;
@@ -431,11 +440,11 @@ __global__ void __launch_bounds__(WG) hop_mrhs_kernel(const HopArgs<S> a)
     const int t = threadIdx.x;
     const int rg = t % G;
     const int s = (t / G) % MR_SITES;
-    const int jl = t / (MR_SITES * G);
     const int i = i0 + s;
     LdsLinks<S> links{lk, s};
-    for (int j0 = 0; j0 < a.n_rhs; j0 += RT) {
-        const int rhs = j0 + jl;
+    const int items = MR_SITES * G * a.n_rhs;
+    for (int e0 = 0; e0 < items; e0 += nt) {
+        const int rhs = (e0 + t) / (MR_SITES * G);
         double nrm = 0;
         if (i < a.g.half && rhs < a.n_rhs) nrm = site_hop<NR, RS, S, DAG, EPI>(a, parity, i, rg * RS, rhs, links);
         if (EPI != EPI_PLAIN && a.partial) {
@@ -466,13 +475,38 @@ inline void hop_tiling(const Geom &g, int sites_per_wg, int *ts, int *c)
 template <class S> constexpr int dtype_id() { return 1; }
 template <> constexpr int dtype_id<double>() { return 0; }
 
+// Workgroup size of one multi-source kernel instance for n_rhs sources, from
+// the runtime's occupancy figure for each candidate size (queried once per
+// instance and size; lds is fixed per instance).
+template <int NR, int RS, class S, bool D, int E>
+int mr_block(int n_rhs, size_t lds)
+{
+    static int occ[MR_MAX_THREADS / 64 + 1] = {};
+    static std::mutex mu;
+    auto blocks_per_cu = [&](int t) {
+        std::lock_guard<std::mutex> lock(mu);
+        int &o = occ[t / 64];
+        if (!o) {
+            int nb = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, hop_mrhs_kernel<NR, RS, S, D, E>, t, lds) !=
+                    hipSuccess || nb < 1)
+                nb = 1;
+            o = nb;
+        }
+        return o;
+    };
+    return mr_threads(NR / RS, n_rhs, blocks_per_cu);
+}
+
 template <int NR, int RS, class S, bool MRK>
 void launch_hop_rs(bool dagger, int epi, dim3 grid, size_t lds, const HopArgs<S> &b, hipStream_t st)
 {
-#define HRW_LAUNCH(D, E)                                                               \
-    do {                                                                               \
-        if (MRK) hop_mrhs_kernel<NR, RS, S, D, E><<<grid, WG, lds, st>>>(b);           \
-        else hop_kernel<NR, RS, S, D, E><<<grid, WG, 0, st>>>(b);                      \
+#define HRW_LAUNCH(D, E)                                                                           \
+    do {                                                                                           \
+        if (MRK)                                                                                   \
+            hop_mrhs_kernel<NR, RS, S, D, E><<<grid, dim3(mr_block<NR, RS, S, D, E>(b.n_rhs, lds)), \
+                                                lds, st>>>(b);                                     \
+        else hop_kernel<NR, RS, S, D, E><<<grid, WG, 0, st>>>(b);                                  \
     } while (0)
     if (epi == EPI_PLAIN) {
         if (dagger) HRW_LAUNCH(true, EPI_PLAIN);

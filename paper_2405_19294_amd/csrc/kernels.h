@@ -95,12 +95,43 @@ constexpr int hop_rows(int nr, int dt)
 constexpr int HOP_MAX_G = 8;  // largest threads-per-site of any instance
 constexpr int PG_SITES = 16;  // sites per FP64 partial-sum group of the hopping kernels
 constexpr int MR_SITES = 16;  // sites per workgroup of the multi-source hopping kernel
+constexpr int MR_MAX_THREADS = 256;  // largest multi-source workgroup
+
+// Threads of a multi-source workgroup for n_rhs sources.  The MR_SITES x g x
+// n_rhs (source, site, row group) items run in rounds of `threads` (a whole
+// number of wavefronts and of 16-site partial-sum groups); the choice
+// maximises blocks_per_cu(threads) x items per round, i.e. the busy lanes a CU
+// holds on average.  Ties go to the larger workgroup.
+template <class F>
+inline int mr_threads(int g, int n_rhs, F blocks_per_cu)
+{
+    const long items = (long)MR_SITES * g * n_rhs;
+    const int unit = PG_SITES * g > 64 ? PG_SITES * g : 64;
+    int best = MR_MAX_THREADS;
+    double best_score = -1;
+    for (int t = MR_MAX_THREADS; t >= unit; t -= 64) {
+        if (t % unit) continue;
+        const long rounds = (items + t - 1) / t;
+        const double score = (double)blocks_per_cu(t) * (double)items / (double)rounds;
+        if (score > best_score) {
+            best_score = score;
+            best = t;
+        }
+    }
+    return best;
+}
+
+// Fewest sources for which the multi-source kernel beats one single-source
+// launch row per source (measured at 32^4: N_R <= 4 from 3 sources; N_R >= 6
+// from 4 in FP64 and from 6 in 32-bit storage, whose single-source kernel is
+// relatively faster).
+constexpr int mrhs_min_sources(int nr, int dt) { return nr < 6 ? 3 : (dt == 0 ? 4 : 6); }
 
 // Whether a launch with n_rhs sources runs the multi-source kernel (links
 // shared through LDS); else one grid row per source re-reads the links.
 constexpr bool hop_uses_mrhs(int nr, int dt, int n_rhs)
 {
-    return n_rhs > 1 && (nr / hop_rows(nr, dt)) * MR_SITES <= WG / 2;
+    return n_rhs >= mrhs_min_sources(nr, dt) && (nr / hop_rows(nr, dt)) * MR_SITES <= WG / 2;
 }
 
 // Partial sums per parity written by one hopping launch: one per 16-site

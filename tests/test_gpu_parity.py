@@ -131,6 +131,31 @@ def test_multi_rhs_apply_equals_single():
         fp64_close(many[k], orc.deo(dims, ur, ks[k], pe[k], THETA_AP))
 
 
+# (colours, representation, storage, sources): source counts that need one
+# round, several rounds and a ragged last round of the multi-source kernel,
+# with one, two and eight threads per site
+MULTI_SOURCE_CASES = [(3, "fund", "f64", 40), (3, "fund", "f32", 40), (3, "sym", "f64", 17), (3, "sym", "f32", 24),
+                      (3, "adj", "f64", 5), (3, "adj", "f32", 7), (2, "fund", "bf16", 9), (4, "asym", "f16", 6), (4, "asym", "f32", 2)]
+
+
+@pytest.mark.parametrize("nc,rep,dtype,n", MULTI_SOURCE_CASES)
+@pytest.mark.parametrize("dims", [(2, 2, 2, 6), (4, 2, 4, 4)])
+def test_multi_source_kernel_equals_single(nc, rep, dtype, n, dims):
+    """Every source of a batched D_W and D_hat apply equals its single-source apply bit for bit
+    (the 24-site half lattice leaves a partly filled 16-site group); FP64 also matches the oracle."""
+    uf, ur, g = setup(dims, nc, rep, "haar", seed=31, dtypes=(dtype,))
+    psi = fx.gaussian_spinor(dims, g.nr, seed=32, n_rhs=n)
+    many = hrw.dw_apply(g, 0.12, to_dev(psi), THETA_TW, dtype).cpu().numpy()
+    pe = orc.split_eo(dims, psi)[0]
+    many_eo = hrw.deo_apply(g, 0.125, to_dev(pe), THETA_TW, dtype).cpu().numpy()
+    for k in range(n):
+        assert np.array_equal(many[k], hrw.dw_apply(g, 0.12, to_dev(psi[k]), THETA_TW, dtype).cpu().numpy())
+        assert np.array_equal(many_eo[k], hrw.deo_apply(g, 0.125, to_dev(pe[k]), THETA_TW, dtype).cpu().numpy())
+    if dtype == "f64":
+        for k in (0, n - 1):
+            fp64_close(many[k], orc.dw(dims, ur, 0.12, psi[k], THETA_TW))
+
+
 def test_thermal_links_c2_shape_small():
     """Near-thermal SU(3) links (eps = 0.3), the c2 link ensemble at 8^4."""
     dims = (8, 8, 8, 8)
