@@ -5,6 +5,7 @@ failure isolation and latency accounting."""
 import numpy as np
 
 from paper_2405_19294_amd import serve
+from serve_fakes import OracleBackend
 
 SMALL = [(4, 4, 4, 4), (2, 4, 4, 4)]
 REPS = [(2, "fund"), (3, "fund")]
@@ -23,7 +24,7 @@ def test_stream_is_seeded_and_poisson_like():
 
 
 def test_all_served_results_equal_standalone_and_slots_reused():
-    be = serve.OracleBackend()
+    be = OracleBackend()
     reqs = stream()
     srv = serve.Server(be, hbm_budget=1 << 40, n_slots=4, keep_x=True)
     rep = srv.run(reqs, realtime=False)
@@ -38,7 +39,7 @@ def test_all_served_results_equal_standalone_and_slots_reused():
 
 
 def test_admission_by_footprint_parks_then_serves():
-    be = serve.OracleBackend(session_bytes_per_slot=100)
+    be = OracleBackend(session_bytes_per_slot=100)
     reqs = stream(n=10)
     keys = {r.key for r in reqs}
     assert len(keys) > 1
@@ -50,13 +51,13 @@ def test_admission_by_footprint_parks_then_serves():
 
 
 def test_refusals():
-    be = serve.OracleBackend(session_bytes_per_slot=100)
+    be = OracleBackend(session_bytes_per_slot=100)
     reqs = stream(n=6, max_rhs=3)
     reqs[0].n_rhs = 9                      # more sources than slots
     srv = serve.Server(be, hbm_budget=1 << 30, n_slots=4)
     rep = srv.run(reqs, realtime=False)
     assert reqs[0].status == "refused" and rep["refused"] == 1 and rep["done"] == len(reqs) - 1
-    tiny = serve.Server(serve.OracleBackend(session_bytes_per_slot=10 ** 9), hbm_budget=10 ** 6, n_slots=4)
+    tiny = serve.Server(OracleBackend(session_bytes_per_slot=10 ** 9), hbm_budget=10 ** 6, n_slots=4)
     rep = tiny.run(stream(n=3), realtime=False)
     assert rep["refused"] == 3
 
@@ -64,7 +65,7 @@ def test_refusals():
 def test_failure_is_isolated():
     reqs = stream(n=12)
     bad = reqs[0].key
-    be = serve.OracleBackend(fail_keys=[bad])
+    be = OracleBackend(fail_keys=[bad])
     srv = serve.Server(be, hbm_budget=1 << 40, n_slots=4)
     rep = srv.run(reqs, realtime=False)
     n_bad = sum(r.key == bad for r in reqs)
@@ -73,7 +74,7 @@ def test_failure_is_isolated():
 
 
 def test_realtime_latency_includes_queueing():
-    be = serve.OracleBackend(iters_per_step=5)
+    be = OracleBackend(iters_per_step=5)
     reqs = stream(n=8, rate=50.0, max_rhs=2)
     srv = serve.Server(be, hbm_budget=1 << 40, n_slots=2)
     rep = srv.run(reqs, realtime=True)
