@@ -185,9 +185,73 @@ def main():
     }
 
     out["hbm_copy_reference"] = copy_reference(torch, dev)
+    out["operators"] = operator_table(torch, hrw, dev, dims, nc, rep, uf_d, kappa, theta,
+                                      out["hbm_copy_reference"]["gbs"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dims, uf, b, kappa, theta, r["iters"], args.cpu_iters)
     print(json.dumps(out), flush=True)
+
+
+def operator_table(torch, hrw, dev, dims, nc, rep, uf_d, kappa, theta, copy_gbs, reps=20):
+    """Single applies of D_W (full lattice) and D_hat (even sites) in FP64 and FP32.
+
+    Per call: the hopping kernels' time from HIP events on the launch stream
+    (library timing) and the whole call (canonical-layout packing included).
+    Byte and flop models per unit, N = N_R, c = bytes per complex:
+      D_W   per site:      min traffic (every link once) c (4N^2 + 8N);
+                           as streamed (each link read by both of its sites) c (8N^2 + 12N);
+                           flops 128N^2 + 72N
+      D_hat per even site: c (16N^2 + 20N) (min traffic = as streamed);
+                           flops 2 (128N^2 + 56N) + 8N
+    """
+    v = int(np.prod(dims))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11)
+    g = hrw.Gauge(dims, nc, rep, uf_d, dtypes=("f64", "f32"))
+    n = g.nr
+    psi = torch.complex(torch.randn((v, 4, n), generator=gen, device=dev, dtype=torch.float64),
+                        torch.randn((v, 4, n), generator=gen, device=dev, dtype=torch.float64)) * np.sqrt(0.5)
+    pe = psi[: v // 2].contiguous()
+    out_f, out_e = torch.empty_like(psi), torch.empty_like(pe)
+    ws = hrw.Workspace.for_apply(g, 1)
+    rows = {}
+    for dt, cb in (("f64", 16), ("f32", 8)):
+        for op in ("dw", "deo"):
+            def call():
+                if op == "dw":
+                    hrw.dw_apply(g, kappa, psi, theta, dt, out=out_f, ws=ws)
+                else:
+                    hrw.deo_apply(g, kappa, pe, theta, dt, out=out_e, ws=ws)
+            for _ in range(3):
+                call()
+            torch.cuda.synchronize()
+            hrw.timing_enable(True)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                call()
+            e1.record()
+            torch.cuda.synchronize()
+            hop = hrw.timing_read(0)
+            hrw.timing_enable(False)
+            hop_us = hop["ms"] * 1e3 / reps
+            if op == "dw":
+                b_min = cb * (4 * n * n + 8 * n) * v
+                b_str = cb * (8 * n * n + 12 * n) * v
+                flops = (128 * n * n + 72 * n) * v
+            else:
+                b_min = b_str = cb * (16 * n * n + 20 * n) * (v // 2)
+                flops = (2 * (128 * n * n + 56 * n) + 8 * n) * (v // 2)
+            gbs = b_min / (hop_us * 1e-6) / 1e9
+            rows[f"{op}_{dt}"] = {
+                "hop_us": round(hop_us, 1), "call_us": round(e0.elapsed_time(e1) * 1e3 / reps, 1),
+                "bytes_min": b_min, "GBs_min": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+                "frac_of_copy": round(gbs / copy_gbs, 3),
+                "GBs_as_streamed": round(b_str / (hop_us * 1e-6) / 1e9, 1),
+                "GFLOPs": round(flops / (hop_us * 1e-6) / 1e9, 1)}
+            log(f"{op} {dt}: {rows[f'{op}_{dt}']}")
+    g.close()
+    return rows
 
 
 # ---------------------------------------------------------------- other workloads
@@ -408,6 +472,25 @@ def workload_c5(args):
             log(f"c5: {done}/{n} requests done")
     rep = srv.run(reqs, realtime=True, on_progress=progress)
     lat = rep["latency_s"]
+    # arrival-rate sweep: 20 s of arrivals at each lower rate (the 20/s row is
+    # the main stream above); the highest rate whose p99 latency stays within
+    # twice the p99 service time (at most as much queueing as service) is
+    # reported as sustainable
+    sweep, bounded = [], None
+    for rate in (1.0, 2.0, 5.0, 10.0, 20.0):
+        if rate == 20.0:
+            sreqs, r = reqs, rep
+        else:
+            sreqs = serve.poisson_stream(int(20 * rate), rate=rate, seed=5)
+            r = serve.Server(be, hbm_budget=budget, n_slots=12, step_iters=20).run(sreqs, realtime=True)
+        ms = lambda v: None if v is None else round(v * 1e3, 1)  # noqa: E731
+        row = {"rate_per_s": rate, "p50_ms": ms(r["latency_s"]["p50"]), "p99_ms": ms(r["latency_s"]["p99"]),
+               "service_p99_ms": ms(r["service_s"]["p99"]),
+               "rhs_solves_per_s": round(r["rhs_solves_per_s"], 3), "done": r["done"], "refused": r["refused"]}
+        sweep.append(row)
+        log(f"c5 sweep: {row}")
+        if r["done"] == len(sreqs) and r["latency_s"]["p99"] <= 2.0 * r["service_s"]["p99"]:
+            bounded = rate
     return _line(round(rep["rhs_solves_per_s"], 3), "rhs-solves/s", len(reqs), 0,
                  round(rep["wall_s"] * 1e3 / max(rep["done"], 1), 3), "f32",
                  {"workload": "serving_poisson_20hz_400req", "rate_per_s": 20.0, "requests": len(reqs),
@@ -417,7 +500,8 @@ def workload_c5(args):
                  latency_ms={"p50": round(lat["p50"] * 1e3, 1), "p99": round(lat["p99"] * 1e3, 1),
                              "max": round(lat["max"] * 1e3, 1)},
                  service_ms={k: round(v * 1e3, 1) for k, v in rep["service_s"].items()},
-                 report={k: v for k, v in rep.items() if k not in ("latency_s", "service_s")})
+                 report={k: v for k, v in rep.items() if k not in ("latency_s", "service_s")},
+                 rate_sweep=sweep, highest_rate_with_bounded_p99=bounded)
 
 
 def copy_reference(torch, dev, nbytes=1 << 30, reps=10):
