@@ -156,6 +156,28 @@ def test_multi_source_kernel_equals_single(nc, rep, dtype, n, dims):
             fp64_close(many[k], orc.dw(dims, ur, 0.12, psi[k], THETA_TW))
 
 
+@pytest.mark.parametrize("nc,rep,n", [(3, "sym", 6), (3, "sym", 7), (4, "asym", 24)])
+@pytest.mark.parametrize("dims", [(2, 2, 2, 6), (4, 2, 4, 4)])
+def test_mfma_multi_source_within_fp32_bound(nc, rep, n, dims, monkeypatch):
+    """The matrix-core multi-source kernel (opt-in, FP32, N_R = 6): every source of a batched D_W
+    meets the FP32 a-priori bound against the oracle, and of D_hat and D_hat^+ agrees with the
+    vector kernel's single-source apply to FP32 rounding."""
+    uf, ur, g = setup(dims, nc, rep, "haar", seed=41, dtypes=("f32",))
+    psi = fx.gaussian_spinor(dims, g.nr, seed=42, n_rhs=n)
+    pe = orc.split_eo(dims, psi)[0]
+    monkeypatch.setenv("HRW_MRHS_MFMA", "1")
+    many = hrw.dw_apply(g, 0.12, to_dev(psi), THETA_TW, "f32").cpu().numpy()
+    many_eo = [hrw.deo_apply(g, 0.125, to_dev(pe), THETA_TW, "f32", dagger=d).cpu().numpy() for d in (False, True)]
+    monkeypatch.delenv("HRW_MRHS_MFMA")
+    ur_r = orc.round_to("f32", ur)
+    for k in range(n):
+        psi_r = orc.round_to("f32", psi[k])
+        _bound_check(dims, ur_r, psi_r, 0.12, many[k], orc.dw(dims, ur_r, 0.12, psi_r, THETA_TW), g.nr, U32)
+        for d in (False, True):
+            one = hrw.deo_apply(g, 0.125, to_dev(pe[k]), THETA_TW, "f32", dagger=d).cpu().numpy()
+            assert np.max(np.abs(many_eo[d][k] - one)) <= 1e-6 * np.max(np.abs(one))
+
+
 def test_thermal_links_c2_shape_small():
     """Near-thermal SU(3) links (eps = 0.3), the c2 link ensemble at 8^4."""
     dims = (8, 8, 8, 8)
