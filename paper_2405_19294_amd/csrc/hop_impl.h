@@ -26,7 +26,12 @@
 // backward hop s = +1; H^+ swaps them.
 #pragma once
 
+#include <stdlib.h>
+
+#include <array>
+#include <map>
 #include <mutex>
+#include <utility>
 
 #include "kernels.h"
 
@@ -256,7 +261,7 @@ __device__ __forceinline__ int xcd_remap(int b, int n)
 // whole time slice apart (which exceeds an XCD's L2 at 32^4).
 __device__ __forceinline__ int tile_remap(int L, int n, int ts, int c)
 {
-    if (ts <= 0) return L;
+    if (ts <= 0 || c <= 0) return L;
     const int T = n / ts;
     const int ch = L / (c * T);
     const int rem = L - ch * c * T;
@@ -457,7 +462,7 @@ hop_mrhs_kernel(const HopArgs<S> a)
 
 // Tiling of the work order (see tile_remap); disabled unless every time slice
 // holds a whole number of workgroups.
-inline void hop_tiling(const Geom &g, int sites_per_wg, int *ts, int *c)
+inline void hop_tiling(const Geom &g, int sites_per_wg, int *ts, int *c, int cmax = 16)
 {
     *ts = 0;
     *c = 0;
@@ -466,7 +471,7 @@ inline void hop_tiling(const Geom &g, int sites_per_wg, int *ts, int *c)
     const int n = (int)(per_slice / sites_per_wg);
     if (n < 2) return;
     int best = 1;
-    for (int k = 1; k <= 16 && k <= n; ++k)
+    for (int k = 1; k <= cmax && k <= n; ++k)
         if (n % k == 0) best = k;
     *ts = n;
     *c = best;
@@ -498,15 +503,137 @@ int mr_block(int n_rhs, size_t lds)
     return mr_threads(NR / RS, n_rhs, blocks_per_cu);
 }
 
+// ------------------------------------------------------------ launch-shape tuning
+//
+// Launch shape of the multi-source kernel: threads per workgroup and the
+// spatial chunk of the time-tiled walk.  Neither changes any result (the
+// partial sums are per 16-site group, the per-source arithmetic is fixed), so
+// the shape is picked by timing.  On the first plain-epilogue launch of each
+// (instance family, sources, half volume) the candidates — every admissible
+// workgroup size x chunk 16 or 4 — run twice each on the caller's stream and
+// the fastest is kept for every epilogue of that key for the life of the
+// process.  Until a key is tuned (or with HRW_TUNE=0, or while the stream is
+// being captured into a graph) the occupancy model (mr_block) and chunk 16
+// are used.
+struct MrShape {
+    int threads;
+    int cmax;  // chunk limit handed to hop_tiling (the chunk itself follows the launch's geometry)
+};
+
+inline bool mr_tuning_enabled()
+{
+    const char *e = getenv("HRW_TUNE");
+    return !(e && e[0] == '0');
+}
+
+template <int NR, int RS, class S>
+struct MrTuner {
+    typedef std::array<int, 5> Key;  // sources and the four extents
+    std::mutex mu;
+    std::map<Key, MrShape> best;
+
+    static Key key(const HopArgs<S> &b) { return Key{b.n_rhs, b.g.d[0], b.g.d[1], b.g.d[2], b.g.d[3]}; }
+
+    bool lookup(const HopArgs<S> &b, MrShape *out)
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = best.find(key(b));
+        if (it == best.end()) return false;
+        *out = it->second;
+        return true;
+    }
+
+    // time every candidate with the plain epilogue (out = H in: re-running it is
+    // harmless); returns the fastest, or false if timing was not possible
+    template <bool D>
+    bool tune(const HopArgs<S> &b0, size_t lds, dim3 grid, hipStream_t st, MrShape *out)
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = best.find(key(b0));
+        if (it != best.end()) {
+            *out = it->second;
+            return true;
+        }
+        constexpr int G = NR / RS;
+        const int unit = PG_SITES * G > 64 ? PG_SITES * G : 64;
+        hipEvent_t ev[2];
+        if (hipEventCreate(&ev[0]) != hipSuccess) return false;
+        if (hipEventCreate(&ev[1]) != hipSuccess) {
+            (void)hipEventDestroy(ev[0]);
+            return false;
+        }
+        float best_ms = 0;
+        MrShape pick{0, 0};
+        bool ok = true;
+        int ts16 = 0, c16 = 0;
+        hop_tiling(b0.g, MR_SITES, &ts16, &c16, 16);
+        for (int cmax : {16, 4}) {
+            HopArgs<S> b = b0;
+            hop_tiling(b.g, MR_SITES, &b.tile_ts, &b.tile_c, cmax);
+            if (cmax == 4 && b.tile_c == c16) continue;  // no distinct chunk
+            for (int t = MR_MAX_THREADS; t >= unit && ok; t -= 64) {
+                if (t % unit) continue;
+                float ms = 0;
+                for (int rep = 0; rep < 2 && ok; ++rep) {
+                    ok = hipEventRecord(ev[0], st) == hipSuccess;
+                    hop_mrhs_kernel<NR, RS, S, D, EPI_PLAIN><<<grid, dim3(t), lds, st>>>(b);
+                    ok = ok && hipGetLastError() == hipSuccess && hipEventRecord(ev[1], st) == hipSuccess &&
+                         hipEventSynchronize(ev[1]) == hipSuccess;
+                    float e = 0;
+                    ok = ok && hipEventElapsedTime(&e, ev[0], ev[1]) == hipSuccess;
+                    if (ok && (rep == 0 || e < ms)) ms = e;
+                }
+                if (ok && (pick.threads == 0 || ms < best_ms)) {
+                    best_ms = ms;
+                    pick = MrShape{t, cmax};
+                }
+            }
+        }
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+        if (!ok || pick.threads == 0) return false;
+        best[key(b0)] = pick;
+        *out = pick;
+        return true;
+    }
+};
+
+template <int NR, int RS, class S>
+MrTuner<NR, RS, S> &mr_tuner()
+{
+    static MrTuner<NR, RS, S> t;
+    return t;
+}
+
+// shape for this launch (see MrTuner); tunes on a plain-epilogue launch
+template <int NR, int RS, class S, bool D, int E>
+MrShape mr_shape(const HopArgs<S> &b, size_t lds, dim3 grid, hipStream_t st)
+{
+    MrShape sh;
+    auto &tuner = mr_tuner<NR, RS, S>();
+    if (tuner.lookup(b, &sh)) return sh;
+    if (E == EPI_PLAIN && mr_tuning_enabled()) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone &&
+            tuner.template tune<D>(b, lds, grid, st, &sh))
+            return sh;
+    }
+    return MrShape{mr_block<NR, RS, S, D, E>(b.n_rhs, lds), 16};
+}
+
 template <int NR, int RS, class S, bool MRK>
 void launch_hop_rs(bool dagger, int epi, dim3 grid, size_t lds, const HopArgs<S> &b, hipStream_t st)
 {
 #define HRW_LAUNCH(D, E)                                                                           \
     do {                                                                                           \
-        if (MRK)                                                                                   \
-            hop_mrhs_kernel<NR, RS, S, D, E><<<grid, dim3(mr_block<NR, RS, S, D, E>(b.n_rhs, lds)), \
-                                                lds, st>>>(b);                                     \
-        else hop_kernel<NR, RS, S, D, E><<<grid, WG, 0, st>>>(b);                                  \
+        if (MRK) {                                                                                 \
+            const MrShape sh = mr_shape<NR, RS, S, D, E>(b, lds, grid, st);                        \
+            HopArgs<S> bt = b;                                                                     \
+            hop_tiling(bt.g, MR_SITES, &bt.tile_ts, &bt.tile_c, sh.cmax);                          \
+            hop_mrhs_kernel<NR, RS, S, D, E><<<grid, dim3(sh.threads), lds, st>>>(bt);             \
+        } else {                                                                                   \
+            hop_kernel<NR, RS, S, D, E><<<grid, WG, 0, st>>>(b);                                   \
+        }                                                                                          \
     } while (0)
     if (epi == EPI_PLAIN) {
         if (dagger) HRW_LAUNCH(true, EPI_PLAIN);
