@@ -102,6 +102,7 @@ struct HopCall {
     const double *coef = nullptr;
     const double *alpha = nullptr;
     const int *active = nullptr;
+    const int *run = nullptr;  // per rhs: skip sources whose system is not iterating
     double *partial = nullptr;
     int pstride = 0;
 };

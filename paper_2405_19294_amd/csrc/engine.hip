@@ -158,6 +158,7 @@ int run_hop(const hrw_gauge *g, const Phases &ph, const HopCall &c, hipStream_t 
         a.coef = c.coef;
         a.alpha = c.alpha;
         a.active = c.active;
+        a.run = c.run;
         a.partial = c.partial;
         a.pstride = c.pstride;
         err = launch_hop<S>(g->nr, c.dagger, c.epi, a, st);
@@ -555,6 +556,7 @@ static int cg_iteration(CgRun &R, int max_iter, ReliableSchedule sched, int *hos
     c.dt = dt;
     c.n_rhs = R.n_rhs;
     c.rstride = P.RS;
+    c.run = P.active;  // systems that are not iterating skip every hop of the iteration
     int rc;
     if (R.full()) {
         HopCall a = c;

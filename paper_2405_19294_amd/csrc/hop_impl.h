@@ -382,6 +382,7 @@ __global__ void __launch_bounds__(WG) hop_kernel(const HopArgs<S> a)
     }
     bx = tile_remap(xcd_remap(bx, a.grid_half), a.grid_half, a.tile_ts, a.tile_c);
     const int rhs = blockIdx.y;
+    if (a.run && !a.run[rhs]) return;  // whole workgroup: one source
     const int gid = bx * WG + threadIdx.x;
     const int i = gid / G;
     const int r0 = (gid - i * G) * RS;
@@ -450,11 +451,12 @@ hop_mrhs_kernel(const HopArgs<S> a)
     const int items = MR_SITES * G * a.n_rhs;
     for (int e0 = 0; e0 < items; e0 += nt) {
         const int rhs = (e0 + t) / (MR_SITES * G);
+        const bool live = rhs < a.n_rhs && (!a.run || a.run[rhs]);
         double nrm = 0;
-        if (i < a.g.half && rhs < a.n_rhs) nrm = site_hop<NR, RS, S, DAG, EPI>(a, parity, i, rg * RS, rhs, links);
+        if (i < a.g.half && live) nrm = site_hop<NR, RS, S, DAG, EPI>(a, parity, i, rg * RS, rhs, links);
         if (EPI != EPI_PLAIN && a.partial) {
             const double tt = group_sum<G>(nrm, sh);
-            if ((t & (PG_SITES * G - 1)) == 0 && rhs < a.n_rhs)
+            if ((t & (PG_SITES * G - 1)) == 0 && live)
                 a.partial[(size_t)rhs * a.pstride + (a.parity < 0 ? parity * a.ngroups : 0) + bx] = tt;
         }
     }

@@ -114,7 +114,7 @@ __device__ __forceinline__ void mfma_dir(const HopArgs<float> &a, const cpx<floa
     for (int t = 0; t < NT; ++t) {
         const int s = src0 + 2 * t + (q >> 1);
         float pr[2][NR], pi[2][NR];
-        if (s < a.n_rhs) {
+        if (s < a.n_rhs && (!a.run || a.run[s])) {
             // component k of site j sits at lay(j, k) = lay(j, 0) + 64 k
             const cpx<float> *pa = in_base + (size_t)s * a.rstride + lay(j, sa * NR, M::NC);
             const cpx<float> *pb = in_base + (size_t)s * a.rstride + lay(j, sb * NR, M::NC);
@@ -268,7 +268,8 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) ho
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const int s = src0 + 2 * t + (q >> 1);
-            const bool ok = site_ok && s < a.n_rhs;
+            const bool live = s < a.n_rhs && (!a.run || a.run[s]);
+            const bool ok = site_ok && live;
             double nrm = 0;
             if (ok) {
                 const size_t roff = (size_t)s * a.rstride;
@@ -320,7 +321,7 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) ho
             }
             if (EPI != EPI_PLAIN && a.partial) {
                 const double tot = mfma_source_sum(nrm);
-                if (b == 0 && h == 0 && s < a.n_rhs)
+                if (b == 0 && h == 0 && live)
                     a.partial[(size_t)s * a.pstride + (a.parity < 0 ? parity * a.ngroups : 0) + bx] = tot;
             }
         }

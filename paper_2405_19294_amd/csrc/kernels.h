@@ -71,6 +71,8 @@ struct HopArgs {
     const double *coef;          // device, per rhs: c of the epilogue
     const double *alpha;         // device, per rhs (EPI_CG)
     const int *active;           // device, per rhs: 0 = frozen (EPI_CG leaves r, x)
+    const int *run;              // device, per rhs, or null: 0 = skip this source entirely
+                                 // (no loads, stores or partial; its outputs keep old values)
     double *partial;             // per-block partial norms, [rhs * pstride + block]
     int pstride;
     int tile_ts;                 // workgroups per time slice (0 = no tiling)
