@@ -73,14 +73,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=0, help="oracle CG iterations in the CPU sample (0 = auto)")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "ops"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is not part of it",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload != "c2":
-        out = {"c1": workload_c1, "c3": workload_c3, "c4": workload_c4, "c5": workload_c5}[args.workload](args)
+        out = {"c1": workload_c1, "c3": workload_c3, "c4": workload_c4, "c5": workload_c5,
+               "ops": workload_ops}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
 
@@ -502,6 +503,40 @@ def workload_c5(args):
                  service_ms={k: round(v * 1e3, 1) for k, v in rep["service_s"].items()},
                  report={k: v for k, v in rep.items() if k not in ("latency_s", "service_s")},
                  rate_sweep=sweep, highest_rate_with_bounded_p99=bounded)
+
+
+def workload_ops(args):
+    """Single D_W and D_hat applies in FP64 and FP32 for the four representations at the sizes of
+    the solve workloads (SU(3) fund and sym 32^4, SU(2) adj and SU(4) asym 24^3x48)."""
+    import torch
+
+    import fixtures as fx
+    from paper_2405_19294_amd import hrw
+    hrw.load()
+    dev = torch.device("cuda:0")
+    theta, kappa = (np.pi, 0.0, 0.0, 0.0), 0.135
+    copy = copy_reference(torch, dev)
+    table, worst = {}, None
+    for nc, rep, dims in [(3, "fund", (32, 32, 32, 32)), (2, "adj", (48, 24, 24, 24)),
+                          (4, "asym", (48, 24, 24, 24)), (3, "sym", (32, 32, 32, 32))]:
+        uf = torch.from_numpy(fx.gauge_field(dims, nc, "thermal", seed=2, eps=0.3)).to(dev)
+        rows = operator_table(torch, hrw, dev, dims, nc, rep, uf, kappa, theta, copy["gbs"])
+        del uf
+        torch.cuda.empty_cache()
+        key = f"SU({nc}) {rep} {'x'.join(str(d) for d in dims[::-1])}"
+        table[key] = rows
+        for name in ("deo_f64", "deo_f32"):
+            if worst is None or rows[name]["frac_of_peak"] < worst[1]:
+                worst = (f"{key} {name}", rows[name]["frac_of_peak"])
+    fracs = [r["frac_of_peak"] for t in table.values() for n, r in t.items() if n.startswith("deo")]
+    best = max(((k, n, r) for k, t in table.items() for n, r in t.items() if n.startswith("deo")),
+               key=lambda v: v[2]["frac_of_peak"])
+    roof = {"bound": "hbm", "kernel": f"D_hat apply (two e/o hops), {best[0]} {best[1]}",
+            "achieved": best[2]["GBs_min"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": best[2]["frac_of_peak"], "traffic": None}
+    return _line(round(sum(fracs) / len(fracs), 4), "mean fraction of 8 TB/s (D_hat, FP64 and FP32, 4 reps)", 20, 3,
+                 None, "f64+f32", {"workload": "operator_sweep_4_reps", "kappa": kappa, "theta": "(pi,0,0,0)"}, roof,
+                 operators=table, lowest=worst, hbm_copy_reference=copy)
 
 
 def copy_reference(torch, dev, nbytes=1 << 30, reps=10):
