@@ -440,6 +440,20 @@ def workload_c4(args):
                   "rel_error_vs_fp64_source0": err0, "hop_roofline": r}
         log(f"c4 n={n}: {out[n]}")
         roof = r
+    # the same 24 sources with FP16 storage of the inner fields (FP32 arithmetic)
+    prm16 = hrw.solve_params(tol=1e-10, max_iter=20000, system="ddag_d_eo", inner_dtype="f16",
+                             reliable_every=50, reliable_delta=hrw.RELIABLE_DELTA["f16"], theta=theta)
+    g16 = hrw.Gauge(dims, 3, "sym", torch.from_numpy(fx.gauge_field(dims, 3, "thermal", seed=6, eps=0.3)).to(dev),
+                    dtypes=("f64", "f16"))
+    x16, res16, per16, _ = _solve_timed(hrw, torch, g16, srcs, kappa, prm16, max(1, args.steps // 2), 1)
+    f16_row = {"rhs_solves_per_s": round(nmax / per16, 3), "ms_per_batch": round(per16 * 1e3, 1),
+               "speedup_vs_fp64_cg": round(nmax / per16 / fp64_rate, 2),
+               "max_iters": max(q["iters"] for q in res16),
+               "max_true_rel_resid": max(q["true_rel_resid"] for q in res16),
+               "rel_error_vs_fp64_source0": float((torch.linalg.vector_norm(x16[0] - x64[0]) /
+                                                   torch.linalg.vector_norm(x64[0])).item())}
+    log(f"c4 n=24 f16 storage: {f16_row}")
+    g16.close()
     return _line(out[24]["rhs_solves_per_s"], "rhs-solves/s", max(1, args.steps // 2), 1, out[24]["ms_per_batch"],
                  "f32", {"workload": "su3_sym_32^4_multi_source_mixed_cg", "lattice": list(dims), "kappa": kappa,
                          "sources": "point-smeared (Gaussian spatial profile, width 2), 12 and 24",
@@ -448,7 +462,7 @@ def workload_c4(args):
                  fp64_cg={"solves_per_s": round(fp64_rate, 3), "iters": res64[0]["iters"],
                           "batched_24_rhs_solves_per_s": round(nmax / per64b, 3),
                           "batched_max_iters": max(q["iters"] for q in res64b)},
-                 multi_source=out, hbm_copy_reference=copy_reference(torch, dev))
+                 multi_source=out, multi_source_24_f16_storage=f16_row, hbm_copy_reference=copy_reference(torch, dev))
 
 
 def workload_c5(args):
