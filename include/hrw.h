@@ -49,6 +49,16 @@
  * anything is enqueued; on a negative status nothing was enqueued (except
  * HRW_EDEVICE, which reports a failed HIP call) and hrw_last_error() returns
  * a message for the calling thread.
+ *
+ * Environment (read at each hopping-kernel launch):
+ *   HRW_TUNE=0       use the occupancy model for the multi-source kernel's
+ *                    launch shape instead of timing the candidates on the
+ *                    first plain-epilogue launch of each (sources, extents);
+ *                    results are bitwise the same either way;
+ *   HRW_MRHS_MFMA=1  run FP32 N_R = 6 launches with >= 6 sources on the
+ *                    matrix-core multi-source kernel (results differ from the
+ *                    default vector kernel only by FP32 rounding; slower on
+ *                    MI355X).
  */
 #ifndef HRW_H
 #define HRW_H
