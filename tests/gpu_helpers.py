@@ -35,3 +35,12 @@ def fp64_close(out, ref):
     """FP64 operator parity: l2 relative <= 1e-13 and componentwise <= 1e-12 max|ref|."""
     assert rel(out, ref) <= 1e-13, rel(out, ref)
     assert np.max(np.abs(out - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def bound_check(dims, ur_r, psi_r, kappa, out, ref, nr, unit_out):
+    """|out - ref| <= gamma_k (|psi| + kappa |H||psi|) + unit_out |ref| componentwise (a-priori bound of a
+    low-precision D_W evaluation on the rounded inputs; k = 2 N_R + 16)."""
+    bound = orc.gamma_k(2 * nr + 16, U32) * (np.abs(psi_r) + kappa * orc.hop_abs(dims, np.abs(ur_r), np.abs(psi_r)))
+    bound = bound + unit_out * np.abs(ref) + 1e-300
+    excess = np.abs(out - ref) / bound
+    assert np.max(excess) <= 1.0, np.max(excess)

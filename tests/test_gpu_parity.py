@@ -21,7 +21,7 @@ import fixtures as fx
 import oracle as orc
 from paper_2405_19294_amd import hrw
 
-from gpu_helpers import (THETA_AP, THETA_TW, U32, U_BF16, U_F16, fp64_close, rel, setup, to_dev)
+from gpu_helpers import (THETA_AP, THETA_TW, U32, U_BF16, U_F16, bound_check, fp64_close, rel, setup, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -77,14 +77,6 @@ def test_hop_eo_and_deo_f64(case):
                    orc.deo(dims, ur, 0.131, pe, THETA_TW, dagger))
 
 
-def _bound_check(dims, ur_r, psi_r, kappa, out, ref, nr, unit_out):
-    """|out - ref| <= gamma_k (|psi| + kappa |H||psi|) + unit_out |ref| componentwise."""
-    bound = orc.gamma_k(2 * nr + 16, U32) * (np.abs(psi_r) + kappa * orc.hop_abs(dims, np.abs(ur_r), np.abs(psi_r)))
-    bound = bound + unit_out * np.abs(ref) + 1e-300
-    excess = np.abs(out - ref) / bound
-    assert np.max(excess) <= 1.0, np.max(excess)
-
-
 @pytest.mark.parametrize("case", OPERATOR_CASES, ids=ids)
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
 def test_dw_low_precision_within_bound(case, dtype):
@@ -97,7 +89,7 @@ def test_dw_low_precision_within_bound(case, dtype):
     out = hrw.dw_apply(g, kappa, to_dev(psi), THETA_TW, dtype).cpu().numpy()
     ref = orc.dw(dims, ur_r, kappa, psi_r, THETA_TW)
     unit_out = {"f32": U32, "bf16": U_BF16, "f16": U_F16}[dtype]
-    _bound_check(dims, ur_r, psi_r, kappa, out, ref, g.nr, unit_out)
+    bound_check(dims, ur_r, psi_r, kappa, out, ref, g.nr, unit_out)
     # the storage error alone is reported against the unrounded FP64 operator
     exact = orc.dw(dims, ur, kappa, psi, THETA_TW)
     assert rel(out, exact) < {"f32": 1e-6, "bf16": 2e-2, "f16": 3e-3}[dtype]
@@ -172,7 +164,7 @@ def test_mfma_multi_source_within_fp32_bound(nc, rep, n, dims, monkeypatch):
     ur_r = orc.round_to("f32", ur)
     for k in range(n):
         psi_r = orc.round_to("f32", psi[k])
-        _bound_check(dims, ur_r, psi_r, 0.12, many[k], orc.dw(dims, ur_r, 0.12, psi_r, THETA_TW), g.nr, U32)
+        bound_check(dims, ur_r, psi_r, 0.12, many[k], orc.dw(dims, ur_r, 0.12, psi_r, THETA_TW), g.nr, U32)
         for d in (False, True):
             one = hrw.deo_apply(g, 0.125, to_dev(pe[k]), THETA_TW, "f32", dagger=d).cpu().numpy()
             assert np.max(np.abs(many_eo[d][k] - one)) <= 1e-6 * np.max(np.abs(one))
