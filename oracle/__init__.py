@@ -64,6 +64,7 @@ def _load():
             "orc_hop_eo": (I, [P, I, P, P, I, I, P, P]),
             "orc_deo": (I, [P, I, P, D, P, I, P, P]),
             "orc_cg": (I, [P, I, P, D, P, I, P, P, D, I, P, P, P]),
+            "orc_bicgstab": (I, [P, I, P, D, P, I, P, P, D, I, P]),
             "orc_round": (I, [I, L, P]),
             "orc_parity_count": (I, [P, I]),
             "orc_num_threads": (I, []),
@@ -268,6 +269,42 @@ def solve_d_eo(dims, u_r, kappa, b, theta=None, tol=1e-10, max_iter=10000):
     bpe = be + kappa * hop_eo(dims, u_r, bo, 0, theta)
     eta = deo(dims, u_r, kappa, bpe, theta, dagger=True)
     xe, info = cg(dims, u_r, kappa, eta, theta, SYSTEM_EO, tol, max_iter)
+    xo = bo + kappa * hop_eo(dims, u_r, xe, 1, theta)
+    return merge_eo(dims, xe, xo), info
+
+
+# ---------------------------------------------------------------- BiCGstab
+
+BICG_FULL = 0     # D x = b on the full lattice
+BICG_EO = 1       # D_hat x_e = b_e on the even sites
+
+
+def bicgstab(dims, u_r, kappa, b, theta=None, system=BICG_EO, tol=1e-10, max_iter=10000):
+    """Stabilised bi-conjugate gradient for D x = b or D_hat x_e = b_e from x = 0
+    (Sec. 3.3 inverters; van der Vorst 1992).
+
+    Returns (x, info) with info = {"status", "iters", "true_rel_resid",
+    "restarts"}; the true residual is recomputed in FP64.
+    """
+    u, bb = _c128(u_r), _c128(b)
+    x = np.zeros_like(bb)
+    info = np.zeros(3)
+    rc = _load().orc_bicgstab(_ptr(_dims(dims)), _nr_of(u), _ptr(u), float(kappa), _ptr(_theta(theta)),
+                              int(system), _ptr(bb), _ptr(x), float(tol), int(max_iter), _ptr(info))
+    _check(rc if rc != -5 else 0, "bicgstab")
+    return x, {"status": int(rc), "iters": int(info[0]), "true_rel_resid": float(info[1]),
+               "restarts": int(info[2])}
+
+
+def solve_d_eo_bicgstab(dims, u_r, kappa, b, theta=None, tol=1e-10, max_iter=10000):
+    """Solve D x = b by the even/odd Schur complement and BiCGstab on D_hat.
+
+    b'_e = b_e + kappa H_eo b_o; D_hat x_e = b'_e; x_o = b_o + kappa H_oe x_e
+    (Sec. 3.1 even/odd, Sec. 3.3 inverters).
+    """
+    be, bo = split_eo(dims, b)
+    bpe = be + kappa * hop_eo(dims, u_r, bo, 0, theta)
+    xe, info = bicgstab(dims, u_r, kappa, bpe, theta, BICG_EO, tol, max_iter)
     xo = bo + kappa * hop_eo(dims, u_r, xe, 1, theta)
     return merge_eo(dims, xe, xo), info
 

@@ -1,7 +1,7 @@
 /*
  * Plain FP64 CPU oracle for the Wilson-Dirac operator with fermions in a
- * representation R of SU(N), its even/odd (Schur) form and conjugate-gradient
- * inversion of D^dagger D.
+ * representation R of SU(N), its even/odd (Schur) form, conjugate-gradient
+ * inversion of D^dagger D and BiCGstab inversion of D.
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct
  * definition the GPU library is checked against.  Only the test suite, the
@@ -13,8 +13,8 @@
  *     any N_c and higher representations, with even/odd preconditioning
  *     (Sec. 3.1); the spinor carries ~N_f colour components and the
  *     represented link is an N_f x N_f matrix (Sec. 3.1.2);
- *   - the inverters are CG (Sec. 3.3); inner products and norms are global
- *     reductions (Sec. 3.2).
+ *   - the inverters are CG and BiCGstab (Sec. 3.3); inner products and norms
+ *     are global reductions (Sec. 3.2).
  * The paper prints no formula for D, the gamma basis, the representation
  * bases or the boundary-phase placement; the readings fixed here are:
  *   - Euclidean chiral gamma basis, gamma_5 = g0 g1 g2 g3 = diag(1,1,-1,-1);
@@ -578,6 +578,143 @@ int orc_cg(const int *dims, int nr, const double *u, double kappa, const double 
     free(r);
     free(p);
     free(q);
+    return status;
+}
+
+/* ------------------------------------------------------------------ BiCGstab */
+
+/* D (system 0, full lattice) or D_hat (system 1, even sites) applied to in. */
+static void apply_op(op_ctx *c, const cplx *in, cplx *out)
+{
+    if (c->system == 0)
+        orc_dw(c->dims, c->nr, c->u, c->kappa, c->theta, 0, (const double *)in, (double *)out);
+    else
+        orc_deo(c->dims, c->nr, c->u, c->kappa, c->theta, 0, (const double *)in, (double *)out);
+}
+
+/* <a, b> = sum_i conj(a_i) b_i */
+static cplx cdot(long n, const cplx *a, const cplx *b)
+{
+    cplx s = 0;
+    for (long i = 0; i < n; ++i) s += conj(a[i]) * b[i];
+    return s;
+}
+
+static int cfinite(cplx z) { return isfinite(creal(z)) && isfinite(cimag(z)); }
+
+/*
+ * Stabilised bi-conjugate gradient (van der Vorst, SIAM J. Sci. Stat. Comput.
+ * 13 (1992) 631, one of the inverters of Sec. 3.3) for D x = b on the full
+ * lattice (system 0) or D_hat x_e = b_e on the even sites (system 1), from
+ * x = 0 with the shadow residual r0 equal to the starting residual.  Each
+ * iteration is a Bi-CG step followed by a one-dimensional minimal-residual
+ * step:
+ *   p = r + (rho / rho_old)(alpha / omega)(p - omega v)   (p = r after a start)
+ *   v = A p,  alpha = rho / <r0, v>,  s = r - alpha v
+ *   t = A s,  omega = <t, s> / |t|^2  (0 when t = 0),  x += alpha p + omega s
+ *   r = s - omega t,  rho_old = rho,  rho = <r0, r>
+ * with <a, b> = sum conj(a) b.  When |r| <= tol |b| the true residual b - A x
+ * is recomputed; if it is still above tol, or a coefficient is not finite
+ * (rho, <r0, v> or omega vanished), the iteration starts again from the true
+ * residual, which also becomes the new shadow vector.  info[0] = iterations,
+ * info[1] = true relative residual, info[2] = restarts.
+ */
+int orc_bicgstab(const int *dims, int nr, const double *u, double kappa, const double *theta,
+                 int system, const double *b_in, double *x_out, double tol, int max_iter,
+                 double *info)
+{
+    if (!check_dims(dims, nr) || (system != 0 && system != 1) || !b_in || !x_out)
+        return ORC_EINVAL;
+    if (system == 1 && !even_dims(dims)) return ORC_EINVAL;
+    const long sites = system == 0 ? vol(dims) : vol(dims) / 2;
+    const long n = sites * 4 * nr;
+    const size_t bytes = sizeof(cplx) * (size_t)n;
+    op_ctx c = {dims, nr, u, kappa, theta, system, NULL};
+    cplx *x = (cplx *)x_out;
+    cplx *r = (cplx *)malloc(bytes), *r0 = (cplx *)malloc(bytes), *p = (cplx *)malloc(bytes),
+         *v = (cplx *)malloc(bytes), *s = (cplx *)malloc(bytes), *t = (cplx *)malloc(bytes);
+    const cplx *b = (const cplx *)b_in;
+    memset(x, 0, bytes);
+    memcpy(r, b, bytes);
+    memcpy(r0, b, bytes);
+    memset(p, 0, bytes);
+    memset(v, 0, bytes);
+    const double bb = norm2(n, b);
+    const double tol2 = tol * tol * bb;
+    cplx rho = bb, rho_old = 1, alpha = 1, omega = 1;
+    int it = 0, restarts = 0, fresh = 1, status = ORC_NOT_CONVERGED;
+    double rr_true = bb;
+    if (!isfinite(bb)) status = ORC_BREAKDOWN;
+    else if (bb == 0) status = ORC_OK;
+    while (status == ORC_NOT_CONVERGED && it < max_iter) {
+        int restart = 0;
+        if (fresh) {
+            memcpy(p, r, bytes);
+        } else {
+            const cplx beta = (rho / rho_old) * (alpha / omega);
+            if (!cfinite(beta) || omega == 0 || rho_old == 0) {
+                restart = 1;
+            } else {
+                for (long i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+            }
+        }
+        if (!restart) {
+            fresh = 0;
+            apply_op(&c, p, v);
+            const cplx rv = cdot(n, r0, v);
+            alpha = rho / rv;
+            if (rv == 0 || !cfinite(alpha)) restart = 1;
+        }
+        if (!restart) {
+            for (long i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
+            apply_op(&c, s, t);
+            const double tt = norm2(n, t);
+            omega = tt > 0 ? cdot(n, t, s) / tt : 0;
+            for (long i = 0; i < n; ++i) {
+                x[i] += alpha * p[i] + omega * s[i];
+                r[i] = s[i] - omega * t[i];
+            }
+            ++it;
+            rho_old = rho;
+            rho = cdot(n, r0, r);
+            if (norm2(n, r) > tol2) continue;
+        }
+        /* recursive convergence or breakdown: check the true residual */
+        apply_op(&c, x, t);
+        for (long i = 0; i < n; ++i) r[i] = b[i] - t[i];
+        rr_true = norm2(n, r);
+        if (!isfinite(rr_true)) {
+            status = ORC_BREAKDOWN;
+            break;
+        }
+        if (rr_true <= tol2) {
+            status = ORC_OK;
+            break;
+        }
+        if (++restarts > 100) {
+            status = ORC_BREAKDOWN;
+            break;
+        }
+        memcpy(r0, r, bytes);
+        rho = rr_true;
+        fresh = 1;
+    }
+    if (status == ORC_NOT_CONVERGED) {
+        apply_op(&c, x, t);
+        for (long i = 0; i < n; ++i) r[i] = b[i] - t[i];
+        rr_true = norm2(n, r);
+    }
+    if (info) {
+        info[0] = it;
+        info[1] = bb > 0 ? sqrt(rr_true / bb) : 0.0;
+        info[2] = restarts;
+    }
+    free(r);
+    free(r0);
+    free(p);
+    free(v);
+    free(s);
+    free(t);
     return status;
 }
 

@@ -349,6 +349,116 @@ def test_lanczos_extremes_match_dense_spectrum():
     assert (ev[-1] - hi) / ev[-1] < 1e-2 and (lo - ev[0]) / ev[0] < 1e-2
 
 
+# ----------------------------------------------------------------- BiCGstab
+
+def test_bicgstab_matches_dense_solve_and_scipy():
+    """The oracle's BiCGstab against a dense solve on D_hat, D and the Schur route,
+    and its iteration count against scipy's independent implementation of the
+    same method (van der Vorst 1992) run on the dense D_hat."""
+    sla = pytest.importorskip("scipy.sparse.linalg")
+    dims = (4, 2, 2, 4)
+    ur = _random_setup(dims, 2, "fund", seed=55)
+    nr, kappa, v = 2, 0.13, fx.volume(dims)
+    dhat = dense(lambda f: orc.deo(dims, ur, kappa, f, THETA_AP), v // 2, nr)
+    be = orc.split_eo(dims, fx.gaussian_spinor(dims, nr, seed=56))[0]
+    x, info = orc.bicgstab(dims, ur, kappa, be, THETA_AP, orc.BICG_EO, tol=1e-12)
+    assert info["status"] == 0 and info["true_rel_resid"] <= 1e-12
+    assert rel(x.reshape(-1), np.linalg.solve(dhat, be.reshape(-1))) <= np.linalg.cond(dhat) * 1e-12
+    steps = []
+    xs, flag = sla.bicgstab(dhat, be.reshape(-1), rtol=1e-12, atol=0.0, maxiter=1000,
+                            callback=lambda xk: steps.append(1))
+    assert flag == 0
+    assert abs(len(steps) - info["iters"]) <= 1, (len(steps), info["iters"])
+    # full lattice, directly and through the Schur complement
+    dm = dense(lambda f: orc.dw(dims, ur, kappa, f, THETA_AP), v, nr)
+    b = fx.gaussian_spinor(dims, nr, seed=57)
+    ref = np.linalg.solve(dm, b.reshape(-1))
+    bound = np.linalg.cond(dm) * 1e-12
+    xf, info = orc.bicgstab(dims, ur, kappa, b, THETA_AP, orc.BICG_FULL, tol=1e-12)
+    assert info["status"] == 0 and rel(xf.reshape(-1), ref) <= bound
+    xe, info = orc.solve_d_eo_bicgstab(dims, ur, kappa, b, THETA_AP, tol=1e-12)
+    assert info["status"] == 0 and rel(xe.reshape(-1), ref) <= bound
+
+
+def test_bicgstab_pins_catch_planted_mistakes():
+    """Typical slips in a BiCGstab recurrence still converge (the stop is on the
+    residual) but take more iterations: the iteration-count pin against scipy
+    rejects each.  The mutants are numpy re-statements written here; the
+    oracle is untouched."""
+    sla = pytest.importorskip("scipy.sparse.linalg")
+    dims = (4, 2, 2, 4)
+    ur = _random_setup(dims, 2, "fund", seed=55)
+    a = dense(lambda f: orc.deo(dims, ur, 0.13, f, THETA_AP), fx.volume(dims) // 2, 2)
+    b = orc.split_eo(dims, fx.gaussian_spinor(dims, 2, seed=56))[0].reshape(-1)
+
+    def iterations(mutant, tol=1e-12):
+        x, r = np.zeros_like(b), b.copy()
+        r0, p, v = b.copy(), b.copy(), np.zeros_like(b)
+        rho, rho_old, al, om = np.vdot(b, b), 1.0, 1.0, 1.0
+        for it in range(1, 500):
+            if it > 1:
+                beta = rho / rho_old * (1 if mutant == "beta_without_alpha_over_omega" else al / om)
+                p = r + beta * (p + om * v if mutant == "p_sign" else p - om * v)
+            v = a @ p
+            al = rho / np.vdot(r0, v)
+            s_ = r - al * v
+            t = a @ s_
+            om = (np.vdot(s_, t) if mutant == "omega_conjugated" else np.vdot(t, s_)) / np.vdot(t, t).real
+            x, r = x + al * p + om * s_, s_ - om * t
+            rho_old, rho = rho, (np.vdot(r, r0) if mutant == "rho_conjugated" else np.vdot(r0, r))
+            if np.vdot(r, r).real <= tol ** 2 * np.vdot(b, b).real:
+                return it
+        return 500
+
+    steps = []
+    sla.bicgstab(a, b, rtol=1e-12, atol=0.0, maxiter=1000, callback=lambda xk: steps.append(1))
+    assert abs(iterations(None) - len(steps)) <= 1
+    for m in ["beta_without_alpha_over_omega", "p_sign", "omega_conjugated", "rho_conjugated"]:
+        assert abs(iterations(m) - len(steps)) > 1, m
+
+
+def test_bicgstab_special_cases():
+    """kappa = 0 (D_hat = 1): one iteration gives x = b exactly; a free-field plane
+    wave (two distinct eigenvalues of the symbol) converges in at most two
+    iterations to the analytic solution; zero and non-finite sources."""
+    dims = (4, 4, 2, 4)
+    ur = _random_setup(dims, 3, "fund", seed=58)
+    be = orc.split_eo(dims, fx.gaussian_spinor(dims, 3, seed=59))[0]
+    x, info = orc.bicgstab(dims, ur, 0.0, be, THETA_AP, orc.BICG_EO)
+    assert info["iters"] == 1 and info["status"] == 0 and np.array_equal(x, be)
+    unit = fx.unit_gauge(dims, 3)
+    sc = fx.rng(4, 60).standard_normal((4, 3)) + 1j * fx.rng(4, 61).standard_normal((4, 3))
+    pw, pm = plane_wave(dims, (1, 0, 1, 1), THETA_TW, sc)
+    kappa = 0.12
+    x, info = orc.bicgstab(dims, unit, kappa, pw, THETA_TW, orc.BICG_FULL, tol=1e-13)
+    exact = np.einsum("ab,sbc->sac", np.linalg.inv(free_symbol(pm, kappa)), pw)
+    assert info["status"] == 0 and info["iters"] <= 2
+    assert rel(x, exact) < 1e-12
+    zero = np.zeros_like(be)
+    x, info = orc.bicgstab(dims, ur, 0.12, zero, THETA_AP)
+    assert info["status"] == 0 and info["iters"] == 0 and not np.abs(x).max()
+    bad = be.copy()
+    bad[1, 2, 0] = np.nan
+    _, info = orc.bicgstab(dims, ur, 0.12, bad, THETA_AP)
+    assert info["status"] == -5
+
+
+def test_bicgstab_and_cg_solve_the_same_system():
+    """D x = b solved through the Schur complement by BiCGstab on D_hat and by CG
+    on its normal equations: the solution is unique, so both agree to the
+    tolerance; BiCGstab needs fewer D_hat applications here."""
+    dims = (4, 4, 4, 4)
+    ur = _random_setup(dims, 3, "fund", seed=62, kind="thermal")
+    b = fx.gaussian_spinor(dims, 3, seed=63)
+    kappa = 0.135
+    xb, ib = orc.solve_d_eo_bicgstab(dims, ur, kappa, b, THETA_AP, tol=1e-11)
+    xc, ic = orc.solve_d_eo(dims, ur, kappa, b, THETA_AP, tol=1e-12)
+    assert ib["status"] == 0 and ic["status"] == 0
+    assert np.linalg.norm(b - orc.dw(dims, ur, kappa, xb, THETA_AP)) / np.linalg.norm(b) <= 1e-10
+    assert rel(xb, xc) < 1e-8
+    assert 2 * ib["iters"] < 2 * ic["iters"]
+
+
 # ----------------------------------------------------------------- rounding to storage formats
 
 def test_round_f32_and_f16_match_ieee_casts():
