@@ -188,9 +188,49 @@ def main():
     out["hbm_copy_reference"] = copy_reference(torch, dev)
     out["operators"] = operator_table(torch, hrw, dev, dims, nc, rep, uf_d, kappa, theta,
                                       out["hbm_copy_reference"]["gbs"])
+    out["bicgstab"] = bicgstab_rows(torch, hrw, dev, dims, nc, rep, uf_d, b_d, kappa, theta, out["value"],
+                                    max(2, min(args.steps, 5)))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dims, uf, b, kappa, theta, r["iters"], args.cpu_iters)
     print(json.dumps(out), flush=True)
+
+
+def bicgstab_rows(torch, hrw, dev, dims, nc, rep, uf_d, b_d, kappa, theta, cg_value, steps):
+    """The same request (D x = b through the even/odd Schur complement, |b'_e - D_hat x_e| <= 1e-10
+    |b'_e| in FP64) solved by BiCGstab on D_hat itself: plain FP64, and FP32 inner fields with FP64
+    reliable updates.  A step is the whole request as in the main line (gauge field built, solve,
+    reconstruction, |b - D x|); solves/s beside CG's."""
+    rows = {}
+    for inner in ("f64", "f32"):
+        dtypes = ("f64",) if inner == "f64" else ("f64", "f32")
+        prm = hrw.solve_params(tol=WORKLOAD["tol"], max_iter=5000, system="d_eo", inner_dtype=inner, theta=theta,
+                               reliable_delta=hrw.RELIABLE_DELTA[inner])
+        ws = hrw.Workspace(hrw.workspace_size(dims, nc, rep, 1, prm), dev)
+        x_d = torch.empty_like(b_d)
+
+        def step():
+            g = hrw.Gauge(dims, nc, rep, uf_d, dtypes=dtypes)
+            x, res, rc = hrw.bicgstab_solve(g, b_d, kappa, prm, x=x_d, ws=ws)
+            g.close()
+            if rc != 0:
+                raise RuntimeError(f"BiCGstab solve failed: {res}")
+            return res[0]
+
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        rows[inner] = {"solves_per_s": round(steps / el, 3), "ms_per_solve": round(el / steps * 1e3, 2),
+                       "iters": r["iters"], "dhat_applies": 2 * r["iters"],
+                       "reliable_updates": r["reliable_updates"], "restarts": r["restarts"],
+                       "true_rel_resid": r["true_rel_resid"], "d_rel_resid": r["d_rel_resid"],
+                       "vs_fp64_cg": round(steps / el / cg_value, 3), "steps": steps}
+        log(f"BiCGstab {inner}: {rows[inner]}")
+        del ws
+    return rows
 
 
 def operator_table(torch, hrw, dev, dims, nc, rep, uf_d, kappa, theta, copy_gbs, reps=20):

@@ -91,13 +91,17 @@ enum hrw_dtype { HRW_F64 = 0, HRW_F32 = 1, HRW_BF16 = 2, HRW_F16 = 3 };
 #define HRW_STORE_BF16 (1u << HRW_BF16)
 #define HRW_STORE_F16 (1u << HRW_F16)
 
-/* Linear systems hrw_cg_solve can solve. */
+/* Linear systems: 0-2 for hrw_cg_solve (Hermitian positive definite normal
+ * equations), 3-4 for hrw_bicgstab_solve (the operator itself). */
 enum hrw_system {
     HRW_SYS_DDAG_D_FULL = 0, /* D^+ D x = b on the full lattice                       */
     HRW_SYS_DDAG_D_EO = 1,   /* D_hat^+ D_hat x_e = b_e on the even sites (half field) */
-    HRW_SYS_D_CGNR_EO = 2    /* D x = b on the full lattice via the even/odd Schur
+    HRW_SYS_D_CGNR_EO = 2,   /* D x = b on the full lattice via the even/odd Schur
                                 complement, CG on its normal equations, and
                                 reconstruction of the odd sites                     */
+    HRW_SYS_DHAT_EO = 3,     /* D_hat x_e = b_e on the even sites (half field)      */
+    HRW_SYS_D_EO = 4         /* D x = b on the full lattice via the even/odd Schur
+                                complement (BiCGstab on D_hat) and reconstruction   */
 };
 
 typedef struct hrw_gauge hrw_gauge; /* opaque resident represented gauge field */
@@ -208,6 +212,28 @@ int hrw_deo_apply(const hrw_gauge *g, const double *kappa_per_rhs, const double 
 int hrw_cg_solve(const hrw_gauge *g, const hrw_solve_params *params, int n_rhs,
                  const double *kappa_per_rhs, const double *b, double *x, hrw_solve_result *res,
                  void *workspace, size_t ws_bytes, void *stream);
+
+/* Stabilised bi-conjugate gradient (BiCGstab, van der Vorst 1992; one of the
+ * inverters of Sec. 3.3) on D_hat itself (HRW_SYS_DHAT_EO: b, x are even half
+ * fields) or for D x = b through the even/odd Schur complement
+ * (HRW_SYS_D_EO: b, x full-lattice fields; b'_e = b_e + kappa H_eo b_o,
+ * D_hat x_e = b'_e, x_o = b_o + kappa H_oe x_e; res.d_rel_resid receives
+ * |b - D x| / |b|).  n_rhs independent systems share the gauge field, each
+ * with its own kappa (host double[n_rhs]).  x = 0 is the start vector, the
+ * starting residual is the shadow vector, and each system stops on its FP64
+ * true relative residual |b_e - D_hat x_e| / |b_e| <= tol.  inner_dtype
+ * HRW_F64 runs plain FP64 (the true residual is checked at recursive
+ * convergence; above tol the iteration starts again from it); HRW_F32 runs
+ * the recurrences on FP32 fields with FP64 reliable updates (reliable_every,
+ * reliable_delta, and at recursive convergence), the solution accumulating in
+ * FP64.  A vanished coefficient (rho, <r0, D_hat p> or omega) also starts
+ * again; more than 100 new starts end as HRW_EBREAKDOWN.  res.iters counts
+ * BiCGstab iterations (two D_hat applications each).  Workspace:
+ * hrw_workspace_size with the same params.  Returns as hrw_cg_solve;
+ * EUNSUPPORTED for 16-bit inner storage, EINVAL for systems 0-2. */
+int hrw_bicgstab_solve(const hrw_gauge *g, const hrw_solve_params *params, int n_rhs,
+                       const double *kappa_per_rhs, const double *b, double *x, hrw_solve_result *res,
+                       void *workspace, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------- solver sessions
  * A session is a CG solver with n_slots slots (n_slots <= 64) that share one

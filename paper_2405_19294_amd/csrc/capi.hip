@@ -172,7 +172,7 @@ static int check_params(const hrw_solve_params *p)
 {
     if (!p) return fail(HRW_EINVAL, "params is null");
     if (!(p->tol > 0) || p->max_iter < 1) return fail(HRW_EINVAL, "tol must be > 0 and max_iter >= 1");
-    if (p->system < 0 || p->system > 2) return fail(HRW_EINVAL, "bad system %d", p->system);
+    if (p->system < 0 || p->system > 4) return fail(HRW_EINVAL, "bad system %d", p->system);
     if (p->inner_dtype < 0 || p->inner_dtype > 3) return fail(HRW_EINVAL, "bad inner dtype %d", p->inner_dtype);
     if (p->reliable_every < 0) return fail(HRW_EINVAL, "reliable_every must be >= 0");
     if (!(p->reliable_delta >= 0 && p->reliable_delta < 1)) return fail(HRW_EINVAL, "reliable_delta must be in [0, 1)");
@@ -188,6 +188,7 @@ int hrw_workspace_size(const int dims[4], int nc, int rep, int n_rhs, const hrw_
         const Geom g = make_geom(dims);
         if (!params) return apply_workspace(g, nr, n_rhs, bytes);
         if ((rc = check_params(params))) return rc;
+        if (params->system >= HRW_SYS_DHAT_EO) return bicg_workspace(g, nr, n_rhs, params, bytes);
         return cg_workspace(g, nr, n_rhs, params, bytes);
     });
 }
@@ -246,11 +247,32 @@ int hrw_cg_solve(const hrw_gauge *g, const hrw_solve_params *params, int n_rhs, 
         int rc;
         if (!g) return fail(HRW_EINVAL, "null gauge");
         if ((rc = check_params(params)) || (rc = check_rhs(n_rhs))) return rc;
+        if (params->system > HRW_SYS_D_CGNR_EO) return fail(HRW_EINVAL, "CG solves systems 0-2 (normal equations)");
         if (!kappa_per_rhs || !b || !x || !res || !workspace) return fail(HRW_EINVAL, "null pointer");
         if (b == x) return fail(HRW_EINVAL, "b and x must not overlap");
         if (!g->blocks[0][0]) return fail(HRW_EUNSUPPORTED, "CG needs FP64 links (HRW_STORE_F64)");
         if (!g->blocks[params->inner_dtype][0]) return fail(HRW_EUNSUPPORTED, "gauge field lacks links in the inner dtype");
         return cg_solve(g, params, n_rhs, kappa_per_rhs, b, x, res, workspace, ws_bytes, (hipStream_t)stream);
+    });
+}
+
+int hrw_bicgstab_solve(const hrw_gauge *g, const hrw_solve_params *params, int n_rhs, const double *kappa_per_rhs,
+                       const double *b, double *x, hrw_solve_result *res, void *workspace, size_t ws_bytes,
+                       void *stream)
+{
+    return guarded([&] {
+        int rc;
+        if (!g) return fail(HRW_EINVAL, "null gauge");
+        if ((rc = check_params(params)) || (rc = check_rhs(n_rhs))) return rc;
+        if (params->system != HRW_SYS_DHAT_EO && params->system != HRW_SYS_D_EO)
+            return fail(HRW_EINVAL, "BiCGstab solves HRW_SYS_DHAT_EO or HRW_SYS_D_EO, got system %d", params->system);
+        if (params->inner_dtype != HRW_F64 && params->inner_dtype != HRW_F32)
+            return fail(HRW_EUNSUPPORTED, "BiCGstab runs with FP64 or FP32 inner fields");
+        if (!kappa_per_rhs || !b || !x || !res || !workspace) return fail(HRW_EINVAL, "null pointer");
+        if (b == x) return fail(HRW_EINVAL, "b and x must not overlap");
+        if (!g->blocks[0][0]) return fail(HRW_EUNSUPPORTED, "BiCGstab needs FP64 links (HRW_STORE_F64)");
+        if (!g->blocks[params->inner_dtype][0]) return fail(HRW_EUNSUPPORTED, "gauge field lacks links in the inner dtype");
+        return bicgstab_solve(g, params, n_rhs, kappa_per_rhs, b, x, res, workspace, ws_bytes, (hipStream_t)stream);
     });
 }
 
@@ -261,6 +283,7 @@ int hrw_cg_session_create(const hrw_gauge *g, const hrw_solve_params *params, in
         int rc;
         if (!g || !out || !workspace) return fail(HRW_EINVAL, "null pointer");
         if ((rc = check_params(params)) || (rc = check_rhs(n_slots))) return rc;
+        if (params->system > HRW_SYS_D_CGNR_EO) return fail(HRW_EINVAL, "CG solves systems 0-2 (normal equations)");
         if (!g->blocks[0][0]) return fail(HRW_EUNSUPPORTED, "CG needs FP64 links (HRW_STORE_F64)");
         if (!g->blocks[params->inner_dtype][0]) return fail(HRW_EUNSUPPORTED, "gauge field lacks links in the inner dtype");
         return session_create(g, params, n_slots, workspace, ws_bytes, (hipStream_t)stream, out);

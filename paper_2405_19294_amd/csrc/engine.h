@@ -135,6 +135,10 @@ int deo_apply(const hrw_gauge *g, const double *kappa, const double theta[4], in
 int cg_solve(const hrw_gauge *g, const hrw_solve_params *p, int n_rhs, const double *kappa,
              const double *b, double *x, hrw_solve_result *res, void *ws, size_t ws_bytes,
              hipStream_t st);
+int bicg_workspace(const Geom &g, int nr, int n_rhs, const hrw_solve_params *p, size_t *bytes);
+int bicgstab_solve(const hrw_gauge *g, const hrw_solve_params *p, int n_rhs, const double *kappa,
+                   const double *b, double *x, hrw_solve_result *res, void *ws, size_t ws_bytes,
+                   hipStream_t st);
 int session_create(const hrw_gauge *g, const hrw_solve_params *prm, int n_slots, void *ws, size_t ws_bytes,
                    hipStream_t st, hrw_cg_session **out);
 int session_destroy(hrw_cg_session *s);

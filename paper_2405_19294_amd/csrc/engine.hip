@@ -1023,7 +1023,7 @@ int session_step(hrw_cg_session *s, int max_iters, int *running)
         for (int j = 0; j < n; ++j) c += s->used[j] && s->hf.host[j] != 0;
         return c;
     };
-    if (n == 0 || !any_running(s->hf.host, n) && !any_due(s->hf.host, n)) {
+    if (n == 0 || (!any_running(s->hf.host, n) && !any_due(s->hf.host, n))) {
         if (running) *running = 0;
         return refresh_states(s);
     }

@@ -22,7 +22,8 @@ OK, NOT_CONVERGED = 0, 1
 EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE, EBREAKDOWN = -1, -2, -3, -4, -5
 REPS = {"fund": 0, "adj": 1, "sym": 2, "asym": 3}
 DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
-SYSTEMS = {"ddag_d_full": 0, "ddag_d_eo": 1, "d_cgnr_eo": 2}
+SYSTEMS = {"ddag_d_full": 0, "ddag_d_eo": 1, "d_cgnr_eo": 2,   # CG (normal equations)
+           "dhat_eo": 3, "d_eo": 4}                             # BiCGstab (the operator itself)
 
 
 class HrwError(RuntimeError):
@@ -65,6 +66,8 @@ SIGNATURES = {
     "hrw_hop_eo": (I, [P, I, DP, I, I, I, P, P, P, SZ, P]),
     "hrw_deo_apply": (I, [P, DP, DP, I, I, I, P, P, P, SZ, P]),
     "hrw_cg_solve": (I, [P, ctypes.POINTER(SolveParams), I, DP, P, P, ctypes.POINTER(SolveResult), P, SZ, P]),
+    "hrw_bicgstab_solve": (I, [P, ctypes.POINTER(SolveParams), I, DP, P, P, ctypes.POINTER(SolveResult), P, SZ,
+                               P]),
     "hrw_cg_session_create": (I, [P, ctypes.POINTER(SolveParams), I, P, SZ, P, ctypes.POINTER(P)]),
     "hrw_cg_session_load": (I, [P, I, I, DP, P]),
     "hrw_cg_session_step": (I, [P, I, IP]),
@@ -266,6 +269,12 @@ def solve_params(tol=1e-10, max_iter=10000, system="ddag_d_eo", inner_dtype="f64
     return p
 
 
+def _system_field(g: Gauge, system: int) -> int:
+    """Complex elements of one right-hand side: even half field for the systems on D_hat."""
+    half = system in (SYSTEMS["ddag_d_eo"], SYSTEMS["dhat_eo"])
+    return (g.volume // 2 if half else g.volume) * 4 * g.nr
+
+
 def cg_workspace(g: Gauge, params: SolveParams, n_rhs: int = 1) -> Workspace:
     return Workspace(workspace_size(g.dims, g.nc, g.rep, n_rhs, params), g.device)
 
@@ -273,14 +282,30 @@ def cg_workspace(g: Gauge, params: SolveParams, n_rhs: int = 1) -> Workspace:
 def cg_solve(g: Gauge, b: torch.Tensor, kappa, params: SolveParams, x=None, ws: Workspace | None = None,
              stream=None):
     """CG for n_rhs stacked systems; returns (x, [result dict per rhs], overall status)."""
-    per = (g.volume // 2 if params.system == SYSTEMS["ddag_d_eo"] else g.volume) * 4 * g.nr
-    n = _n_rhs(b, per)
+    n = _n_rhs(b, _system_field(g, params.system))
     ks = [kappa] * n if isinstance(kappa, (int, float)) else list(kappa)
     x = torch.empty_like(b) if x is None else x
     ws = ws or cg_workspace(g, params, n)
     res = (SolveResult * n)()
     rc = load().hrw_cg_solve(g.handle, ctypes.byref(params), n, _doubles(ks), _dev_field(b, "b"),
                              _dev_field(x, "x"), res, ws.buf.data_ptr(), ws.nbytes, _stream(stream))
+    if rc < 0 and rc != EBREAKDOWN:
+        _check(rc)
+    return x, [r.as_dict() for r in res], rc
+
+
+def bicgstab_solve(g: Gauge, b: torch.Tensor, kappa, params: SolveParams, x=None, ws: Workspace | None = None,
+                   stream=None):
+    """BiCGstab for n_rhs stacked systems (params.system "dhat_eo": even half
+    fields, "d_eo": full-lattice fields); returns (x, [result dict per rhs],
+    overall status)."""
+    n = _n_rhs(b, _system_field(g, params.system))
+    ks = [kappa] * n if isinstance(kappa, (int, float)) else list(kappa)
+    x = torch.empty_like(b) if x is None else x
+    ws = ws or cg_workspace(g, params, n)
+    res = (SolveResult * n)()
+    rc = load().hrw_bicgstab_solve(g.handle, ctypes.byref(params), n, _doubles(ks), _dev_field(b, "b"),
+                                   _dev_field(x, "x"), res, ws.buf.data_ptr(), ws.nbytes, _stream(stream))
     if rc < 0 and rc != EBREAKDOWN:
         _check(rc)
     return x, [r.as_dict() for r in res], rc

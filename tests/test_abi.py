@@ -79,3 +79,22 @@ def test_validation_errors(lib):
     assert lib.hrw_workspace_size((ctypes.c_int * 4)(*dims), 3, 0, 1, ctypes.byref(p), ctypes.byref(sz)) == hrw.EINVAL
     assert lib.hrw_rep_map(3, 0, 10, None, None, None) == hrw.EINVAL
     assert lib.hrw_timing_read(7, None, None, None) == hrw.EINVAL
+
+
+def test_bicgstab_systems_sizes_and_validation(lib):
+    from paper_2405_19294_amd import hrw
+    dims = (4, 4, 4, 4)
+    cg = hrw.workspace_size(dims, 3, "fund", 1, hrw.solve_params(system="ddag_d_eo"))
+    dhat = hrw.workspace_size(dims, 3, "fund", 1, hrw.solve_params(system="dhat_eo"))
+    d = hrw.workspace_size(dims, 3, "fund", 1, hrw.solve_params(system="d_eo"))
+    mixed = hrw.workspace_size(dims, 3, "fund", 1, hrw.solve_params(system="dhat_eo", inner_dtype="f32"))
+    # FP32 inner fields take half the bytes of the FP64 ones; mixed mode adds an FP64 solution
+    assert 0 < cg and 0 < dhat < d and 0 < mixed < dhat
+    p = hrw.solve_params(system="dhat_eo")
+    res = (hrw.SolveResult * 1)()
+    k = (ctypes.c_double * 1)(0.13)
+    assert lib.hrw_bicgstab_solve(None, ctypes.byref(p), 1, k, None, None, res, None, 0, None) == hrw.EINVAL
+    bad = hrw.solve_params(system="dhat_eo")
+    bad.system = 5
+    sz = ctypes.c_size_t()
+    assert lib.hrw_workspace_size((ctypes.c_int * 4)(*dims), 3, 0, 1, ctypes.byref(bad), ctypes.byref(sz)) == hrw.EINVAL

@@ -4,7 +4,8 @@ The inputs are the benchmarks' own seeded fields (fixtures); the references come
 either on the whole field (it finishes in seconds at these sizes) or through properties the oracle
 recomputes (the residual of a solve):
   * SU(3) fund 32^4 (default workload): D_hat and D_hat^+ in FP64 to 1e-13, the full-lattice D_W in
-    FP32 within the a-priori bound, and the FP64 solve's |b - D x| / |b| recomputed by the oracle;
+    FP32 within the a-priori bound, and the |b - D x| / |b| of the FP64 CG solve and of the BiCGstab
+    solves (FP64 and FP32 inner) recomputed by the oracle;
   * SU(2) adj and SU(4) asym 24^3x48: D_hat in FP64, and the FP32-inner mixed solve's residual of the
     even/odd normal equations recomputed by the oracle;
   * SU(3) sym 32^4 with 24 sources: the multi-source FP32 kernel (the launch the multi-source CG uses)
@@ -62,6 +63,21 @@ def test_c2_solve_residual_by_oracle(c2_field):
     d_res = rel(orc.dw(C2, ur, KAPPA, x.cpu().numpy(), THETA_AP), b)
     assert abs(d_res - res[0]["d_rel_resid"]) <= 1e-3 * d_res
     assert d_res < 1e-8
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32"])
+def test_c2_bicgstab_residual_by_oracle(c2_field, inner):
+    """The default workload's system solved by BiCGstab on D_hat (FP64, and FP32 inner fields with
+    FP64 reliable updates): |b - D x| / |b| recomputed by the oracle."""
+    ur, g = c2_field
+    b = fx.gaussian_spinor(C2, 3, seed=3)
+    prm = hrw.solve_params(tol=1e-10, max_iter=5000, system="d_eo", inner_dtype=inner, theta=THETA_AP,
+                           reliable_delta=hrw.RELIABLE_DELTA[inner])
+    x, res, rc = hrw.bicgstab_solve(g, to_dev(b), KAPPA, prm)
+    assert rc == 0 and res[0]["true_rel_resid"] <= 1e-10
+    d_res = rel(orc.dw(C2, ur, KAPPA, x.cpu().numpy(), THETA_AP), b)
+    assert abs(d_res - res[0]["d_rel_resid"]) <= 1e-3 * d_res
+    assert d_res < 1e-9
 
 
 @pytest.mark.parametrize("nc,rep", [(2, "adj"), (4, "asym")])
