@@ -13,12 +13,13 @@ hopping-kernel instance measured with HIP events inside the timed steps, and
 the CPU oracle timed on a bounded sample as ``cpu_baseline``.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--workload c2|c1|c3|c4|c5]
+                       [--workload c2|c1|c3|c4|c5|ops|bicgstab]
 
 The default workload (c2) is the one the headline numbers are quoted on; the
 others print the same kind of JSON line for the remaining configurations:
 c1 SU(2) fund 4^4 (latency-bound), c3 SU(2) adj / SU(4) asym 24^3x48 mixed
-precision, c4 SU(3) sym 32^4 multi-source, c5 the serving stream.
+precision, c4 SU(3) sym 32^4 multi-source, c5 the serving stream, ops the operator table
+over the four representations, bicgstab the default request solved by BiCGstab.
 """
 
 from __future__ import annotations
@@ -73,7 +74,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=0, help="oracle CG iterations in the CPU sample (0 = auto)")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "ops"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "ops", "bicgstab"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is not part of it",
@@ -81,7 +82,7 @@ def main():
         sys.exit(2)
     if args.workload != "c2":
         out = {"c1": workload_c1, "c3": workload_c3, "c4": workload_c4, "c5": workload_c5,
-               "ops": workload_ops}[args.workload](args)
+               "ops": workload_ops, "bicgstab": workload_bicgstab}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
 
@@ -195,13 +196,42 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def bicgstab_rows(torch, hrw, dev, dims, nc, rep, uf_d, b_d, kappa, theta, cg_value, steps):
+def workload_bicgstab(args):
+    """The default workload's request solved by BiCGstab on D_hat (FP32 inner fields with FP64
+    reliable updates as the line's value, plain FP64 beside it), against FP64 CG on the normal
+    equations; the roofline is that of the hopping kernel inside the mixed solves."""
+    import torch
+
+    import fixtures as fx
+    from paper_2405_19294_amd import hrw
+    dev = torch.device("cuda:0")
+    dims = tuple(WORKLOAD["lattice"])
+    kappa, theta = WORKLOAD["kappa"], (np.pi, 0.0, 0.0, 0.0)
+    uf_d = torch.from_numpy(fx.gauge_field(dims, 3, "thermal", seed=2, eps=0.3)).to(dev)
+    b_d = torch.from_numpy(fx.gaussian_spinor(dims, 3, seed=3)).to(dev)
+    prm = hrw.solve_params(tol=WORKLOAD["tol"], max_iter=5000, system="d_cgnr_eo", inner_dtype="f64", theta=theta)
+    g = hrw.Gauge(dims, 3, "fund", uf_d, dtypes=("f64",))
+    _, _, per_cg, _ = _solve_timed(hrw, torch, g, b_d, kappa, prm, max(1, args.steps // 2), 1)
+    g.close()
+    rows = bicgstab_rows(torch, hrw, dev, dims, 3, "fund", uf_d, b_d, kappa, theta, 1.0 / per_cg, args.steps,
+                         order=("f32", "f64"), timed="f32")
+    roof = rows.pop("roofline")
+    cfg = dict(WORKLOAD, workload="su3_fund_32^4_eo_bicgstab_mixed_f32",
+               system="D x = b via even/odd Schur complement, BiCGstab on D_hat", inner_dtype="f32",
+               reliable_every=50, reliable_delta=1e-3)
+    m = rows["f32"]
+    return _line(m["solves_per_s"], "solves/s", args.steps, 1, m["ms_per_solve"], "f32", cfg, roof,
+                 bicgstab=rows, fp64_cg_solves_per_s=round(1.0 / per_cg, 3))
+
+
+def bicgstab_rows(torch, hrw, dev, dims, nc, rep, uf_d, b_d, kappa, theta, cg_value, steps,
+                  order=("f64", "f32"), timed=None):
     """The same request (D x = b through the even/odd Schur complement, |b'_e - D_hat x_e| <= 1e-10
     |b'_e| in FP64) solved by BiCGstab on D_hat itself: plain FP64, and FP32 inner fields with FP64
     reliable updates.  A step is the whole request as in the main line (gauge field built, solve,
     reconstruction, |b - D x|); solves/s beside CG's."""
     rows = {}
-    for inner in ("f64", "f32"):
+    for inner in order:
         dtypes = ("f64",) if inner == "f64" else ("f64", "f32")
         prm = hrw.solve_params(tol=WORKLOAD["tol"], max_iter=5000, system="d_eo", inner_dtype=inner, theta=theta,
                                reliable_delta=hrw.RELIABLE_DELTA[inner])
@@ -218,11 +248,16 @@ def bicgstab_rows(torch, hrw, dev, dims, nc, rep, uf_d, b_d, kappa, theta, cg_va
 
         step()
         torch.cuda.synchronize()
+        if timed == inner:
+            hrw.timing_enable(True)
         t0 = time.perf_counter()
         for _ in range(steps):
             r = step()
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        if timed == inner:
+            rows["roofline"] = _hop_roofline(hrw, "hop_kernel<N_R=3, RS=3, float> (the class also holds the few FP64 launches of the reliable updates)")
+            hrw.timing_enable(False)
         rows[inner] = {"solves_per_s": round(steps / el, 3), "ms_per_solve": round(el / steps * 1e3, 2),
                        "iters": r["iters"], "dhat_applies": 2 * r["iters"],
                        "reliable_updates": r["reliable_updates"], "restarts": r["restarts"],
@@ -324,15 +359,16 @@ def _even_part(dims, full):
     return np.ascontiguousarray(full[..., (x.sum(axis=0) & 1) == 0, :, :])
 
 
-def _solve_timed(hrw, torch, g, b, kappa, prm, steps, warmup):
+def _solve_timed(hrw, torch, g, b, kappa, prm, steps, warmup, solver=None):
+    solver = solver or hrw.cg_solve
     for _ in range(warmup):
-        hrw.cg_solve(g, b, kappa, prm)
+        solver(g, b, kappa, prm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     lat = []
     for _ in range(steps):
         ts = time.perf_counter()
-        x, res, rc = hrw.cg_solve(g, b, kappa, prm)
+        x, res, rc = solver(g, b, kappa, prm)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - ts)
         if rc != 0:
@@ -494,6 +530,7 @@ def workload_c4(args):
                                                    torch.linalg.vector_norm(x64[0])).item())}
     log(f"c4 n=24 f16 storage: {f16_row}")
     g16.close()
+    bicg = _c4_bicgstab(hrw, torch, g, srcs, kappa, theta, max(1, args.steps // 2))
     return _line(out[24]["rhs_solves_per_s"], "rhs-solves/s", max(1, args.steps // 2), 1, out[24]["ms_per_batch"],
                  "f32", {"workload": "su3_sym_32^4_multi_source_mixed_cg", "lattice": list(dims), "kappa": kappa,
                          "sources": "point-smeared (Gaussian spatial profile, width 2), 12 and 24",
@@ -502,7 +539,35 @@ def workload_c4(args):
                  fp64_cg={"solves_per_s": round(fp64_rate, 3), "iters": res64[0]["iters"],
                           "batched_24_rhs_solves_per_s": round(nmax / per64b, 3),
                           "batched_max_iters": max(q["iters"] for q in res64b)},
-                 multi_source=out, multi_source_24_f16_storage=f16_row, hbm_copy_reference=copy_reference(torch, dev))
+                 multi_source=out, multi_source_24_f16_storage=f16_row, bicgstab_propagators=bicg,
+                 hbm_copy_reference=copy_reference(torch, dev))
+
+
+def _c4_bicgstab(hrw, torch, g, srcs, kappa, theta, steps):
+    """The same sources as propagators, D_hat y = eta: BiCGstab on D_hat (plain FP64 one source at a
+    time, and 24 sources with FP32 inner fields and FP64 reliable updates) against FP64 CG on the
+    normal equations D_hat^+ D_hat y = D_hat^+ eta of the same system."""
+    n = srcs.shape[0]
+    eta_dag = hrw.deo_apply(g, kappa, srcs[0:1].contiguous(), theta, "f64", dagger=True)
+    prm_cg = hrw.solve_params(tol=1e-10, max_iter=20000, system="ddag_d_eo", inner_dtype="f64", theta=theta)
+    _, res_cg, per_cg, _ = _solve_timed(hrw, torch, g, eta_dag, kappa, prm_cg, steps, 1)
+    rows = {"fp64_cgnr_solves_per_s": round(1.0 / per_cg, 3), "fp64_cgnr_iters": res_cg[0]["iters"]}
+    prm64 = hrw.solve_params(tol=1e-10, max_iter=20000, system="dhat_eo", inner_dtype="f64", theta=theta)
+    y64, res64, per64, _ = _solve_timed(hrw, torch, g, srcs[0:1].contiguous(), kappa, prm64, steps, 1,
+                                        solver=hrw.bicgstab_solve)
+    rows["fp64_bicgstab"] = {"solves_per_s": round(1.0 / per64, 3), "iters": res64[0]["iters"],
+                             "vs_fp64_cgnr": round(per_cg / per64, 2)}
+    prm32 = hrw.solve_params(tol=1e-10, max_iter=20000, system="dhat_eo", inner_dtype="f32", theta=theta,
+                             reliable_delta=hrw.RELIABLE_DELTA["f32"])
+    y, res, per, _ = _solve_timed(hrw, torch, g, srcs, kappa, prm32, steps, 1, solver=hrw.bicgstab_solve)
+    rows[f"mixed_f32_{n}_sources"] = {
+        "rhs_solves_per_s": round(n / per, 3), "ms_per_batch": round(per * 1e3, 1),
+        "vs_fp64_cgnr": round(n / per * per_cg, 2), "max_iters": max(q["iters"] for q in res),
+        "max_true_rel_resid": max(q["true_rel_resid"] for q in res),
+        "rel_error_vs_fp64_source0": float((torch.linalg.vector_norm(y[0] - y64[0]) /
+                                            torch.linalg.vector_norm(y64[0])).item())}
+    log(f"c4 BiCGstab propagators: {rows}")
+    return rows
 
 
 def workload_c5(args):
