@@ -90,6 +90,16 @@ enum hrw_dtype { HRW_F64 = 0, HRW_F32 = 1, HRW_BF16 = 2, HRW_F16 = 3 };
 #define HRW_STORE_F32 (1u << HRW_F32)
 #define HRW_STORE_BF16 (1u << HRW_BF16)
 #define HRW_STORE_F16 (1u << HRW_F16)
+/* Also keep the fundamental links, in the hopping layout of every precision in
+ * the mask, and let single-source hops build the rows of U_R from them in
+ * registers (the representation map fused into the hop: the link stream
+ * shrinks by N^2 / N_R^2 for extra arithmetic).  Built for SU(2) adjoint and
+ * symmetric, SU(3) symmetric and SU(4) antisymmetric; HRW_EUNSUPPORTED for
+ * the others.  Results agree with the stored-U_R path to rounding (U_R is
+ * evaluated in the arithmetic precision of the hop).  Multi-source launches
+ * keep using the stored U_R.  Sec. 3.1.2 (the represented link is built from
+ * the fundamental one). */
+#define HRW_STORE_FUND_HOP (1u << 4)
 
 /* Linear systems: 0-2 for hrw_cg_solve (Hermitian positive definite normal
  * equations), 3-4 for hrw_bicgstab_solve (the operator itself). */

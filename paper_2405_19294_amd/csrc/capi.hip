@@ -55,6 +55,14 @@ int check_dtype(int dt)
     return HRW_OK;
 }
 
+int check_storage_mask(int nc, int rep, unsigned mask)
+{
+    if (!(mask & 0xf) || (mask & ~0x1fu)) return fail(HRW_EINVAL, "bad storage mask 0x%x", mask);
+    if ((mask & HRW_STORE_FUND_HOP) && !hop_fused_supported(nc, rep))
+        return fail(HRW_EUNSUPPORTED, "the fused representation map is built for SU(2) adj/sym, SU(3) sym, SU(4) asym");
+    return HRW_OK;
+}
+
 int check_rhs(int n)
 {
     if (n < 1 || n > MAX_RHS) return fail(HRW_EINVAL, "n_rhs = %d outside 1..%d", n, MAX_RHS);
@@ -111,8 +119,8 @@ int hrw_gauge_storage_size(const int dims[4], int nc, int rep, unsigned storage_
     return guarded([&] {
         int nr, rc;
         if ((rc = check_lattice(dims)) || (rc = check_group(nc, rep, &nr))) return rc;
-        if (!bytes || !(storage_mask & 0xf) || (storage_mask & ~0xfu)) return fail(HRW_EINVAL, "bad storage mask or null output");
-        return gauge_storage_bytes(make_geom(dims), nr, storage_mask, bytes);
+        if (!bytes || (rc = check_storage_mask(nc, rep, storage_mask))) return rc ? rc : fail(HRW_EINVAL, "null output");
+        return gauge_storage_bytes(make_geom(dims), nc, nr, storage_mask, bytes);
     });
 }
 
@@ -123,10 +131,10 @@ int hrw_gauge_create(const int dims[4], int nc, int rep, const double *u_f, unsi
         int nr, rc;
         if ((rc = check_lattice(dims)) || (rc = check_group(nc, rep, &nr))) return rc;
         if (!u_f || !storage || !out) return fail(HRW_EINVAL, "null pointer");
-        if (!(storage_mask & 0xf) || (storage_mask & ~0xfu)) return fail(HRW_EINVAL, "bad storage mask");
+        if ((rc = check_storage_mask(nc, rep, storage_mask))) return rc;
         const Geom g = make_geom(dims);
         size_t need;
-        gauge_storage_bytes(g, nr, storage_mask, &need);
+        gauge_storage_bytes(g, nc, nr, storage_mask, &need);
         if (storage_bytes < need) return fail(HRW_ENOMEM, "storage too small: need %zu bytes", need);
         hrw_gauge *h = new hrw_gauge;
         memset(h, 0, sizeof *h);
@@ -140,7 +148,14 @@ int hrw_gauge_create(const int dims[4], int nc, int rep, const double *u_f, unsi
         for (int d = 0; d < 4; ++d)
             if (storage_mask & (1u << d))
                 for (int q = 0; q < 2; ++q) h->blocks[d][q] = ar.take(gauge_block_elems(g, nr) * dtype_cbytes(d));
+        if (storage_mask & HRW_STORE_FUND_HOP)
+            for (int d = 0; d < 4; ++d)
+                if (storage_mask & (1u << d))
+                    for (int q = 0; q < 2; ++q) h->fblocks[d][q] = ar.take(gauge_block_elems(g, nc) * dtype_cbytes(d));
         hipError_t e = launch_gauge_pack(nc, rep, nr, g, u_f, h->blocks, (hipStream_t)stream);
+        // the fundamental links in the same hopping layout (representation map = identity)
+        if (e == hipSuccess && (storage_mask & HRW_STORE_FUND_HOP))
+            e = launch_gauge_pack(nc, HRW_REP_FUND, nc, g, u_f, h->fblocks, (hipStream_t)stream);
         if (e != hipSuccess) {
             delete h;
             return fail(HRW_EDEVICE, "gauge packing failed: %s", hipGetErrorString(e));

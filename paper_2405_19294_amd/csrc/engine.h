@@ -15,6 +15,7 @@ struct hrw_gauge {
     unsigned mask;
     hrw::Geom g;
     void *blocks[4][2];  // [dtype][output parity] packed hopping blocks (or null)
+    void *fblocks[4][2]; // fundamental links in the hopping layout for the fused representation map (or null)
 };
 
 namespace hrw {
@@ -83,7 +84,7 @@ struct Phases {
 Phases make_phases(const double theta[4]);
 
 // algorithmic bytes of one hop launch (min-traffic model)
-double hop_bytes(const Geom &g, int nr, int dt, int parity, int epi, int n_rhs);
+double hop_bytes(const Geom &g, int nr, int dt, int parity, int epi, int n_rhs, int fused_nc = 0);
 
 // generic hop launch with timing, dtype-erased pointers
 struct HopCall {
@@ -122,7 +123,7 @@ void host_flags_release(HostFlags *f);
 
 // ------------------------------------------------------------------ engine entry points
 
-int gauge_storage_bytes(const Geom &g, int nr, unsigned mask, size_t *bytes);
+int gauge_storage_bytes(const Geom &g, int nc, int nr, unsigned mask, size_t *bytes);
 int apply_workspace(const Geom &g, int nr, int n_rhs, size_t *bytes);
 int cg_workspace(const Geom &g, int nr, int n_rhs, const hrw_solve_params *p, size_t *bytes);
 

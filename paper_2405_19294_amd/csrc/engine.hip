@@ -113,24 +113,28 @@ Phases make_phases(const double theta[4])
     return p;
 }
 
-double hop_bytes(const Geom &g, int nr, int dt, int parity, int epi, int n_rhs)
+double hop_bytes(const Geom &g, int nr, int dt, int parity, int epi, int n_rhs, int fused_nc)
 {
     const double sites = (double)g.half * (parity < 0 ? 2 : 1);
     const double cb = (double)dtype_cbytes(dt);
-    const double links = 8.0 * nr * nr * cb;
+    // the fused representation map streams the N x N fundamental links
+    const double links = 8.0 * (fused_nc ? fused_nc * fused_nc : nr * nr) * cb;
     const double sp = 4.0 * nr * cb;
     double per = sp;  // neighbour spinors (each input spinor once)
     if (epi == EPI_PLAIN) per += sp;            // out
     else if (epi == EPI_AXPY) per += 2 * sp;    // self + out
     else per += 6 * sp;                         // self, r, x, p read; r, x written
     // the multi-source kernel reads each link once for all sources
-    const double link_reads = hop_uses_mrhs(nr, dt, n_rhs) ? 1.0 : (double)n_rhs;
+    const double link_reads = !fused_nc && hop_uses_mrhs(nr, dt, n_rhs) ? 1.0 : (double)n_rhs;
     return (per * n_rhs + links * link_reads) * sites;
 }
 
 int run_hop(const hrw_gauge *g, const Phases &ph, const HopCall &c, hipStream_t st)
 {
     if (!g->blocks[c.dt][0]) return fail(HRW_EUNSUPPORTED, "gauge field has no links stored in dtype %d", c.dt);
+    // single-source launches of a field that keeps its fundamental links build U_R in the hop;
+    // the multi-source kernel keeps its LDS copy of the stored U_R
+    const int fused_nc = (g->fblocks[c.dt][0] && !hop_uses_mrhs(g->nr, c.dt, c.n_rhs)) ? g->nc : 0;
     hipEvent_t ev;
     const bool tm = timed_begin(st, &ev);
     hipError_t err = hipErrorInvalidValue;
@@ -143,7 +147,7 @@ int run_hop(const hrw_gauge *g, const Phases &ph, const HopCall &c, hipStream_t 
         a.n_rhs = c.n_rhs;
         a.rstride = c.rstride;
         for (int q = 0; q < 2; ++q) {
-            a.gauge[q] = (const cpx<S> *)g->blocks[c.dt][q];
+            a.gauge[q] = (const cpx<S> *)(fused_nc ? g->fblocks[c.dt][q] : g->blocks[c.dt][q]);
             a.in[q] = (const cpx<S> *)c.in[q];
             a.out[q] = (cpx<S> *)c.out[q];
             a.self[q] = (const cpx<S> *)c.self[q];
@@ -161,10 +165,13 @@ int run_hop(const hrw_gauge *g, const Phases &ph, const HopCall &c, hipStream_t 
         a.run = c.run;
         a.partial = c.partial;
         a.pstride = c.pstride;
-        err = launch_hop<S>(g->nr, c.dagger, c.epi, a, st);
+        err = fused_nc ? launch_hop_fused<S>(g->nc, g->rep, c.dagger, c.epi, a, st)
+                       : launch_hop<S>(g->nr, c.dagger, c.epi, a, st);
     });
     if (err != hipSuccess) return fail(HRW_EDEVICE, "hop launch failed: %s", hipGetErrorString(err));
-    if (tm) timed_end(st, ev, KC_HOP, KC_HOP_PLAIN + c.epi, hop_bytes(g->g, g->nr, c.dt, c.parity, c.epi, c.n_rhs));
+    if (tm)
+        timed_end(st, ev, KC_HOP, KC_HOP_PLAIN + c.epi,
+                  hop_bytes(g->g, g->nr, c.dt, c.parity, c.epi, c.n_rhs, fused_nc));
     return HRW_OK;
 }
 
@@ -224,12 +231,16 @@ void host_flags_release(HostFlags *f)
 
 // ------------------------------------------------------------------ sizes
 
-int gauge_storage_bytes(const Geom &g, int nr, unsigned mask, size_t *bytes)
+int gauge_storage_bytes(const Geom &g, int nc, int nr, unsigned mask, size_t *bytes)
 {
     Arena ar(nullptr, 0);
     for (int d = 0; d < 4; ++d)
         if (mask & (1u << d))
             for (int q = 0; q < 2; ++q) ar.take(gauge_block_elems(g, nr) * dtype_cbytes(d));
+    if (mask & HRW_STORE_FUND_HOP)
+        for (int d = 0; d < 4; ++d)
+            if (mask & (1u << d))
+                for (int q = 0; q < 2; ++q) ar.take(gauge_block_elems(g, nc) * dtype_cbytes(d));
     *bytes = ar.off + 256;
     return HRW_OK;
 }

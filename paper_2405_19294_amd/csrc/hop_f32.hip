@@ -9,4 +9,9 @@ hipError_t launch_hop<float>(int nr, bool dagger, int epi, const HopArgs<float> 
     if (hop_uses_mfma(nr, 1, a.n_rhs)) return launch_hop_mfma<6>(dagger, epi, a, st);
     return launch_hop_impl<float>(nr, dagger, epi, a, st);
 }
+template <>
+hipError_t launch_hop_fused<float>(int nc, int rep, bool dagger, int epi, const HopArgs<float> &a, hipStream_t st)
+{
+    return launch_hop_fused_impl<float>(nc, rep, dagger, epi, a, st);
+}
 }  // namespace hrw

@@ -145,6 +145,10 @@ __device__ __forceinline__ void link_row(const A (&ur)[NR], const A (&ui)[NR], c
 template <class S, int NR>
 struct GlobalLinks {
     static constexpr bool ROWWISE = false;  // all rows' loads issued up front (HBM latency)
+    static constexpr bool FUSED = false;
+    static constexpr bool REAL = false;
+    static constexpr int NF = 1;
+    static constexpr int REPID = 0;
     const cpx<S> *__restrict__ g;
     int i;
     __device__ __forceinline__ void load(int comp, typename acc_of<S>::type &re,
@@ -157,6 +161,10 @@ struct GlobalLinks {
 template <class S>
 struct LdsLinks {
     static constexpr bool ROWWISE = true;  // one row at a time: fewer live registers
+    static constexpr bool FUSED = false;
+    static constexpr bool REAL = false;
+    static constexpr int NF = 1;
+    static constexpr int REPID = 0;
     const cpx<S> *l;  // [comp][MR_SITES]
     int s;
     __device__ __forceinline__ void load(int comp, typename acc_of<S>::type &re,
@@ -165,6 +173,152 @@ struct LdsLinks {
         load_c(l + comp * MR_SITES + s, re, im);
     }
 };
+
+// Fundamental links in HBM (the N x N hopping blocks: U(x) forward, U(x - mu)^+
+// backward) and the rows of U_R built from them in registers: the
+// representation map fused into the hop.  R(U^+) = R(U)^+ for a unitary U, so
+// the backward slots need no separate formula.
+template <class S, int N, int REP>
+struct RepLinks {
+    static constexpr bool ROWWISE = true;
+    static constexpr bool FUSED = true;
+    static constexpr bool REAL = REP == 1;  // the adjoint representation is real
+    static constexpr int NF = N;
+    static constexpr int REPID = REP;
+    const cpx<S> *__restrict__ g;
+    int i;
+    template <class A>
+    __device__ __forceinline__ void load_fund(int dd, A (&fr)[N][N], A (&fi)[N][N]) const
+    {
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+#pragma unroll
+            for (int c = 0; c < N; ++c) load_c_nt(g + lay(i, dd * N * N + r * N + c, 8 * N * N), fr[r][c], fi[r][c]);
+    }
+};
+
+// (j, k) of the q-th index pair in lexicographic order: j <= k with the
+// diagonal (symmetric basis), j < k without it (antisymmetric basis)
+__host__ __device__ constexpr int pair_j(int n, bool diag, int q)
+{
+    int j = 0;
+    while (q >= (diag ? n - j : n - j - 1)) {
+        q -= diag ? n - j : n - j - 1;
+        ++j;
+    }
+    return j;
+}
+__host__ __device__ constexpr int pair_k(int n, bool diag, int q)
+{
+    int j = 0;
+    while (q >= (diag ? n - j : n - j - 1)) {
+        q -= diag ? n - j : n - j - 1;
+        ++j;
+    }
+    return diag ? j + q : j + 1 + q;
+}
+
+// Row a of U_R from the fundamental link u = (fr, fi).
+//   antisymmetric, basis (E_jk - E_kj)/sqrt2:  (U_R)_(jk),(lm) = u_jl u_km - u_jm u_kl
+//   symmetric, basis E_jj and (E_jk + E_kj)/sqrt2:
+//       (U_R)_(jk),(lm) = (u_jl u_km + u_jm u_kl) 2 c_jk c_lm,  c = 1/2 on the diagonal, 1/sqrt2 off it
+//   SU(2) adjoint, T^a = sigma_a / 2:  (U_R)_ab = (1/2) Re Tr(sigma_a u sigma_b u^+), i.e. the Pauli
+//       components of W = u^+ sigma_a u:  (Re w01, -Im w01, w00)
+// The rows j, k of u are picked with selects, so a row index that differs
+// between the lanes of a wavefront costs no dynamic register indexing.
+template <int N, int REP, int NR, class A>
+__device__ __forceinline__ void rep_row(const A (&fr)[N][N], const A (&fi)[N][N], int a, A (&lr)[NR],
+                                        A (&li)[NR])
+{
+    if constexpr (REP == 1) {
+        static_assert(N == 2 && NR == 3, "fused adjoint row: SU(2) only");
+        // z = conj(u00) u10, and the (0, 1) entry of W for each sigma_a
+        const A zr = fr[0][0] * fr[1][0] + fi[0][0] * fi[1][0];
+        const A zi = fr[0][0] * fi[1][0] - fi[0][0] * fr[1][0];
+        A w00, w01r, w01i;
+        if (a == 0) {  // sigma_1: w01 = conj(u00) u11 + conj(u10) u01
+            w00 = zr + zr;
+            w01r = fr[0][0] * fr[1][1] + fi[0][0] * fi[1][1] + fr[1][0] * fr[0][1] + fi[1][0] * fi[0][1];
+            w01i = fr[0][0] * fi[1][1] - fi[0][0] * fr[1][1] + fr[1][0] * fi[0][1] - fi[1][0] * fr[0][1];
+        } else if (a == 1) {  // sigma_2: w01 = -i conj(u00) u11 + i conj(u10) u01
+            w00 = zi + zi;
+            const A ar = fr[0][0] * fr[1][1] + fi[0][0] * fi[1][1], ai = fr[0][0] * fi[1][1] - fi[0][0] * fr[1][1];
+            const A br = fr[1][0] * fr[0][1] + fi[1][0] * fi[0][1], bi = fr[1][0] * fi[0][1] - fi[1][0] * fr[0][1];
+            w01r = ai - bi;
+            w01i = br - ar;
+        } else {  // sigma_3: w01 = conj(u00) u01 - conj(u10) u11
+            w00 = fr[0][0] * fr[0][0] + fi[0][0] * fi[0][0] - fr[1][0] * fr[1][0] - fi[1][0] * fi[1][0];
+            w01r = fr[0][0] * fr[0][1] + fi[0][0] * fi[0][1] - fr[1][0] * fr[1][1] - fi[1][0] * fi[1][1];
+            w01i = fr[0][0] * fi[0][1] - fi[0][0] * fr[0][1] - fr[1][0] * fi[1][1] + fi[1][0] * fr[1][1];
+        }
+        lr[0] = w01r;
+        lr[1] = -w01i;
+        lr[2] = w00;
+        li[0] = li[1] = li[2] = (A)0;
+    } else {
+        constexpr bool DIAG = REP == 2;
+        int q = a, j = 0, k = 0;
+#pragma unroll
+        for (int jj = 0; jj < N; ++jj) {
+            const int cnt = DIAG ? N - jj : N - jj - 1;
+            if (q >= 0 && q < cnt) {
+                j = jj;
+                k = DIAG ? jj + q : jj + 1 + q;
+            }
+            q -= cnt;
+        }
+        A ujr[N], uji[N], ukr[N], uki[N];
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+            ujr[c] = fr[0][c];
+            uji[c] = fi[0][c];
+            ukr[c] = fr[0][c];
+            uki[c] = fi[0][c];
+        }
+#pragma unroll
+        for (int t = 1; t < N; ++t)
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                ujr[c] = j == t ? fr[t][c] : ujr[c];
+                uji[c] = j == t ? fi[t][c] : uji[c];
+                ukr[c] = k == t ? fr[t][c] : ukr[c];
+                uki[c] = k == t ? fi[t][c] : uki[c];
+            }
+        const A cj = DIAG ? (j == k ? (A)1 : (A)M_SQRT2) : (A)1;  // 2 c_jk
+#pragma unroll
+        for (int b = 0; b < NR; ++b) {
+            const int l = pair_j(N, DIAG, b), m = pair_k(N, DIAG, b);
+            const A pr = ujr[l] * ukr[m] - uji[l] * uki[m], pi = ujr[l] * uki[m] + uji[l] * ukr[m];
+            const A qr = ujr[m] * ukr[l] - uji[m] * uki[l], qi = ujr[m] * uki[l] + uji[m] * ukr[l];
+            if (DIAG) {
+                const A f = cj * (l == m ? (A)0.5 : (A)M_SQRT1_2);
+                lr[b] = f * (pr + qr);
+                li[b] = f * (pi + qi);
+            } else {
+                lr[b] = pr - qr;
+                li[b] = pi - qi;
+            }
+        }
+    }
+}
+
+// g = U h for a real link row
+template <class A, int NR>
+__device__ __forceinline__ void link_row_real(const A (&ur)[NR], const A (&hr)[2][NR], const A (&hi)[2][NR],
+                                              A &s0r, A &s0i, A &s1r, A &s1i)
+{
+    s0r = ur[0] * hr[0][0];
+    s0i = ur[0] * hi[0][0];
+    s1r = ur[0] * hr[1][0];
+    s1i = ur[0] * hi[1][0];
+#pragma unroll
+    for (int c = 1; c < NR; ++c) {
+        s0r = fmac(ur[c], hr[0][c], s0r);
+        s0i = fmac(ur[c], hi[0][c], s0i);
+        s1r = fmac(ur[c], hr[1][c], s1r);
+        s1i = fmac(ur[c], hi[1][c], s1i);
+    }
+}
 
 // one direction (forward or backward) of one mu, for colour rows r0 .. r0+RS-1
 template <int MU, int DIR, bool DAG, int NR, int RS, class S, class LS>
@@ -198,12 +352,15 @@ __device__ __forceinline__ void hop_dir(const HopArgs<S> &a, const cpx<S> *__res
     // links from HBM: every row's loads are issued together with the spinor's,
     // before any arithmetic waits on them (unused when links come from LDS)
     A ur[LS::ROWWISE ? 1 : RS][NR], ui[LS::ROWWISE ? 1 : RS][NR];
-    if (!LS::ROWWISE) {
+    if constexpr (!LS::ROWWISE) {
 #pragma unroll
         for (int r = 0; r < RS; ++r)
 #pragma unroll
             for (int c = 0; c < NR; ++c) links.load(DD * NR * NR + (r0 + r) * NR + c, ur[r][c], ui[r][c]);
     }
+    // fundamental link of this direction (fused representation map)
+    A fr[LS::NF][LS::NF], fi[LS::NF][LS::NF];
+    if constexpr (LS::FUSED) links.load_fund(DD, fr, fi);
     A hr[2][NR], hi[2][NR];
     project<MU, SG>(pr, pi, hr, hi);
     if (wrap) {
@@ -219,15 +376,20 @@ __device__ __forceinline__ void hop_dir(const HopArgs<S> &a, const cpx<S> *__res
                 hi[k][c] = ti;
             }
     }
-    if (LS::ROWWISE) {
-        // links from LDS: fetch, multiply and reconstruct one row at a time
+    if constexpr (LS::ROWWISE) {
+        // links from LDS (or built from the fundamental link): one row at a time
 #pragma unroll
         for (int r = 0; r < RS; ++r) {
             A lr[NR], li[NR];
+            if constexpr (LS::FUSED) {
+                rep_row<LS::NF, LS::REPID>(fr, fi, r0 + r, lr, li);
+            } else {
 #pragma unroll
-            for (int c = 0; c < NR; ++c) links.load(DD * NR * NR + (r0 + r) * NR + c, lr[c], li[c]);
+                for (int c = 0; c < NR; ++c) links.load(DD * NR * NR + (r0 + r) * NR + c, lr[c], li[c]);
+            }
             A s0r, s0i, s1r, s1i;
-            link_row(lr, li, hr, hi, s0r, s0i, s1r, s1i);
+            if constexpr (LS::REAL) link_row_real(lr, hr, hi, s0r, s0i, s1r, s1i);
+            else link_row(lr, li, hr, hi, s0r, s0i, s1r, s1i);
             reconstruct_row<MU, SG>(s0r, s0i, s1r, s1i, ar[0][r], ai[0][r], ar[1][r], ai[1][r], ar[2][r],
                                     ai[2][r], ar[3][r], ai[3][r]);
         }
@@ -389,6 +551,37 @@ __global__ void __launch_bounds__(WG) hop_kernel(const HopArgs<S> a)
     double nrm = 0;
     if (i < a.g.half) {
         GlobalLinks<S, NR> links{a.gauge[parity], i};
+        nrm = site_hop<NR, RS, S, DAG, EPI>(a, parity, i, r0, rhs, links);
+    }
+    if (EPI != EPI_PLAIN && a.partial) {
+        const double t = group_sum<G>(nrm, sh);
+        const int grp = i / PG_SITES;
+        if ((threadIdx.x & (PG_SITES * G - 1)) == 0 && grp < a.ngroups)
+            a.partial[(size_t)rhs * a.pstride + (a.parity < 0 ? parity * a.ngroups : 0) + grp] = t;
+    }
+}
+
+// The single-source kernel with the representation map fused in (RepLinks):
+// a.gauge[q] holds the fundamental hopping blocks of output parity q.
+template <int N, int REP, int NR, int RS, class S, bool DAG, int EPI>
+__global__ void __launch_bounds__(WG) hop_fused_kernel(const HopArgs<S> a)
+{
+    constexpr int G = NR / RS;
+    __shared__ double sh[WG / 64];
+    int parity = a.parity, bx = blockIdx.x;
+    if (parity < 0) {
+        parity = bx >= a.grid_half;
+        if (parity) bx -= a.grid_half;
+    }
+    bx = tile_remap(xcd_remap(bx, a.grid_half), a.grid_half, a.tile_ts, a.tile_c);
+    const int rhs = blockIdx.y;
+    if (a.run && !a.run[rhs]) return;
+    const int gid = bx * WG + threadIdx.x;
+    const int i = gid / G;
+    const int r0 = (gid - i * G) * RS;
+    double nrm = 0;
+    if (i < a.g.half) {
+        RepLinks<S, N, REP> links{a.gauge[parity], i};
         nrm = site_hop<NR, RS, S, DAG, EPI>(a, parity, i, r0, rhs, links);
     }
     if (EPI != EPI_PLAIN && a.partial) {
@@ -698,6 +891,44 @@ hipError_t launch_hop_impl(int nr, bool dagger, int epi, const HopArgs<S> &a, hi
     });
     if (!ok) return hipErrorInvalidValue;
     if (err != hipSuccess) return err;
+    return hipGetLastError();
+}
+
+// Fused representation map: one grid row per source (the multi-source kernel
+// keeps its LDS copy of U_R), same tiling and partial-sum groups as hop_kernel.
+template <class S>
+hipError_t launch_hop_fused_impl(int nc, int rep, bool dagger, int epi, const HopArgs<S> &a, hipStream_t st)
+{
+    if (epi == EPI_CG && !dagger) return hipErrorInvalidValue;
+    HopArgs<S> b = a;
+    bool ok = false;
+    auto go = [&](auto nv, auto rv) {
+        constexpr int N = decltype(nv)::value;
+        constexpr int REP = decltype(rv)::value;
+        constexpr int NR = REP == 1 ? N * N - 1 : REP == 2 ? N * (N + 1) / 2 : N * (N - 1) / 2;
+        constexpr int RS = hop_rows(NR, dtype_id<S>());
+        constexpr int G = NR / RS;
+        b.ngroups = hop_groups(a.g);
+        const int gh = hop_grid(a.g, G);
+        b.grid_half = gh;
+        hop_tiling(a.g, WG / G, &b.tile_ts, &b.tile_c);
+        dim3 grid(a.parity < 0 ? 2 * gh : gh, a.n_rhs);
+        if (epi == EPI_PLAIN) {
+            if (dagger) hop_fused_kernel<N, REP, NR, RS, S, true, EPI_PLAIN><<<grid, WG, 0, st>>>(b);
+            else hop_fused_kernel<N, REP, NR, RS, S, false, EPI_PLAIN><<<grid, WG, 0, st>>>(b);
+        } else if (epi == EPI_AXPY) {
+            if (dagger) hop_fused_kernel<N, REP, NR, RS, S, true, EPI_AXPY><<<grid, WG, 0, st>>>(b);
+            else hop_fused_kernel<N, REP, NR, RS, S, false, EPI_AXPY><<<grid, WG, 0, st>>>(b);
+        } else {
+            hop_fused_kernel<N, REP, NR, RS, S, true, EPI_CG><<<grid, WG, 0, st>>>(b);
+        }
+        ok = true;
+    };
+    if (nc == 2 && rep == 1) go(std::integral_constant<int, 2>{}, std::integral_constant<int, 1>{});
+    else if (nc == 2 && rep == 2) go(std::integral_constant<int, 2>{}, std::integral_constant<int, 2>{});
+    else if (nc == 3 && rep == 2) go(std::integral_constant<int, 3>{}, std::integral_constant<int, 2>{});
+    else if (nc == 4 && rep == 3) go(std::integral_constant<int, 4>{}, std::integral_constant<int, 3>{});
+    if (!ok) return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

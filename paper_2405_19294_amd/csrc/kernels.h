@@ -84,6 +84,19 @@ struct HopArgs {
 template <class S>
 hipError_t launch_hop(int nr, bool dagger, int epi, const HopArgs<S> &a, hipStream_t st);
 
+// Hopping kernel with the representation map fused in: a.gauge holds the
+// fundamental links (packed like the N x N fundamental hopping blocks) and
+// each thread builds the rows of U_R it needs in registers, so the link
+// stream shrinks by N^2 / N_R^2.  Built for the representations whose rows
+// are cheap closed forms: SU(2) adjoint and symmetric, SU(3) symmetric,
+// SU(4) antisymmetric.
+constexpr bool hop_fused_supported(int nc, int rep)
+{
+    return (nc == 2 && (rep == 1 || rep == 2)) || (nc == 3 && rep == 2) || (nc == 4 && rep == 3);
+}
+template <class S>
+hipError_t launch_hop_fused(int nc, int rep, bool dagger, int epi, const HopArgs<S> &a, hipStream_t st);
+
 // Colour rows each thread of the hopping kernel owns (threads per site =
 // N_R / rows): the colour-parallel split keeps the registers of the larger
 // representations below the spill point (zero scratch for every instance,

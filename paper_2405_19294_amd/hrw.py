@@ -142,23 +142,32 @@ def rep_map(nc: int, rep: str, u_f: torch.Tensor, stream=None) -> torch.Tensor:
     return out
 
 
-def gauge_storage_size(dims, nc: int, rep: str, dtypes=("f64",)) -> int:
+STORE_FUND_HOP = 1 << 4  # keep the fundamental links too: single-source hops build U_R in registers
+
+
+def _storage_mask(dtypes, fused: bool) -> int:
+    return sum(1 << DTYPES[d] for d in dtypes) | (STORE_FUND_HOP if fused else 0)
+
+
+def gauge_storage_size(dims, nc: int, rep: str, dtypes=("f64",), fused: bool = False) -> int:
     out = ctypes.c_size_t()
-    mask = sum(1 << DTYPES[d] for d in dtypes)
-    _check(load().hrw_gauge_storage_size(_ints(dims), nc, REPS[rep], mask, ctypes.byref(out)))
+    _check(load().hrw_gauge_storage_size(_ints(dims), nc, REPS[rep], _storage_mask(dtypes, fused),
+                                         ctypes.byref(out)))
     return out.value
 
 
 class Gauge:
     """Resident represented gauge field: a handle plus the torch storage it lives in."""
 
-    def __init__(self, dims, nc: int, rep: str, u_f: torch.Tensor, dtypes=("f64", "f32"), stream=None):
+    def __init__(self, dims, nc: int, rep: str, u_f: torch.Tensor, dtypes=("f64", "f32"), stream=None,
+                 fused: bool = False):
         self.dims = tuple(int(d) for d in dims)
         self.nc, self.rep = int(nc), rep
         self.nr = rep_dim(nc, rep)
         self.dtypes = tuple(dtypes)
-        mask = sum(1 << DTYPES[d] for d in dtypes)
-        nbytes = gauge_storage_size(dims, nc, rep, dtypes)
+        self.fused = bool(fused)
+        mask = _storage_mask(dtypes, fused)
+        nbytes = gauge_storage_size(dims, nc, rep, dtypes, fused)
         self.storage = _alloc_bytes(nbytes, u_f.device)
         h = ctypes.c_void_p()
         _check(load().hrw_gauge_create(_ints(dims), nc, REPS[rep], _dev_field(u_f, "u_f"), mask,
@@ -183,8 +192,8 @@ class Gauge:
         return d[0] * d[1] * d[2] * d[3]
 
 
-def gauge_create(dims, nc, rep, u_f, dtypes=("f64", "f32"), stream=None) -> Gauge:
-    return Gauge(dims, nc, rep, u_f, dtypes, stream)
+def gauge_create(dims, nc, rep, u_f, dtypes=("f64", "f32"), stream=None, fused=False) -> Gauge:
+    return Gauge(dims, nc, rep, u_f, dtypes, stream, fused)
 
 
 def workspace_size(dims, nc: int, rep: str, n_rhs: int = 1, params: SolveParams | None = None) -> int:

@@ -1,0 +1,129 @@
+"""GPU parity of the hops with the representation map fused in (gauge fields created with the
+fundamental links kept, HRW_STORE_FUND_HOP) against the CPU oracle.
+
+Tolerances:
+  * FP64: the same as the stored-U_R path (l2 relative <= 1e-13, componentwise <= 1e-12 max|ref|);
+    the rows of U_R are built from U in FP64 and R(U^+) = R(U)^+ holds to the unitarity of U.
+  * FP32 arithmetic on FP32 / BF16 / FP16 storage: the oracle applies FP64 D with U_R = R(U_r), the
+    representation map of the rounded stored fundamental links U_r, to the rounded input.  Besides
+    the hop's own bound gamma_k (|psi| + kappa |H||psi|) (k = 2 N_R + 16, u = 2^-24) the kernel's
+    evaluation of each U_R entry from U_r adds at most 2 gamma_5 (every entry is a sum of at most
+    four products of entries of modulus <= 1), which enters as kappa 2 gamma_5 |H|_1 |psi| with
+    |H|_1 the hop with every link entry set to 1; plus one rounding of the stored output.
+"""
+
+import numpy as np
+import pytest
+
+import fixtures as fx
+import oracle as orc
+from paper_2405_19294_amd import hrw
+
+from gpu_helpers import THETA_AP, THETA_TW, U32, U_BF16, U_F16, fp64_close, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ((4, 4, 2, 4), 2, "adj"),
+    ((4, 2, 4, 4), 2, "sym"),
+    ((4, 4, 2, 4), 3, "sym"),
+    ((2, 4, 4, 4), 4, "asym"),
+    ((2, 2, 2, 6), 3, "sym"),      # ragged half field (24 sites)
+    ((8, 8, 8, 8), 3, "sym"),      # several tiles
+    ((6, 4, 4, 8), 2, "adj"),
+]
+
+
+def ids(c):
+    return f"{'x'.join(map(str, c[0]))}-su{c[1]}-{c[2]}"
+
+
+def fused_setup(dims, nc, rep, dtypes=("f64", "f32", "bf16", "f16"), seed=11, kind="haar"):
+    uf = fx.gauge_field(dims, nc, kind, seed=seed)
+    ur = orc.rep_map(nc, rep, uf)
+    g = hrw.Gauge(dims, nc, rep, to_dev(uf), dtypes=dtypes, fused=True)
+    return uf, ur, g
+
+
+@pytest.mark.parametrize("case", CASES, ids=ids)
+def test_fused_f64_operators(case):
+    dims, nc, rep = case
+    uf, ur, g = fused_setup(dims, nc, rep, dtypes=("f64",))
+    kappa = 0.131
+    psi = fx.gaussian_spinor(dims, g.nr, seed=12)
+    for dagger in (False, True):
+        out = hrw.dw_apply(g, kappa, to_dev(psi), THETA_TW, "f64", dagger=dagger).cpu().numpy()
+        fp64_close(out, orc.dw(dims, ur, kappa, psi, THETA_TW, dagger=dagger))
+    pe, po = orc.split_eo(dims, psi)
+    for dagger in (False, True):
+        out = hrw.deo_apply(g, kappa, to_dev(pe), THETA_TW, "f64", dagger=dagger).cpu().numpy()
+        fp64_close(out, orc.deo(dims, ur, kappa, pe, THETA_TW, dagger=dagger))
+    out = hrw.hop_eo(g, 1, to_dev(pe), THETA_TW, "f64").cpu().numpy()
+    fp64_close(out, orc.hop_eo(dims, ur, pe, 1, THETA_TW))
+    out = hrw.hop_eo(g, 0, to_dev(po), THETA_TW, "f64").cpu().numpy()
+    fp64_close(out, orc.hop_eo(dims, ur, po, 0, THETA_TW))
+
+
+@pytest.mark.parametrize("case", CASES[:5], ids=ids)
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
+def test_fused_low_precision_within_bound(case, dtype):
+    dims, nc, rep = case
+    uf, ur, g = fused_setup(dims, nc, rep, dtypes=(dtype,), seed=13)
+    kappa = 0.137
+    psi = fx.gaussian_spinor(dims, g.nr, seed=14)
+    uf_r = orc.round_to(dtype, uf)
+    ur_ref = orc.rep_map(nc, rep, uf_r)
+    psi_r = orc.round_to(dtype, psi)
+    out = hrw.dw_apply(g, kappa, to_dev(psi), THETA_TW, dtype).cpu().numpy()
+    ref = orc.dw(dims, ur_ref, kappa, psi_r, THETA_TW)
+    nr = g.nr
+    unit_out = {"f32": U32, "bf16": U_BF16, "f16": U_F16}[dtype]
+    ones = np.ones_like(np.abs(ur_ref))
+    bound = (orc.gamma_k(2 * nr + 16, U32) * (np.abs(psi_r) + kappa * orc.hop_abs(dims, np.abs(ur_ref), np.abs(psi_r)))
+             + 2 * orc.gamma_k(5, U32) * kappa * orc.hop_abs(dims, ones, np.abs(psi_r))
+             + unit_out * np.abs(ref) + 1e-300)
+    excess = np.max(np.abs(out - ref) / bound)
+    assert excess <= 1.0, excess
+    assert rel(out, orc.dw(dims, ur, kappa, psi, THETA_TW)) < {"f32": 1e-6, "bf16": 2e-2, "f16": 3e-3}[dtype]
+
+
+def test_fused_matches_stored_path_and_multi_source_keeps_stored_links():
+    """FP64 fused and stored-U_R applies agree to rounding; with enough sources for the multi-source
+    kernel a fused field takes the stored U_R (bitwise the result of a field without the flag)."""
+    dims, nc, rep = (4, 4, 4, 4), 3, "sym"
+    uf = fx.gauge_field(dims, nc, "thermal", seed=15)
+    gf = hrw.Gauge(dims, nc, rep, to_dev(uf), dtypes=("f64", "f32"), fused=True)
+    gs = hrw.Gauge(dims, nc, rep, to_dev(uf), dtypes=("f64", "f32"))
+    pe = orc.split_eo(dims, fx.gaussian_spinor(dims, 6, seed=16, n_rhs=8))[0]
+    a = hrw.deo_apply(gf, 0.13, to_dev(pe[0]), THETA_AP, "f64").cpu().numpy()
+    b = hrw.deo_apply(gs, 0.13, to_dev(pe[0]), THETA_AP, "f64").cpu().numpy()
+    assert rel(a, b) < 1e-14
+    for dt in ("f64", "f32"):
+        many_f = hrw.deo_apply(gf, 0.13, to_dev(pe), THETA_AP, dt).cpu().numpy()
+        many_s = hrw.deo_apply(gs, 0.13, to_dev(pe), THETA_AP, dt).cpu().numpy()
+        assert np.array_equal(many_f, many_s), dt
+
+
+@pytest.mark.parametrize("nc,rep", [(2, "adj"), (4, "asym"), (3, "sym")])
+def test_fused_solves(nc, rep):
+    """CG (FP64 and FP32-inner mixed) and BiCGstab on a fused field: the true residual recomputed by
+    the oracle meets the tolerance and the solution matches the oracle's within cond x tol."""
+    dims, kappa = (4, 4, 4, 8), 0.13
+    uf, ur, g = fused_setup(dims, nc, rep, dtypes=("f64", "f32"), seed=17, kind="thermal")
+    b = orc.split_eo(dims, fx.gaussian_spinor(dims, g.nr, seed=18))[0]
+    xo, info = orc.cg(dims, ur, kappa, b, THETA_AP, orc.SYSTEM_EO, tol=1e-10)
+    lo, hi = orc.lanczos_extremes(info["alpha"], info["beta"])
+    for inner in ("f64", "f32"):
+        prm = hrw.solve_params(tol=1e-10, system="ddag_d_eo", inner_dtype=inner, theta=THETA_AP,
+                               reliable_delta=hrw.RELIABLE_DELTA[inner])
+        x, res, rc = hrw.cg_solve(g, to_dev(b), kappa, prm)
+        x = x.cpu().numpy()
+        assert rc == 0, res
+        ax = orc.deo(dims, ur, kappa, orc.deo(dims, ur, kappa, x, THETA_AP), THETA_AP, dagger=True)
+        assert rel(ax, b) <= 1.01e-10
+        assert rel(x, xo) <= 2 * (hi / lo) * 1e-10
+    prm = hrw.solve_params(tol=1e-10, system="dhat_eo", inner_dtype="f32", theta=THETA_AP,
+                           reliable_delta=hrw.RELIABLE_DELTA["f32"])
+    y, res, rc = hrw.bicgstab_solve(g, to_dev(b), kappa, prm)
+    assert rc == 0, res
+    assert rel(orc.deo(dims, ur, kappa, y.cpu().numpy(), THETA_AP), b) <= 1.01e-10
