@@ -268,8 +268,11 @@ def bicgstab_rows(torch, hrw, dev, dims, nc, rep, uf_d, b_d, kappa, theta, cg_va
     return rows
 
 
-def operator_table(torch, hrw, dev, dims, nc, rep, uf_d, kappa, theta, copy_gbs, reps=20):
+def operator_table(torch, hrw, dev, dims, nc, rep, uf_d, kappa, theta, copy_gbs, reps=20, fused=False):
     """Single applies of D_W (full lattice) and D_hat (even sites) in FP64 and FP32.
+
+    fused: the gauge field keeps its fundamental links and the hops build U_R in registers; the
+    byte models then count the N_F x N_F fundamental links (N_F^2 in place of N^2 in the link terms).
 
     Per call: the hopping kernels' time from HIP events on the launch stream
     (library timing) and the whole call (canonical-layout packing included).
@@ -283,8 +286,9 @@ def operator_table(torch, hrw, dev, dims, nc, rep, uf_d, kappa, theta, copy_gbs,
     v = int(np.prod(dims))
     gen = torch.Generator(device=dev)
     gen.manual_seed(11)
-    g = hrw.Gauge(dims, nc, rep, uf_d, dtypes=("f64", "f32"))
+    g = hrw.Gauge(dims, nc, rep, uf_d, dtypes=("f64", "f32"), fused=fused)
     n = g.nr
+    nl = nc if fused else n  # dimension of the streamed links
     psi = torch.complex(torch.randn((v, 4, n), generator=gen, device=dev, dtype=torch.float64),
                         torch.randn((v, 4, n), generator=gen, device=dev, dtype=torch.float64)) * np.sqrt(0.5)
     pe = psi[: v // 2].contiguous()
@@ -312,11 +316,11 @@ def operator_table(torch, hrw, dev, dims, nc, rep, uf_d, kappa, theta, copy_gbs,
             hrw.timing_enable(False)
             hop_us = hop["ms"] * 1e3 / reps
             if op == "dw":
-                b_min = cb * (4 * n * n + 8 * n) * v
-                b_str = cb * (8 * n * n + 12 * n) * v
+                b_min = cb * (4 * nl * nl + 8 * n) * v
+                b_str = cb * (8 * nl * nl + 12 * n) * v
                 flops = (128 * n * n + 72 * n) * v
             else:
-                b_min = b_str = cb * (16 * n * n + 20 * n) * (v // 2)
+                b_min = b_str = cb * (16 * nl * nl + 20 * n) * (v // 2)
                 flops = (2 * (128 * n * n + 56 * n) + 8 * n) * (v // 2)
             gbs = b_min / (hop_us * 1e-6) / 1e9
             rows[f"{op}_{dt}"] = {
@@ -325,7 +329,7 @@ def operator_table(torch, hrw, dev, dims, nc, rep, uf_d, kappa, theta, copy_gbs,
                 "frac_of_copy": round(gbs / copy_gbs, 3),
                 "GBs_as_streamed": round(b_str / (hop_us * 1e-6) / 1e9, 1),
                 "GFLOPs": round(flops / (hop_us * 1e-6) / 1e9, 1)}
-            log(f"{op} {dt}: {rows[f'{op}_{dt}']}")
+            log(f"{op} {dt}{' fused' if fused else ''}: {rows[f'{op}_{dt}']}")
     g.close()
     return rows
 
@@ -416,7 +420,8 @@ def workload_c1(args):
 
 
 def workload_c3(args):
-    """24^3x48 SU(2) adj and SU(4) asym, U_R built on the device: FP64 / FP32 / BF16 / FP16-storage CG."""
+    """24^3x48 SU(2) adj and SU(4) asym, U_R built on the device: FP64 / FP32 / BF16 / FP16-storage CG,
+    each with the stored U_R and with the representation map fused into the hop."""
     import torch
 
     import fixtures as fx
@@ -429,26 +434,38 @@ def workload_c3(args):
         uf = torch.from_numpy(fx.gauge_field(dims, nc, "thermal", seed=3, eps=0.3)).to(dev)
         log(f"c3 SU({nc}) links in {time.time() - t0:.1f}s")
         g = hrw.Gauge(dims, nc, rep, uf, dtypes=("f64", "f32", "bf16", "f16"))
+        # the same field with the representation map fused into the single-source hops
+        gf = hrw.Gauge(dims, nc, rep, uf, dtypes=("f64", "f32", "bf16", "f16"), fused=True)
         del uf
         b = torch.from_numpy(_even_part(dims, fx.gaussian_spinor(dims, g.nr, seed=4))).to(dev)
         ref = None
-        for inner in ["f64", "f32", "bf16", "f16"]:
+        stored_rate = {}
+        for fused, inner in [(False, d) for d in ("f64", "f32", "bf16", "f16")] + \
+                            [(True, d) for d in ("f64", "f32", "bf16", "f16")]:
+            gg = gf if fused else g
             prm = hrw.solve_params(tol=1e-10, max_iter=20000, system="ddag_d_eo", inner_dtype=inner,
                                    reliable_every=50, reliable_delta=hrw.RELIABLE_DELTA[inner], theta=theta)
             hrw.timing_enable(True)
-            x, res, per, lat = _solve_timed(hrw, torch, g, b, kappa, prm, args.steps, args.warmup)
-            r = _hop_roofline(hrw, f"hop_kernel<N_R={g.nr}, {inner}>")
+            x, res, per, lat = _solve_timed(hrw, torch, gg, b, kappa, prm, args.steps, args.warmup)
+            kname = "hop_fused_kernel" if fused else "hop_kernel"
+            r = _hop_roofline(hrw, f"{kname}<N_R={g.nr}, {inner}>")
             hrw.timing_enable(False)
-            if inner == "f64":
+            if inner == "f64" and not fused:
                 ref = x.clone()
             err = float((torch.linalg.vector_norm(x - ref) / torch.linalg.vector_norm(ref)).item())
-            case = {"rep": f"SU({nc}) {rep}", "n_r": g.nr, "inner": inner, "solves_per_s": round(1.0 / per, 3),
+            case = {"rep": f"SU({nc}) {rep}", "n_r": g.nr, "inner": inner, "fused_rep_map": fused,
+                    "solves_per_s": round(1.0 / per, 3),
                     "ms_per_solve": round(per * 1e3, 2), "iters": res[0]["iters"],
                     "reliable_updates": res[0]["reliable_updates"], "true_rel_resid": res[0]["true_rel_resid"],
                     "rel_error_vs_fp64": err, "hop_roofline": r}
+            if fused:
+                case["speedup_vs_stored_links"] = round(1.0 / per / stored_rate[inner], 3)
+                case["speedup_vs_stored_fp64"] = round(1.0 / per / stored_rate["f64"], 3)
+            else:
+                stored_rate[inner] = 1.0 / per
             cases.append(case)
             log(f"c3 {case}")
-            if nc == 4 and inner == "f32":
+            if nc == 4 and inner == "f32" and fused:
                 main, roof = case, r
         # D_W (full lattice) apply bandwidth in FP64 and FP32 on this representation
         psi = torch.from_numpy(fx.gaussian_spinor(dims, g.nr, seed=5)).to(dev)
@@ -466,11 +483,13 @@ def workload_c3(args):
             cases.append({"rep": f"SU({nc}) {rep}", "dw_apply_hop_" + dt: {
                 "us": round(c["ms"] / c["launches"] * 1e3, 1),
                 "GBs_dup_link_model": round(c["bytes"] / (c["ms"] * 1e-3) / 1e9, 1)}})
-        del g, b, psi, ws, out_
+        gf.close()
+        del g, gf, b, psi, ws, out_
         torch.cuda.empty_cache()
     return _line(main["solves_per_s"], "solves/s", args.steps, args.warmup, main["ms_per_solve"], "f32",
                  {"workload": "su4_asym_24^3x48_mixed_cg", "lattice": list(dims), "kappa": kappa,
                   "reps": ["SU(2) adj", "SU(4) asym"], "inner": ["f64", "f32", "bf16", "f16"],
+                  "value_case": "SU(4) asym, FP32 inner, representation map fused into the hop",
                   "reliable_every": 50, "reliable_delta": hrw.RELIABLE_DELTA, "tol": 1e-10}, roof, cases=cases)
 
 
@@ -485,6 +504,7 @@ def workload_c4(args):
     t0 = time.time()
     uf = torch.from_numpy(fx.gauge_field(dims, 3, "thermal", seed=6, eps=0.3)).to(dev)
     g = hrw.Gauge(dims, 3, "sym", uf, dtypes=("f64", "f32"))
+    g_fused = hrw.Gauge(dims, 3, "sym", uf, dtypes=("f64",), fused=True)
     del uf
     nmax = 24
     srcs = torch.empty((nmax, fx.volume(dims) // 2, 4, g.nr), dtype=torch.complex128, device=dev)
@@ -498,6 +518,12 @@ def workload_c4(args):
     fp64_rate = 1.0 / per64
     # the same FP64 CG batched over all sources (links shared): context only
     _, res64b, per64b, _ = _solve_timed(hrw, torch, g, srcs, kappa, prm64, 1, 0)
+    # FP64 CG, one source at a time, with the representation map fused into the hop (the faster
+    # FP64 single-source path; the ratios below are also given against it)
+    _, res64f, per64f, _ = _solve_timed(hrw, torch, g_fused, srcs[0:1].contiguous(), kappa, prm64,
+                                        max(1, args.steps // 2), 1)
+    g_fused.close()
+    fp64_fused_rate = 1.0 / per64f
     out = {}
     roof = None
     for n in (12, 24):
@@ -511,6 +537,7 @@ def workload_c4(args):
         err0 = float((torch.linalg.vector_norm(x[0] - x64[0]) / torch.linalg.vector_norm(x64[0])).item())
         out[n] = {"rhs_solves_per_s": round(n / per, 3), "ms_per_batch": round(per * 1e3, 1),
                   "speedup_vs_fp64_cg": round(n / per / fp64_rate, 2),
+                  "speedup_vs_fp64_cg_fused_rep_map": round(n / per / fp64_fused_rate, 2),
                   "max_iters": max(q["iters"] for q in res),
                   "max_true_rel_resid": max(q["true_rel_resid"] for q in res),
                   "rel_error_vs_fp64_source0": err0, "hop_roofline": r}
@@ -537,6 +564,7 @@ def workload_c4(args):
                          "inner": "f32", "reliable_every": 50, "reliable_delta": hrw.RELIABLE_DELTA["f32"],
                          "tol": 1e-10}, roof,
                  fp64_cg={"solves_per_s": round(fp64_rate, 3), "iters": res64[0]["iters"],
+                          "fused_rep_map_solves_per_s": round(fp64_fused_rate, 3),
                           "batched_24_rhs_solves_per_s": round(nmax / per64b, 3),
                           "batched_max_iters": max(q["iters"] for q in res64b)},
                  multi_source=out, multi_source_24_f16_storage=f16_row, bicgstab_propagators=bicg,
@@ -635,15 +663,21 @@ def workload_ops(args):
     dev = torch.device("cuda:0")
     theta, kappa = (np.pi, 0.0, 0.0, 0.0), 0.135
     copy = copy_reference(torch, dev)
-    table, worst = {}, None
+    table, fused_table, worst = {}, {}, None
     for nc, rep, dims in [(3, "fund", (32, 32, 32, 32)), (2, "adj", (48, 24, 24, 24)),
                           (4, "asym", (48, 24, 24, 24)), (3, "sym", (32, 32, 32, 32))]:
         uf = torch.from_numpy(fx.gauge_field(dims, nc, "thermal", seed=2, eps=0.3)).to(dev)
         rows = operator_table(torch, hrw, dev, dims, nc, rep, uf, kappa, theta, copy["gbs"])
-        del uf
-        torch.cuda.empty_cache()
         key = f"SU({nc}) {rep} {'x'.join(str(d) for d in dims[::-1])}"
         table[key] = rows
+        if rep != "fund":
+            # the same applies with the representation map fused into the hop
+            fr = operator_table(torch, hrw, dev, dims, nc, rep, uf, kappa, theta, copy["gbs"], fused=True)
+            for name, r in fr.items():
+                r["speedup_vs_stored_links"] = round(rows[name]["hop_us"] / r["hop_us"], 3)
+            fused_table[key] = fr
+        del uf
+        torch.cuda.empty_cache()
         for name in ("deo_f64", "deo_f32"):
             if worst is None or rows[name]["frac_of_peak"] < worst[1]:
                 worst = (f"{key} {name}", rows[name]["frac_of_peak"])
@@ -655,7 +689,7 @@ def workload_ops(args):
             "frac": best[2]["frac_of_peak"], "traffic": None}
     return _line(round(sum(fracs) / len(fracs), 4), "mean fraction of 8 TB/s (D_hat, FP64 and FP32, 4 reps)", 20, 3,
                  None, "f64+f32", {"workload": "operator_sweep_4_reps", "kappa": kappa, "theta": "(pi,0,0,0)"}, roof,
-                 operators=table, lowest=worst, hbm_copy_reference=copy)
+                 operators=table, operators_fused_rep_map=fused_table, lowest=worst, hbm_copy_reference=copy)
 
 
 def copy_reference(torch, dev, nbytes=1 << 30, reps=10):

@@ -96,9 +96,10 @@ enum hrw_dtype { HRW_F64 = 0, HRW_F32 = 1, HRW_BF16 = 2, HRW_F16 = 3 };
  * shrinks by N^2 / N_R^2 for extra arithmetic).  Built for SU(2) adjoint and
  * symmetric, SU(3) symmetric and SU(4) antisymmetric; HRW_EUNSUPPORTED for
  * the others.  Results agree with the stored-U_R path to rounding (U_R is
- * evaluated in the arithmetic precision of the hop).  Multi-source launches
- * keep using the stored U_R.  Sec. 3.1.2 (the represented link is built from
- * the fundamental one). */
+ * evaluated in the arithmetic precision of the hop).  Multi-source launches,
+ * and 16-bit-storage hops with N_R = 6 (where the extra arithmetic outweighs
+ * the saved bytes), keep using the stored U_R.  Sec. 3.1.2 (the represented
+ * link is built from the fundamental one). */
 #define HRW_STORE_FUND_HOP (1u << 4)
 
 /* Linear systems: 0-2 for hrw_cg_solve (Hermitian positive definite normal

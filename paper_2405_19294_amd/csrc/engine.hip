@@ -134,7 +134,8 @@ int run_hop(const hrw_gauge *g, const Phases &ph, const HopCall &c, hipStream_t 
     if (!g->blocks[c.dt][0]) return fail(HRW_EUNSUPPORTED, "gauge field has no links stored in dtype %d", c.dt);
     // single-source launches of a field that keeps its fundamental links build U_R in the hop;
     // the multi-source kernel keeps its LDS copy of the stored U_R
-    const int fused_nc = (g->fblocks[c.dt][0] && !hop_uses_mrhs(g->nr, c.dt, c.n_rhs)) ? g->nc : 0;
+    const int fused_nc =
+        (g->fblocks[c.dt][0] && hop_fused_pays(g->nr, c.dt) && !hop_uses_mrhs(g->nr, c.dt, c.n_rhs)) ? g->nc : 0;
     hipEvent_t ev;
     const bool tm = timed_begin(st, &ev);
     hipError_t err = hipErrorInvalidValue;

@@ -97,6 +97,16 @@ constexpr bool hop_fused_supported(int nc, int rep)
 template <class S>
 hipError_t launch_hop_fused(int nc, int rep, bool dagger, int epi, const HopArgs<S> &a, hipStream_t st);
 
+// Whether a single-source hop of a field that keeps its fundamental links
+// builds U_R in registers.  Building a row costs about as much arithmetic as
+// applying it, so the fused hop does roughly twice the arithmetic of the
+// stored-U_R hop.  Measured on MI355X (D_hat, SU(2) adj and SU(4) asym 24^3x48,
+// SU(3) sym 32^4): 1.2-1.8x faster in FP64 and 1.3-1.9x in FP32 storage;
+// with 16-bit storage the links are already small against the arithmetic and
+// only N_R <= 4 still gains (N_R = 6 in FP16: 7% slower), so 16-bit N_R = 6
+// hops read the stored U_R.
+constexpr bool hop_fused_pays(int nr, int dt) { return dt <= 1 || nr <= 4; }
+
 // Colour rows each thread of the hopping kernel owns (threads per site =
 // N_R / rows): the colour-parallel split keeps the registers of the larger
 // representations below the spill point (zero scratch for every instance,

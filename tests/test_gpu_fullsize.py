@@ -6,8 +6,9 @@ recomputes (the residual of a solve):
   * SU(3) fund 32^4 (default workload): D_hat and D_hat^+ in FP64 to 1e-13, the full-lattice D_W in
     FP32 within the a-priori bound, and the |b - D x| / |b| of the FP64 CG solve and of the BiCGstab
     solves (FP64 and FP32 inner) recomputed by the oracle;
-  * SU(2) adj and SU(4) asym 24^3x48: D_hat in FP64, and the FP32-inner mixed solve's residual of the
-    even/odd normal equations recomputed by the oracle;
+  * SU(2) adj and SU(4) asym 24^3x48, with stored U_R and with the representation map fused into the
+    hop: D_hat in FP64, and the FP32-inner mixed solve's residual of the even/odd normal equations
+    recomputed by the oracle;
   * SU(3) sym 32^4 with 24 sources: the multi-source FP32 kernel (the launch the multi-source CG uses)
     bitwise equal to single-source applies, and the batched FP64 D_hat against the oracle.
 """
@@ -80,11 +81,12 @@ def test_c2_bicgstab_residual_by_oracle(c2_field, inner):
     assert d_res < 1e-9
 
 
+@pytest.mark.parametrize("fused", [False, True], ids=["stored_links", "fused_rep_map"])
 @pytest.mark.parametrize("nc,rep", [(2, "adj"), (4, "asym")])
-def test_c3_operator_and_mixed_solve_full_size(nc, rep):
+def test_c3_operator_and_mixed_solve_full_size(nc, rep, fused):
     uf = fx.gauge_field(C3, nc, "thermal", seed=3, eps=0.3)
     ur = orc.rep_map(nc, rep, uf)
-    g = hrw.Gauge(C3, nc, rep, to_dev(uf), dtypes=("f64", "f32"))
+    g = hrw.Gauge(C3, nc, rep, to_dev(uf), dtypes=("f64", "f32"), fused=fused)
     del uf
     try:
         eta = _even(C3, fx.gaussian_spinor(C3, g.nr, seed=4))
