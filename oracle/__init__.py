@@ -65,6 +65,11 @@ def _load():
             "orc_deo": (I, [P, I, P, D, P, I, P, P]),
             "orc_cg": (I, [P, I, P, D, P, I, P, P, D, I, P, P, P]),
             "orc_bicgstab": (I, [P, I, P, D, P, I, P, P, D, I, P]),
+            "orc_bicgstab_sw": (I, [P, I, P, D, D, P, I, P, P, D, I, P]),
+            "orc_clover": (I, [P, I, P, D, D, P]),
+            "orc_clover_apply": (I, [P, I, P, D, D, I, I, P, P]),
+            "orc_dsw": (I, [P, I, P, D, D, P, I, P, P]),
+            "orc_dsw_eo": (I, [P, I, P, D, D, P, I, P, P]),
             "orc_round": (I, [I, L, P]),
             "orc_parity_count": (I, [P, I]),
             "orc_num_threads": (I, []),
@@ -306,6 +311,70 @@ def solve_d_eo_bicgstab(dims, u_r, kappa, b, theta=None, tol=1e-10, max_iter=100
     bpe = be + kappa * hop_eo(dims, u_r, bo, 0, theta)
     xe, info = bicgstab(dims, u_r, kappa, bpe, theta, BICG_EO, tol, max_iter)
     xo = bo + kappa * hop_eo(dims, u_r, xe, 1, theta)
+    return merge_eo(dims, xe, xo), info
+
+
+# ---------------------------------------------------------------- clover (Sheikholeslami-Wohlert)
+
+def clover(dims, u_r, kappa, csw) -> np.ndarray:
+    """A(x) = 1 - kappa c_sw sum_{mu<nu} g_mu g_nu (x) F_mu,nu(x), F the clover average of the
+    represented plaquette leaves (Sec. 3.1 clover improvement); shape [V][4 nr][4 nr], index
+    spin * nr + colour."""
+    u = _c128(u_r)
+    nr = _nr_of(u)
+    v = int(np.prod(np.asarray(_dims(dims), dtype=np.int64)))
+    out = np.zeros((v, 4 * nr, 4 * nr), dtype=np.complex128)
+    _check(_load().orc_clover(_ptr(_dims(dims)), nr, _ptr(u), float(kappa), float(csw), _ptr(out)), "clover")
+    return out
+
+
+def clover_apply(dims, u_r, kappa, csw, parity, in_half, inverse=False) -> np.ndarray:
+    """A or A^-1 applied on the sites of one parity."""
+    u, a = _c128(u_r), _c128(in_half)
+    out = np.zeros_like(a)
+    _check(_load().orc_clover_apply(_ptr(_dims(dims)), _nr_of(u), _ptr(u), float(kappa), float(csw), int(parity),
+                                    int(bool(inverse)), _ptr(a), _ptr(out)), "clover_apply")
+    return out
+
+
+def dsw(dims, u_r, kappa, csw, psi, theta=None, dagger=False) -> np.ndarray:
+    """D_sw psi = A psi - kappa H psi (H^+ with dagger)."""
+    u, a = _c128(u_r), _c128(psi)
+    out = np.zeros_like(a)
+    _check(_load().orc_dsw(_ptr(_dims(dims)), _nr_of(u), _ptr(u), float(kappa), float(csw), _ptr(_theta(theta)),
+                           int(bool(dagger)), _ptr(a), _ptr(out)), "dsw")
+    return out
+
+
+def dsw_eo(dims, u_r, kappa, csw, in_e, theta=None, dagger=False) -> np.ndarray:
+    """D_hat_sw = A_ee - kappa^2 H_eo A_oo^-1 H_oe on even sites (the Schur complement of D_sw)."""
+    u, a = _c128(u_r), _c128(in_e)
+    out = np.zeros_like(a)
+    _check(_load().orc_dsw_eo(_ptr(_dims(dims)), _nr_of(u), _ptr(u), float(kappa), float(csw),
+                              _ptr(_theta(theta)), int(bool(dagger)), _ptr(a), _ptr(out)), "dsw_eo")
+    return out
+
+
+def bicgstab_sw(dims, u_r, kappa, csw, b, theta=None, system=BICG_EO, tol=1e-10, max_iter=10000):
+    """BiCGstab for D_sw x = b (BICG_FULL) or D_hat_sw x_e = b_e (BICG_EO) from x = 0."""
+    u, bb = _c128(u_r), _c128(b)
+    x = np.zeros_like(bb)
+    info = np.zeros(3)
+    rc = _load().orc_bicgstab_sw(_ptr(_dims(dims)), _nr_of(u), _ptr(u), float(kappa), float(csw),
+                                 _ptr(_theta(theta)), int(system), _ptr(bb), _ptr(x), float(tol), int(max_iter),
+                                 _ptr(info))
+    _check(rc if rc != -5 else 0, "bicgstab_sw")
+    return x, {"status": int(rc), "iters": int(info[0]), "true_rel_resid": float(info[1]),
+               "restarts": int(info[2])}
+
+
+def solve_dsw_eo_bicgstab(dims, u_r, kappa, csw, b, theta=None, tol=1e-10, max_iter=10000):
+    """D_sw x = b through the Schur complement: b'_e = b_e + kappa H_eo A_oo^-1 b_o,
+    D_hat_sw x_e = b'_e, x_o = A_oo^-1 (b_o + kappa H_oe x_e)."""
+    be, bo = split_eo(dims, b)
+    bpe = be + kappa * hop_eo(dims, u_r, clover_apply(dims, u_r, kappa, csw, 1, bo, inverse=True), 0, theta)
+    xe, info = bicgstab_sw(dims, u_r, kappa, csw, bpe, theta, BICG_EO, tol, max_iter)
+    xo = clover_apply(dims, u_r, kappa, csw, 1, bo + kappa * hop_eo(dims, u_r, xe, 1, theta), inverse=True)
     return merge_eo(dims, xe, xo), info
 
 

@@ -463,6 +463,257 @@ int orc_deo(const int *dims, int nr, const double *u, double kappa, const double
 
 int orc_parity_count(const int *dims, int parity) { return (int)half_count(dims, parity & 1); }
 
+/* ------------------------------------------------------------------ clover */
+
+/*
+ * Sheikholeslami-Wohlert (clover) term, one of the operator improvements of
+ * Sec. 3.1.  In the kappa normalisation of D = 1 - kappa H the improved
+ * operator is D_sw = A - kappa H with the site-local
+ *   A(x) = 1 - kappa c_sw sum_{mu<nu} (g_mu g_nu) (x) F_mu,nu(x),
+ * which is (1/(4+m0)) times 1 + c_sw (i/4) sigma_mu,nu F_mu,nu summed over all
+ * mu, nu with sigma_mu,nu = (i/2)[g_mu, g_nu].  F is the clover average in the
+ * representation R: F = (Q - Q^+)/8, Q the sum of the four plaquette leaves in
+ * the mu-nu plane that start and end at x, built from the represented links.
+ * The boundary phases of the fermion field do not enter F.
+ */
+
+/* U_mu at x (periodic) */
+static const cplx *link_at(const int d[4], int nr, const cplx *u, const int x[4], int mu)
+{
+    int y[4];
+    for (int m = 0; m < 4; ++m) y[m] = ((x[m] % d[m]) + d[m]) % d[m];
+    return u + (index_of(d, y) * 4 + mu) * (long)nr * nr;
+}
+
+/* out = M0' M1' M2' M3', Mk' = Mk or Mk^+ */
+static void path4(int n, const cplx *const m[4], const int dag[4], cplx *out)
+{
+    cplx *t = (cplx *)malloc(sizeof(cplx) * n * n), *a = (cplx *)malloc(sizeof(cplx) * n * n),
+         *b = (cplx *)malloc(sizeof(cplx) * n * n);
+    for (int i = 0; i < n * n; ++i) a[i] = 0;
+    for (int i = 0; i < n; ++i) a[i * n + i] = 1;
+    for (int k = 0; k < 4; ++k) {
+        if (dag[k]) dagger(n, m[k], t);
+        else memcpy(t, m[k], sizeof(cplx) * n * n);
+        mm(n, a, t, b);
+        memcpy(a, b, sizeof(cplx) * n * n);
+    }
+    memcpy(out, a, sizeof(cplx) * n * n);
+    free(t);
+    free(a);
+    free(b);
+}
+
+/* F_mu,nu(x) (nr x nr) from the four leaves */
+static void clover_f(const int d[4], int nr, const cplx *u, const int x[4], int mu, int nu, cplx *f)
+{
+    const long n2 = (long)nr * nr;
+    cplx *q = (cplx *)calloc(n2, sizeof(cplx)), *leaf = (cplx *)malloc(sizeof(cplx) * n2);
+    int xm[4], xn[4], xmn[4], xpm_mn[4], xmm_pn[4];
+    for (int k = 0; k < 4; ++k) xm[k] = xn[k] = xmn[k] = xpm_mn[k] = xmm_pn[k] = x[k];
+    /* shifted sites: x+mu, x+nu, x-mu, x-nu, x-mu-nu, x+mu-nu, x-mu+nu */
+    int xpm[4], xpn[4];
+    for (int k = 0; k < 4; ++k) xpm[k] = xpn[k] = x[k];
+    xpm[mu] += 1;
+    xpn[nu] += 1;
+    xm[mu] -= 1;
+    xn[nu] -= 1;
+    xmn[mu] -= 1;
+    xmn[nu] -= 1;
+    xpm_mn[mu] += 1;
+    xpm_mn[nu] -= 1;
+    xmm_pn[mu] -= 1;
+    xmm_pn[nu] += 1;
+    {   /* U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+ */
+        const cplx *m[4] = {link_at(d, nr, u, x, mu), link_at(d, nr, u, xpm, nu), link_at(d, nr, u, xpn, mu),
+                            link_at(d, nr, u, x, nu)};
+        const int dg[4] = {0, 0, 1, 1};
+        path4(nr, m, dg, leaf);
+        for (long i = 0; i < n2; ++i) q[i] += leaf[i];
+    }
+    {   /* U_nu(x) U_mu(x-mu+nu)^+ U_nu(x-mu)^+ U_mu(x-mu) */
+        const cplx *m[4] = {link_at(d, nr, u, x, nu), link_at(d, nr, u, xmm_pn, mu), link_at(d, nr, u, xm, nu),
+                            link_at(d, nr, u, xm, mu)};
+        const int dg[4] = {0, 1, 1, 0};
+        path4(nr, m, dg, leaf);
+        for (long i = 0; i < n2; ++i) q[i] += leaf[i];
+    }
+    {   /* U_mu(x-mu)^+ U_nu(x-mu-nu)^+ U_mu(x-mu-nu) U_nu(x-nu) */
+        const cplx *m[4] = {link_at(d, nr, u, xm, mu), link_at(d, nr, u, xmn, nu), link_at(d, nr, u, xmn, mu),
+                            link_at(d, nr, u, xn, nu)};
+        const int dg[4] = {1, 1, 0, 0};
+        path4(nr, m, dg, leaf);
+        for (long i = 0; i < n2; ++i) q[i] += leaf[i];
+    }
+    {   /* U_nu(x-nu)^+ U_mu(x-nu) U_nu(x+mu-nu) U_mu(x)^+ */
+        const cplx *m[4] = {link_at(d, nr, u, xn, nu), link_at(d, nr, u, xn, mu), link_at(d, nr, u, xpm_mn, nu),
+                            link_at(d, nr, u, x, mu)};
+        const int dg[4] = {1, 0, 0, 1};
+        path4(nr, m, dg, leaf);
+        for (long i = 0; i < n2; ++i) q[i] += leaf[i];
+    }
+    for (int a = 0; a < nr; ++a)
+        for (int b = 0; b < nr; ++b) f[a * nr + b] = (q[a * nr + b] - conj(q[b * nr + a])) / 8.0;
+    free(q);
+    free(leaf);
+}
+
+/* A(x) as a (4 nr) x (4 nr) matrix, index spin * nr + colour, for every site: a_out [V][4nr][4nr] */
+int orc_clover(const int *dims, int nr, const double *u, double kappa, double csw, double *a_out)
+{
+    if (!check_dims(dims, nr) || !u || !a_out) return ORC_EINVAL;
+    init_gamma();
+    const long v = vol(dims);
+    const int sp = 4 * nr;
+    const long n2 = (long)nr * nr;
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < v; ++s) {
+        int x[4];
+        coords(dims, s, x);
+        cplx *a = (cplx *)a_out + s * sp * sp;
+        for (int i = 0; i < sp * sp; ++i) a[i] = 0;
+        for (int i = 0; i < sp; ++i) a[i * sp + i] = 1;
+        cplx *f = (cplx *)malloc(sizeof(cplx) * n2);
+        for (int mu = 0; mu < 4; ++mu)
+            for (int nu = mu + 1; nu < 4; ++nu) {
+                clover_f(dims, nr, (const cplx *)u, x, mu, nu, f);
+                cplx gg[4][4];
+                for (int i = 0; i < 4; ++i)
+                    for (int j = 0; j < 4; ++j) {
+                        cplx z = 0;
+                        for (int k = 0; k < 4; ++k) z += G[mu][i][k] * G[nu][k][j];
+                        gg[i][j] = z;
+                    }
+                for (int al = 0; al < 4; ++al)
+                    for (int be = 0; be < 4; ++be) {
+                        if (gg[al][be] == 0) continue;
+                        for (int p = 0; p < nr; ++p)
+                            for (int q = 0; q < nr; ++q)
+                                a[(al * nr + p) * sp + be * nr + q] -= kappa * csw * gg[al][be] * f[p * nr + q];
+                    }
+            }
+        free(f);
+    }
+    return ORC_OK;
+}
+
+/* Solve m x = b (n unknowns) by Gaussian elimination with partial pivoting; m, b overwritten. */
+static int dense_solve(int n, cplx *m, cplx *b)
+{
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (cabs(m[r * n + c]) > cabs(m[piv * n + c])) piv = r;
+        if (m[piv * n + c] == 0) return ORC_BREAKDOWN;
+        if (piv != c) {
+            for (int k = 0; k < n; ++k) {
+                cplx t = m[c * n + k];
+                m[c * n + k] = m[piv * n + k];
+                m[piv * n + k] = t;
+            }
+            cplx t = b[c];
+            b[c] = b[piv];
+            b[piv] = t;
+        }
+        for (int r = c + 1; r < n; ++r) {
+            const cplx l = m[r * n + c] / m[c * n + c];
+            for (int k = c; k < n; ++k) m[r * n + k] -= l * m[c * n + k];
+            b[r] -= l * b[c];
+        }
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        cplx z = b[r];
+        for (int k = r + 1; k < n; ++k) z -= m[r * n + k] * b[k];
+        b[r] = z / m[r * n + r];
+    }
+    return ORC_OK;
+}
+
+/* A (inverse = 0) or A^-1 (inverse = 1) on the sites of one parity (half fields). */
+int orc_clover_apply(const int *dims, int nr, const double *u, double kappa, double csw, int parity,
+                     int inverse, const double *in_half, double *out_half)
+{
+    if (!check_dims(dims, nr) || !even_dims(dims) || (parity & ~1) || !u || !in_half || !out_half)
+        return ORC_EINVAL;
+    const long v = vol(dims);
+    const int sp = 4 * nr;
+    cplx *a = (cplx *)malloc(sizeof(cplx) * (size_t)v * sp * sp);
+    int rc = orc_clover(dims, nr, u, kappa, csw, (double *)a);
+    long k = 0;
+    cplx *m = (cplx *)malloc(sizeof(cplx) * sp * sp);
+    for (long s = 0; s < v && rc == ORC_OK; ++s) {
+        int x[4];
+        coords(dims, s, x);
+        if (parity_of(x) != parity) continue;
+        const cplx *in = (const cplx *)in_half + k * sp;
+        cplx *out = (cplx *)out_half + k * sp;
+        const cplx *as = a + s * sp * sp;
+        if (inverse) {
+            memcpy(m, as, sizeof(cplx) * sp * sp);
+            memcpy(out, in, sizeof(cplx) * sp);
+            rc = dense_solve(sp, m, out);
+        } else {
+            for (int i = 0; i < sp; ++i) {
+                cplx z = 0;
+                for (int j = 0; j < sp; ++j) z += as[i * sp + j] * in[j];
+                out[i] = z;
+            }
+        }
+        ++k;
+    }
+    free(m);
+    free(a);
+    return rc;
+}
+
+/* D_sw psi = A psi - kappa H psi (dagger: A psi - kappa H^+ psi; A is Hermitian). */
+int orc_dsw(const int *dims, int nr, const double *u, double kappa, double csw, const double *theta,
+            int dagger_, const double *in, double *out)
+{
+    if (!check_dims(dims, nr) || !u || !in || !out || in == out) return ORC_EINVAL;
+    const long v = vol(dims);
+    const int sp = 4 * nr;
+    cplx *a = (cplx *)malloc(sizeof(cplx) * (size_t)v * sp * sp);
+    int rc = orc_clover(dims, nr, u, kappa, csw, (double *)a);
+    if (!rc) rc = orc_hop(dims, nr, u, theta, dagger_, in, out);
+    if (!rc) {
+        const cplx *pin = (const cplx *)in;
+        cplx *po = (cplx *)out;
+        for (long s = 0; s < v; ++s)
+            for (int i = 0; i < sp; ++i) {
+                cplx z = 0;
+                for (int j = 0; j < sp; ++j) z += a[s * sp * sp + i * sp + j] * pin[s * sp + j];
+                po[s * sp + i] = z - kappa * po[s * sp + i];
+            }
+    }
+    free(a);
+    return rc;
+}
+
+/* D_hat_sw psi_e = A_ee psi_e - kappa^2 H_eo A_oo^-1 H_oe psi_e (dagger: with H^+ blocks),
+ * the Schur complement of D_sw on the even sites. */
+int orc_dsw_eo(const int *dims, int nr, const double *u, double kappa, double csw, const double *theta,
+               int dagger_, const double *in_e, double *out_e)
+{
+    if (!check_dims(dims, nr) || !even_dims(dims) || !in_e || !out_e || in_e == out_e) return ORC_EINVAL;
+    const long h = vol(dims) / 2;
+    const size_t bytes = sizeof(cplx) * (size_t)h * 4 * nr;
+    cplx *t = (cplx *)malloc(bytes), *w = (cplx *)malloc(bytes), *ae = (cplx *)malloc(bytes);
+    int rc = orc_hop_eo(dims, nr, u, theta, dagger_, 1, in_e, (double *)t);
+    if (!rc) rc = orc_clover_apply(dims, nr, u, kappa, csw, 1, 1, (const double *)t, (double *)w);
+    if (!rc) rc = orc_hop_eo(dims, nr, u, theta, dagger_, 0, (const double *)w, out_e);
+    if (!rc) rc = orc_clover_apply(dims, nr, u, kappa, csw, 0, 0, in_e, (double *)ae);
+    if (!rc) {
+        const long n = h * 4 * nr;
+        cplx *b = (cplx *)out_e;
+        for (long i = 0; i < n; ++i) b[i] = ae[i] - kappa * kappa * b[i];
+    }
+    free(t);
+    free(w);
+    free(ae);
+    return rc;
+}
+
 /* ------------------------------------------------------------------ CG */
 
 typedef struct {
@@ -471,8 +722,10 @@ typedef struct {
     const double *u;
     double kappa;
     const double *theta;
-    int system; /* 0: D^+D full lattice, 1: D_hat^+ D_hat on even sites */
+    int system; /* CG: 0 D^+D full lattice, 1 D_hat^+ D_hat on even sites;
+                   BiCGstab: 0 D, 1 D_hat, 2 D_sw, 3 D_hat_sw */
     cplx *tmp;
+    double csw;
 } op_ctx;
 
 static void apply_normal(op_ctx *c, const cplx *in, cplx *out)
@@ -519,7 +772,7 @@ int orc_cg(const int *dims, int nr, const double *u, double kappa, const double 
     const long sites = system == 0 ? vol(dims) : vol(dims) / 2;
     const long n = sites * 4 * nr;
     const size_t bytes = sizeof(cplx) * (size_t)n;
-    op_ctx c = {dims, nr, u, kappa, theta, system, (cplx *)malloc(bytes)};
+    op_ctx c = {dims, nr, u, kappa, theta, system, (cplx *)malloc(bytes), 0.0};
     cplx *x = (cplx *)x_out, *r = (cplx *)malloc(bytes), *p = (cplx *)malloc(bytes),
          *q = (cplx *)malloc(bytes);
     const cplx *b = (const cplx *)eta;
@@ -588,8 +841,12 @@ static void apply_op(op_ctx *c, const cplx *in, cplx *out)
 {
     if (c->system == 0)
         orc_dw(c->dims, c->nr, c->u, c->kappa, c->theta, 0, (const double *)in, (double *)out);
-    else
+    else if (c->system == 1)
         orc_deo(c->dims, c->nr, c->u, c->kappa, c->theta, 0, (const double *)in, (double *)out);
+    else if (c->system == 2)
+        orc_dsw(c->dims, c->nr, c->u, c->kappa, c->csw, c->theta, 0, (const double *)in, (double *)out);
+    else
+        orc_dsw_eo(c->dims, c->nr, c->u, c->kappa, c->csw, c->theta, 0, (const double *)in, (double *)out);
 }
 
 /* <a, b> = sum_i conj(a_i) b_i */
@@ -619,6 +876,8 @@ static int cfinite(cplx z) { return isfinite(creal(z)) && isfinite(cimag(z)); }
  * residual, which also becomes the new shadow vector.  info[0] = iterations,
  * info[1] = true relative residual, info[2] = restarts.
  */
+static int bicgstab_run(op_ctx c, const double *b_in, double *x_out, double tol, int max_iter, double *info);
+
 int orc_bicgstab(const int *dims, int nr, const double *u, double kappa, const double *theta,
                  int system, const double *b_in, double *x_out, double tol, int max_iter,
                  double *info)
@@ -626,10 +885,28 @@ int orc_bicgstab(const int *dims, int nr, const double *u, double kappa, const d
     if (!check_dims(dims, nr) || (system != 0 && system != 1) || !b_in || !x_out)
         return ORC_EINVAL;
     if (system == 1 && !even_dims(dims)) return ORC_EINVAL;
-    const long sites = system == 0 ? vol(dims) : vol(dims) / 2;
+    op_ctx c = {dims, nr, u, kappa, theta, system, NULL, 0.0};
+    return bicgstab_run(c, b_in, x_out, tol, max_iter, info);
+}
+
+/* The same method for the clover-improved D_sw (system 0) or its Schur complement D_hat_sw (1). */
+int orc_bicgstab_sw(const int *dims, int nr, const double *u, double kappa, double csw, const double *theta,
+                    int system, const double *b_in, double *x_out, double tol, int max_iter, double *info)
+{
+    if (!check_dims(dims, nr) || (system != 0 && system != 1) || !b_in || !x_out)
+        return ORC_EINVAL;
+    if (system == 1 && !even_dims(dims)) return ORC_EINVAL;
+    op_ctx c = {dims, nr, u, kappa, theta, system + 2, NULL, csw};
+    return bicgstab_run(c, b_in, x_out, tol, max_iter, info);
+}
+
+static int bicgstab_run(op_ctx c, const double *b_in, double *x_out, double tol, int max_iter, double *info)
+{
+    const int *dims = c.dims;
+    const int nr = c.nr;
+    const long sites = (c.system == 0 || c.system == 2) ? vol(dims) : vol(dims) / 2;
     const long n = sites * 4 * nr;
     const size_t bytes = sizeof(cplx) * (size_t)n;
-    op_ctx c = {dims, nr, u, kappa, theta, system, NULL};
     cplx *x = (cplx *)x_out;
     cplx *r = (cplx *)malloc(bytes), *r0 = (cplx *)malloc(bytes), *p = (cplx *)malloc(bytes),
          *v = (cplx *)malloc(bytes), *s = (cplx *)malloc(bytes), *t = (cplx *)malloc(bytes);

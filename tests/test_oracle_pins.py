@@ -459,6 +459,108 @@ def test_bicgstab_and_cg_solve_the_same_system():
     assert 2 * ib["iters"] < 2 * ic["iters"]
 
 
+# ----------------------------------------------------------------- clover (Sheikholeslami-Wohlert)
+
+def _gauge_transformed(dims, nc, uf, gt):
+    x = coords(dims)
+    ugf = np.empty_like(uf)
+    for mu in range(4):
+        y = x.copy()
+        y[mu] = (y[mu] + 1) % dims[mu]
+        fwd = np.ravel_multi_index(tuple(y), dims)
+        ugf[:, mu] = gt @ uf[:, mu] @ np.conj(np.swapaxes(gt[fwd], 1, 2))
+    return ugf
+
+
+@pytest.mark.parametrize("nc,rep", [(2, "fund"), (3, "fund"), (2, "adj"), (3, "sym"), (4, "asym")])
+def test_clover_hermitian_chiral_and_covariant(nc, rep):
+    """A is Hermitian, block-diagonal in the chiral basis (commutes with g5), equals 1 on the free
+    field and for c_sw = 0, and transforms as A -> (1 x Omega_R) A (1 x Omega_R)^+; D_sw is
+    g5-Hermitian and gauge covariant."""
+    dims = (4, 2, 4, 2)
+    uf = fx.gauge_field(dims, nc, "haar", seed=31)
+    ur = orc.rep_map(nc, rep, uf)
+    nr = ur.shape[-1]
+    kappa, csw = 0.13, 1.3
+    a = orc.clover(dims, ur, kappa, csw)
+    assert np.abs(a - np.conj(np.swapaxes(a, 1, 2))).max() < 1e-15
+    assert np.abs(a[:, :2 * nr, 2 * nr:]).max() == 0 and np.abs(a[:, 2 * nr:, :2 * nr]).max() == 0
+    assert np.abs(a - np.eye(4 * nr)).max() > 1e-2
+    assert np.array_equal(orc.clover(dims, orc.rep_map(nc, rep, fx.unit_gauge(dims, nc)), kappa, csw),
+                          np.broadcast_to(np.eye(4 * nr), a.shape))
+    assert np.array_equal(orc.clover(dims, ur, kappa, 0.0), np.broadcast_to(np.eye(4 * nr), a.shape))
+    psi = fx.gaussian_spinor(dims, nr, seed=32)
+    chi = fx.gaussian_spinor(dims, nr, seed=33)
+    assert rel(orc.dsw(dims, ur, kappa, 0.0, psi, THETA_TW), orc.dw(dims, ur, kappa, psi, THETA_TW)) < 1e-15
+    g5 = orc.gamma5
+    lhs = inner(chi, orc.dsw(dims, ur, kappa, csw, psi, THETA_TW))
+    rhs = inner(g5(orc.dsw(dims, ur, kappa, csw, g5(chi), THETA_TW)), psi)
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+    gt = fx.random_gauge_transform(dims, nc, seed=34)
+    urg = orc.rep_map(nc, rep, _gauge_transformed(dims, nc, uf, gt))
+    rg = orc.rep_map(nc, rep, gt)
+    big = np.einsum("ij,sab->siajb", np.eye(4), rg).reshape(-1, 4 * nr, 4 * nr)
+    ag = orc.clover(dims, urg, kappa, csw)
+    assert np.abs(ag - big @ a @ np.conj(np.swapaxes(big, 1, 2))).max() < 1e-13
+    rot = lambda f: np.einsum("sab,sib->sia", rg, f)
+    assert rel(orc.dsw(dims, urg, kappa, csw, rot(psi), THETA_TW), rot(orc.dsw(dims, ur, kappa, csw, psi, THETA_TW))) < 1e-13
+
+
+@pytest.mark.parametrize("n", [1, 3])
+def test_clover_constant_abelian_field(n):
+    """U_1(x) = exp(i b x_0 sigma_3) (b = 2 pi n / N_0, the others 1): every leaf of the 0-1 plane is
+    exp(i b sigma_3), so F_01 = i sin(b) sigma_3 everywhere, the other planes vanish, and
+    A = 1 - kappa c_sw (g_0 g_1) (x) (i sin b sigma_3).  Pins the leaf paths, their orientation,
+    the 1/8 normalisation, the order g_mu g_nu and the sign of the term."""
+    dims = (6, 4, 2, 2)
+    v = fx.volume(dims)
+    x = coords(dims)
+    b = 2 * np.pi * n / dims[0]
+    u = fx.unit_gauge(dims, 2)
+    ph = np.exp(1j * b * x[0])
+    u[:, 1, 0, 0] = ph
+    u[:, 1, 1, 1] = np.conj(ph)
+    kappa, csw = 0.12, 1.7
+    a = orc.clover(dims, u, kappa, csw)
+    s3 = np.diag([1.0, -1.0])
+    g01 = orc.gamma(0) @ orc.gamma(1)
+    expect = np.eye(8) - kappa * csw * np.kron(g01, 1j * np.sin(b) * s3)
+    assert np.abs(a - expect[None]).max() < 1e-14
+    assert v == len(a)
+
+
+def test_clover_schur_complement_and_solves():
+    """D_hat_sw equals the Schur complement of the dense D_sw (and its adjoint that of D_sw^+);
+    clover_apply's A^-1 inverts A; BiCGstab on D_sw and through the Schur route match a dense solve."""
+    dims = (2, 2, 4, 2)
+    nc, rep = 3, "fund"
+    uf = fx.gauge_field(dims, nc, "haar", seed=35)
+    ur = orc.rep_map(nc, rep, uf)
+    nr, v = 3, fx.volume(dims)
+    kappa, csw = 0.12, 1.1
+    d = dense(lambda f: orc.dsw(dims, ur, kappa, csw, f, THETA_TW), v, nr)
+    dd = dense(lambda f: orc.dsw(dims, ur, kappa, csw, f, THETA_TW, dagger=True), v, nr)
+    assert np.allclose(dd, d.conj().T, atol=1e-14)
+    par = np.repeat(orc.parity_of_sites(dims), 4 * nr)
+    ev, od = np.where(par == 0)[0], np.where(par == 1)[0]
+    schur = d[np.ix_(ev, ev)] - d[np.ix_(ev, od)] @ np.linalg.solve(d[np.ix_(od, od)], d[np.ix_(od, ev)])
+    dhat = dense(lambda f: orc.dsw_eo(dims, ur, kappa, csw, f, THETA_TW), v // 2, nr)
+    assert np.allclose(dhat, schur, atol=1e-13)
+    dhat_dag = dense(lambda f: orc.dsw_eo(dims, ur, kappa, csw, f, THETA_TW, dagger=True), v // 2, nr)
+    assert np.allclose(dhat_dag, dhat.conj().T, atol=1e-13)
+    t = fx.gaussian_spinor(dims, nr, seed=36)
+    to = orc.split_eo(dims, t)[1]
+    back = orc.clover_apply(dims, ur, kappa, csw, 1, orc.clover_apply(dims, ur, kappa, csw, 1, to, inverse=True))
+    assert rel(back, to) < 1e-14
+    b = fx.gaussian_spinor(dims, nr, seed=37)
+    ref = np.linalg.solve(d, b.reshape(-1))
+    bound = np.linalg.cond(d) * 1e-12
+    xf, info = orc.bicgstab_sw(dims, ur, kappa, csw, b, THETA_TW, orc.BICG_FULL, tol=1e-12)
+    assert info["status"] == 0 and rel(xf.reshape(-1), ref) <= bound
+    xs, info = orc.solve_dsw_eo_bicgstab(dims, ur, kappa, csw, b, THETA_TW, tol=1e-12)
+    assert info["status"] == 0 and rel(xs.reshape(-1), ref) <= bound
+
+
 # ----------------------------------------------------------------- rounding to storage formats
 
 def test_round_f32_and_f16_match_ieee_casts():
