@@ -246,6 +246,38 @@ int hrw_bicgstab_solve(const hrw_gauge *g, const hrw_solve_params *params, int n
                        const double *kappa_per_rhs, const double *b, double *x, hrw_solve_result *res,
                        void *workspace, size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------- clover term
+ * Sheikholeslami-Wohlert improvement (Sec. 3.1): D_sw = A - kappa H with the
+ * site-local A(x) = 1 - kappa c_sw sum_{mu<nu} g_mu g_nu (x) F_mu,nu(x), F the
+ * clover average (Q - Q^+)/8 of the four plaquette leaves of the mu-nu plane
+ * at x built from the represented links (this is the kappa normalisation of
+ * 1 + c_sw (i/4) sigma_mu,nu F_mu,nu).  A is Hermitian and block-diagonal in
+ * the chiral basis; the handle keeps the two (2 N_R)^2 blocks of A and of
+ * A^-1 per site, built once on the device in FP64 (and rounded to FP32 when
+ * HRW_STORE_F32 is in the mask), for one (kappa, c_sw).  It references the
+ * gauge field, which must stay alive, and holds no device memory of its own. */
+typedef struct hrw_clover hrw_clover;
+
+/* Bytes of caller storage for a clover term (mask: HRW_STORE_F64 and/or HRW_STORE_F32). */
+int hrw_clover_storage_size(const hrw_gauge *g, unsigned storage_mask, size_t *bytes);
+
+/* Build A and A^-1 from g's FP64 links (g needs HRW_STORE_F64).  A singular block
+ * (not possible for small kappa c_sw) leaves non-finite entries in A^-1. */
+int hrw_clover_create(const hrw_gauge *g, double kappa, double csw, unsigned storage_mask, void *storage,
+                      size_t storage_bytes, void *stream, hrw_clover **out);
+int hrw_clover_destroy(hrw_clover *c);
+
+/* out = D_sw in on the full lattice (dagger: A - kappa H^+ = D_sw^+), canonical
+ * fields as hrw_dw_apply; dtype F64 or F32 (the clover blocks and the links must
+ * be stored in it); workspace: hrw_workspace_size with params = NULL. */
+int hrw_dsw_apply(const hrw_clover *c, const double theta[4], int dtype, int n_rhs, int dagger,
+                  const double *in, double *out, void *workspace, size_t ws_bytes, void *stream);
+
+/* out_e = D_hat_sw in_e = A_ee in_e - kappa^2 H_eo A_oo^-1 H_oe in_e on even half
+ * fields (dagger: with the H^+ blocks, = D_hat_sw^+); as hrw_dsw_apply otherwise. */
+int hrw_dsw_eo_apply(const hrw_clover *c, const double theta[4], int dtype, int n_rhs, int dagger,
+                     const double *in_e, double *out_e, void *workspace, size_t ws_bytes, void *stream);
+
 /* ---------------------------------------------------------------- solver sessions
  * A session is a CG solver with n_slots slots (n_slots <= 64) that share one
  * resident gauge field, one set of parameters and one caller workspace

@@ -291,6 +291,63 @@ int hrw_bicgstab_solve(const hrw_gauge *g, const hrw_solve_params *params, int n
     });
 }
 
+int hrw_clover_storage_size(const hrw_gauge *g, unsigned storage_mask, size_t *bytes)
+{
+    return guarded([&] {
+        if (!g || !bytes) return fail(HRW_EINVAL, "null pointer");
+        if (!(storage_mask & 3u) || (storage_mask & ~3u)) return fail(HRW_EINVAL, "clover storage mask: F64 and/or F32");
+        return clover_storage_bytes(g, storage_mask, bytes);
+    });
+}
+
+int hrw_clover_create(const hrw_gauge *g, double kappa, double csw, unsigned storage_mask, void *storage,
+                      size_t storage_bytes, void *stream, hrw_clover **out)
+{
+    return guarded([&] {
+        if (!g || !storage || !out) return fail(HRW_EINVAL, "null pointer");
+        if (!(storage_mask & 3u) || (storage_mask & ~3u)) return fail(HRW_EINVAL, "clover storage mask: F64 and/or F32");
+        if (!(kappa == kappa) || !(csw == csw)) return fail(HRW_EINVAL, "kappa and c_sw must be finite");
+        if (!g->blocks[0][0]) return fail(HRW_EUNSUPPORTED, "the clover term is built from FP64 links (HRW_STORE_F64)");
+        return clover_create(g, kappa, csw, storage_mask, storage, storage_bytes, (hipStream_t)stream, out);
+    });
+}
+
+int hrw_clover_destroy(hrw_clover *c)
+{
+    delete c;
+    return HRW_OK;
+}
+
+static int check_clover_apply(const hrw_clover *c, int dt, int n_rhs, const void *in, const void *out, const void *ws)
+{
+    int rc;
+    if (!c) return fail(HRW_EINVAL, "null clover");
+    if ((rc = check_apply(c->g, dt, n_rhs, in, out))) return rc;
+    if (!ws) return fail(HRW_EINVAL, "null workspace");
+    if (dt > 1 || !c->a[dt][0]) return fail(HRW_EUNSUPPORTED, "clover blocks not stored in dtype %d", dt);
+    return HRW_OK;
+}
+
+int hrw_dsw_apply(const hrw_clover *c, const double theta[4], int dtype, int n_rhs, int dagger, const double *in,
+                  double *out, void *workspace, size_t ws_bytes, void *stream)
+{
+    return guarded([&] {
+        int rc;
+        if ((rc = check_clover_apply(c, dtype, n_rhs, in, out, workspace))) return rc;
+        return dsw_apply(c, theta, dtype, n_rhs, dagger, in, out, workspace, ws_bytes, (hipStream_t)stream);
+    });
+}
+
+int hrw_dsw_eo_apply(const hrw_clover *c, const double theta[4], int dtype, int n_rhs, int dagger,
+                     const double *in_e, double *out_e, void *workspace, size_t ws_bytes, void *stream)
+{
+    return guarded([&] {
+        int rc;
+        if ((rc = check_clover_apply(c, dtype, n_rhs, in_e, out_e, workspace))) return rc;
+        return dsw_eo_apply(c, theta, dtype, n_rhs, dagger, in_e, out_e, workspace, ws_bytes, (hipStream_t)stream);
+    });
+}
+
 int hrw_cg_session_create(const hrw_gauge *g, const hrw_solve_params *params, int n_slots, void *workspace,
                           size_t ws_bytes, void *stream, hrw_cg_session **out)
 {

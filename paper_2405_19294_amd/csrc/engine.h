@@ -18,6 +18,14 @@ struct hrw_gauge {
     void *fblocks[4][2]; // fundamental links in the hopping layout for the fused representation map (or null)
 };
 
+// resident clover term of one gauge field (blocks of A and A^-1 per parity)
+struct hrw_clover {
+    const hrw_gauge *g;
+    double kappa, csw;
+    unsigned mask;
+    void *a[2][2], *inv[2][2];  // [F64 / F32][parity]
+};
+
 namespace hrw {
 
 // error reporting (thread-local message)
@@ -140,6 +148,17 @@ int bicg_workspace(const Geom &g, int nr, int n_rhs, const hrw_solve_params *p, 
 int bicgstab_solve(const hrw_gauge *g, const hrw_solve_params *p, int n_rhs, const double *kappa,
                    const double *b, double *x, hrw_solve_result *res, void *ws, size_t ws_bytes,
                    hipStream_t st);
+int clover_storage_bytes(const hrw_gauge *g, unsigned mask, size_t *bytes);
+int clover_create(const hrw_gauge *g, double kappa, double csw, unsigned mask, void *storage, size_t storage_bytes,
+                  hipStream_t st, hrw_clover **out);
+hipError_t launch_clover_mul(int dt, int nr, const Geom &g, const void *bm, const void *in, void *out, int n_rhs,
+                             size_t rstride, hipStream_t st);
+int dsw_apply(const hrw_clover *c, const double theta[4], int dt, int n_rhs, int dagger, const double *in,
+              double *out, void *ws, size_t ws_bytes, hipStream_t st);
+int dsw_eo_apply(const hrw_clover *c, const double theta[4], int dt, int n_rhs, int dagger, const double *in,
+                 double *out, void *ws, size_t ws_bytes, hipStream_t st);
+int dsw_eo_packed(const hrw_clover *c, const Phases &ph, int dt, int n_rhs, bool dagger, size_t rs, const void *in_e,
+                  void *t, void *w, void *u, void *out_e, const double *coef_k2, const int *run, hipStream_t st);
 int session_create(const hrw_gauge *g, const hrw_solve_params *prm, int n_slots, void *ws, size_t ws_bytes,
                    hipStream_t st, hrw_cg_session **out);
 int session_destroy(hrw_cg_session *s);

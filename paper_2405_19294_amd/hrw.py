@@ -68,6 +68,11 @@ SIGNATURES = {
     "hrw_cg_solve": (I, [P, ctypes.POINTER(SolveParams), I, DP, P, P, ctypes.POINTER(SolveResult), P, SZ, P]),
     "hrw_bicgstab_solve": (I, [P, ctypes.POINTER(SolveParams), I, DP, P, P, ctypes.POINTER(SolveResult), P, SZ,
                                P]),
+    "hrw_clover_storage_size": (I, [P, ctypes.c_uint, SZP]),
+    "hrw_clover_create": (I, [P, D, D, ctypes.c_uint, P, SZ, P, ctypes.POINTER(P)]),
+    "hrw_clover_destroy": (I, [P]),
+    "hrw_dsw_apply": (I, [P, DP, I, I, I, P, P, P, SZ, P]),
+    "hrw_dsw_eo_apply": (I, [P, DP, I, I, I, P, P, P, SZ, P]),
     "hrw_cg_session_create": (I, [P, ctypes.POINTER(SolveParams), I, P, SZ, P, ctypes.POINTER(P)]),
     "hrw_cg_session_load": (I, [P, I, I, DP, P]),
     "hrw_cg_session_step": (I, [P, I, IP]),
@@ -266,6 +271,56 @@ def deo_apply(g: Gauge, kappa, psi_e: torch.Tensor, theta=(0, 0, 0, 0), dtype="f
 # takes 67 iterations to 1e-10, the 1e-3 trigger the same 51 as plain FP64.
 # The coarser 16-bit formats get correspondingly larger factors.
 RELIABLE_DELTA = {"f64": 0.0, "f32": 1e-3, "f16": 1e-2, "bf16": 1e-1}
+
+
+class Clover:
+    """Resident clover term of a gauge field for one (kappa, c_sw): blocks of A and A^-1 per site."""
+
+    def __init__(self, g: Gauge, kappa: float, csw: float, dtypes=("f64",), stream=None):
+        self.g, self.kappa, self.csw = g, float(kappa), float(csw)
+        mask = sum(1 << DTYPES[d] for d in dtypes)
+        out = ctypes.c_size_t()
+        _check(load().hrw_clover_storage_size(g.handle, mask, ctypes.byref(out)))
+        self.storage = _alloc_bytes(out.value, g.device)
+        h = ctypes.c_void_p()
+        _check(load().hrw_clover_create(g.handle, self.kappa, self.csw, mask, self.storage.data_ptr(), out.value,
+                                        _stream(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().hrw_clover_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dsw_apply(c: Clover, psi: torch.Tensor, theta=(0, 0, 0, 0), dtype="f64", dagger=False, out=None,
+              ws: Workspace | None = None, stream=None) -> torch.Tensor:
+    """D_sw psi = A psi - kappa H psi on the full lattice."""
+    g = c.g
+    n = _n_rhs(psi, g.volume * 4 * g.nr)
+    out = torch.empty_like(psi) if out is None else out
+    ws = ws or Workspace.for_apply(g, n)
+    _check(load().hrw_dsw_apply(c.handle, _doubles(theta), DTYPES[dtype], n, int(dagger), _dev_field(psi, "psi"),
+                                _dev_field(out, "out"), ws.buf.data_ptr(), ws.nbytes, _stream(stream)))
+    return out
+
+
+def dsw_eo_apply(c: Clover, psi_e: torch.Tensor, theta=(0, 0, 0, 0), dtype="f64", dagger=False, out=None,
+                 ws: Workspace | None = None, stream=None) -> torch.Tensor:
+    """D_hat_sw psi_e = A_ee psi_e - kappa^2 H_eo A_oo^-1 H_oe psi_e on even half fields."""
+    g = c.g
+    n = _n_rhs(psi_e, g.volume // 2 * 4 * g.nr)
+    out = torch.empty_like(psi_e) if out is None else out
+    ws = ws or Workspace.for_apply(g, n)
+    _check(load().hrw_dsw_eo_apply(c.handle, _doubles(theta), DTYPES[dtype], n, int(dagger), _dev_field(psi_e, "psi_e"),
+                                   _dev_field(out, "out"), ws.buf.data_ptr(), ws.nbytes, _stream(stream)))
+    return out
 
 
 def solve_params(tol=1e-10, max_iter=10000, system="ddag_d_eo", inner_dtype="f64", reliable_every=50,

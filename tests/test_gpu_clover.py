@@ -1,0 +1,102 @@
+"""GPU parity of the clover-improved operator (HIP library through its C ABI) against the CPU oracle.
+
+Tolerances:
+  * FP64: l2 relative <= 1e-13 and componentwise <= 1e-12 max|ref| (as every FP64 operator).
+  * FP32 D_sw: the kernel applies the FP32-rounded clover blocks A_r (built in FP64, rounded once)
+    and the FP32-rounded links to the FP32-rounded input; the reference is A_r psi_r - kappa H(U_r)
+    psi_r in FP64 and the difference must sit inside gamma_k (|A_r||psi_r| + kappa |H||psi_r|) +
+    u |ref| with k = 4 N_R + 18 (a hop of 2 N_R + 16 operations per component plus a block product
+    of 2 N_R), u = 2^-24.
+  * FP32 D_hat_sw (four stages, one of them A^-1): normwise relative error <= 1e-5 against the FP64
+    oracle on unrounded inputs (about 100 u, the stages' componentwise bounds compounded).
+"""
+
+import numpy as np
+import pytest
+
+import fixtures as fx
+import oracle as orc
+from paper_2405_19294_amd import hrw
+
+from gpu_helpers import THETA_AP, THETA_TW, U32, fp64_close, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ((4, 4, 2, 4), 2, "fund"),
+    ((4, 2, 4, 4), 3, "fund"),
+    ((2, 2, 2, 6), 3, "fund"),     # ragged half field
+    ((4, 4, 2, 4), 2, "adj"),
+    ((2, 4, 4, 4), 3, "sym"),
+    ((4, 2, 2, 4), 4, "asym"),
+    ((8, 8, 8, 8), 3, "fund"),     # several tiles
+]
+KAPPA, CSW = 0.13, 1.25
+
+
+def ids(c):
+    return f"{'x'.join(map(str, c[0]))}-su{c[1]}-{c[2]}"
+
+
+def setup(dims, nc, rep, dtypes=("f64", "f32"), seed=41):
+    uf = fx.gauge_field(dims, nc, "haar", seed=seed)
+    ur = orc.rep_map(nc, rep, uf)
+    g = hrw.Gauge(dims, nc, rep, to_dev(uf), dtypes=dtypes)
+    c = hrw.Clover(g, KAPPA, CSW, dtypes=tuple(d for d in dtypes if d in ("f64", "f32")))
+    return ur, g, c
+
+
+@pytest.mark.parametrize("case", CASES, ids=ids)
+def test_clover_f64_operators(case):
+    dims, nc, rep = case
+    ur, g, c = setup(dims, nc, rep, dtypes=("f64",))
+    psi = fx.gaussian_spinor(dims, g.nr, seed=42)
+    for dagger in (False, True):
+        out = hrw.dsw_apply(c, to_dev(psi), THETA_TW, "f64", dagger=dagger).cpu().numpy()
+        fp64_close(out, orc.dsw(dims, ur, KAPPA, CSW, psi, THETA_TW, dagger=dagger))
+    pe = orc.split_eo(dims, psi)[0]
+    for dagger in (False, True):
+        out = hrw.dsw_eo_apply(c, to_dev(pe), THETA_TW, "f64", dagger=dagger).cpu().numpy()
+        fp64_close(out, orc.dsw_eo(dims, ur, KAPPA, CSW, pe, THETA_TW, dagger=dagger))
+
+
+@pytest.mark.parametrize("case", CASES[:6], ids=ids)
+def test_clover_f32_within_bound(case):
+    dims, nc, rep = case
+    ur, g, c = setup(dims, nc, rep, dtypes=("f64", "f32"), seed=43)
+    nr = g.nr
+    psi = fx.gaussian_spinor(dims, nr, seed=44)
+    psi_r, ur_r = orc.round_to("f32", psi), orc.round_to("f32", ur)
+    a_r = orc.round_to("f32", orc.clover(dims, ur, KAPPA, CSW))
+    out = hrw.dsw_apply(c, to_dev(psi), THETA_TW, "f32").cpu().numpy()
+    flat = psi_r.reshape(len(psi_r), 4 * nr)
+    ref = (np.einsum("sij,sj->si", a_r, flat).reshape(psi.shape)
+           - KAPPA * orc.hop(dims, ur_r, psi_r, THETA_TW))
+    absa = np.einsum("sij,sj->si", np.abs(a_r), np.abs(flat)).reshape(psi.shape)
+    bound = (orc.gamma_k(4 * nr + 18, U32) * (absa + KAPPA * orc.hop_abs(dims, np.abs(ur_r), np.abs(psi_r)))
+             + U32 * np.abs(ref) + 1e-300)
+    assert np.max(np.abs(out - ref) / bound) <= 1.0
+    pe = orc.split_eo(dims, psi)[0]
+    out = hrw.dsw_eo_apply(c, to_dev(pe), THETA_TW, "f32").cpu().numpy()
+    assert rel(out, orc.dsw_eo(dims, ur, KAPPA, CSW, pe, THETA_TW)) <= 1e-5
+
+
+def test_clover_multi_rhs_and_limits():
+    """Several right-hand sides in one call equal single calls bitwise; c_sw = 0 reproduces D_W
+    bitwise; a clover term without FP32 blocks refuses FP32 applies."""
+    dims = (4, 4, 4, 4)
+    ur, g, c = setup(dims, 3, "fund")
+    psi = fx.gaussian_spinor(dims, 3, seed=45, n_rhs=3)
+    many = hrw.dsw_apply(c, to_dev(psi), THETA_AP, "f64").cpu().numpy()
+    for k in range(3):
+        assert np.array_equal(many[k], hrw.dsw_apply(c, to_dev(psi[k]), THETA_AP, "f64").cpu().numpy())
+    pe = orc.split_eo(dims, psi)[0]
+    many = hrw.dsw_eo_apply(c, to_dev(pe), THETA_AP, "f32").cpu().numpy()
+    for k in range(3):
+        assert np.array_equal(many[k], hrw.dsw_eo_apply(c, to_dev(pe[k]), THETA_AP, "f32").cpu().numpy())
+    c0 = hrw.Clover(g, KAPPA, 0.0, dtypes=("f64",))
+    a = hrw.dsw_apply(c0, to_dev(psi[0]), THETA_AP, "f64").cpu().numpy()
+    fp64_close(a, orc.dw(dims, ur, KAPPA, psi[0], THETA_AP))
+    with pytest.raises(hrw.HrwError) as e:
+        hrw.dsw_apply(c0, to_dev(psi[0]), THETA_AP, "f32")
+    assert e.value.code == hrw.EUNSUPPORTED
