@@ -278,6 +278,16 @@ int hrw_dsw_apply(const hrw_clover *c, const double theta[4], int dtype, int n_r
 int hrw_dsw_eo_apply(const hrw_clover *c, const double theta[4], int dtype, int n_rhs, int dagger,
                      const double *in_e, double *out_e, void *workspace, size_t ws_bytes, void *stream);
 
+/* BiCGstab with the clover term: D_hat_sw x_e = b_e (HRW_SYS_DHAT_EO) or D_sw x = b
+ * through the Schur complement (HRW_SYS_D_EO: b'_e = b_e + kappa H_eo A_oo^-1 b_o,
+ * D_hat_sw x_e = b'_e, x_o = A_oo^-1 (b_o + kappa H_oe x_e), res.d_rel_resid =
+ * |b - D_sw x| / |b|), for the kappa the clover term was built with; otherwise as
+ * hrw_bicgstab_solve (HRW_F32 inner fields need FP32 clover blocks and links).
+ * Workspace: hrw_clover_workspace_size. */
+int hrw_clover_workspace_size(const hrw_clover *c, int n_rhs, const hrw_solve_params *params, size_t *bytes);
+int hrw_clover_bicgstab_solve(const hrw_clover *c, const hrw_solve_params *params, int n_rhs, const double *b,
+                              double *x, hrw_solve_result *res, void *workspace, size_t ws_bytes, void *stream);
+
 /* ---------------------------------------------------------------- solver sessions
  * A session is a CG solver with n_slots slots (n_slots <= 64) that share one
  * resident gauge field, one set of parameters and one caller workspace

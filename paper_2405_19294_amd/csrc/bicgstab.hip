@@ -524,6 +524,7 @@ struct BiPlan {
     BiField x, r, r0, p, v, s, t, o;  // inner precision (o: odd temporary)
     BiField b, x64, r64, q64, o64;    // FP64 (x64 only in mixed mode)
     BiField bfull, dfull, efull;      // HRW_SYS_D_EO: full source, full solution, D x
+    BiField w, u, w64, u64;           // clover: odd and even temporaries of D_hat_sw
     BiState *st;
     int *active;  // [0, MAX_RHS) active, [MAX_RHS, 2 MAX_RHS) due
     double *coef_k, *coef_k2, *coef_mk, *scal;
@@ -541,7 +542,8 @@ static BiField take_field(Arena &ar, int dt, size_t H, bool two, int n_rhs)
     return f;
 }
 
-static void plan_bicg(Arena &ar, const Geom &g, int nr, int n_rhs, const hrw_solve_params *prm, BiPlan &P)
+static void plan_bicg(Arena &ar, const Geom &g, int nr, int n_rhs, const hrw_solve_params *prm, BiPlan &P,
+                      bool clover = false)
 {
     P.sys = prm->system;
     P.dl = prm->inner_dtype;
@@ -553,6 +555,12 @@ static void plan_bicg(Arena &ar, const Geom &g, int nr, int n_rhs, const hrw_sol
     for (BiField *f : {&P.x, &P.r, &P.r0, &P.p, &P.v, &P.s, &P.t, &P.o}) *f = half(P.dl);
     for (BiField *f : {&P.b, &P.r64, &P.q64, &P.o64}) *f = half(0);
     if (P.mixed) P.x64 = half(0);
+    if (clover) {
+        P.w = half(P.dl);
+        P.u = half(P.dl);
+        P.w64 = half(0);
+        P.u64 = half(0);
+    }
     if (P.sys == HRW_SYS_D_EO) {
         P.bfull = take_field(ar, 0, P.H, true, n_rhs);
         P.dfull = take_field(ar, 0, P.H, true, n_rhs);
@@ -570,11 +578,11 @@ static void plan_bicg(Arena &ar, const Geom &g, int nr, int n_rhs, const hrw_sol
     P.part = (double *)ar.take(sizeof(double) * (size_t)P.pstride * n_rhs);
 }
 
-int bicg_workspace(const Geom &g, int nr, int n_rhs, const hrw_solve_params *p, size_t *bytes)
+int bicg_workspace(const Geom &g, int nr, int n_rhs, const hrw_solve_params *p, size_t *bytes, bool clover)
 {
     Arena ar(nullptr, 0);
     BiPlan P;
-    plan_bicg(ar, g, nr, n_rhs, p, P);
+    plan_bicg(ar, g, nr, n_rhs, p, P, clover);
     *bytes = ar.off + 256;
     return HRW_OK;
 }
@@ -588,11 +596,18 @@ struct BiRun {
     int n;
     hipStream_t st;
     int nbh;  // vector-kernel blocks over one half field
+    const hrw_clover *cl;  // clover term (D_hat_sw in place of D_hat), or null
 };
 
-// out = D_hat in on the dtype of the fields (run: per rhs skip mask)
+// out = D_hat in (or D_hat_sw with a clover term) on the dtype of the fields (run: per rhs skip mask)
 static int apply_dhat(BiRun &R, const BiField &in, const BiField &odd, const BiField &out, const int *run)
 {
+    if (R.cl) {
+        const bool lo = in.dt != 0;
+        const BiField &w = lo ? R.P->w : R.P->w64, &u = lo ? R.P->u : R.P->u64;
+        return dsw_eo_packed(R.cl, R.ph, in.dt, R.n, false, R.P->RS, in.h(0), odd.h(0), w.h(0), u.h(0), out.h(0),
+                             R.P->coef_k2, run, R.st);
+    }
     HopCall a;
     a.dt = in.dt;
     a.n_rhs = R.n;
@@ -754,8 +769,11 @@ static int bi_finish(BiRun &R, double *x_out, hrw_solve_result *res, std::chrono
         c.coef = P.coef_mk;
         c.in[0] = P.dfull.h(0);
         c.self[1] = P.bfull.h(1);
-        c.out[1] = P.dfull.h(1);
+        c.out[1] = R.cl ? P.efull.h(1) : P.dfull.h(1);
         if ((rc = run_hop(g, R.ph, c, st))) return rc;
+        // with a clover term x_o = A_oo^-1 (b_o + kappa H_oe x_e)
+        if (R.cl)
+            HRW_HIP(launch_clover_mul(0, g->nr, g->g, R.cl->inv[0][1], P.efull.h(1), P.dfull.h(1), n, P.RS2, st));
         HRW_HIP(launch_unpack_spinor(0, g->nr, g->g, true, 0, n, P.dfull.h(0), P.dfull.h(1), P.RS2, x_out, st));
         // |b - D x| / |b| on the full lattice
         HopCall d;
@@ -769,6 +787,13 @@ static int bi_finish(BiRun &R, double *x_out, hrw_solve_result *res, std::chrono
             d.in[q] = P.dfull.h(q);
             d.self[q] = P.dfull.h(q);
             d.out[q] = P.efull.h(q);
+        }
+        if (R.cl) {
+            // D_sw x = A x - kappa H x: self = A x (the epilogue reads self before it writes out in place)
+            for (int q = 0; q < 2; ++q) {
+                HRW_HIP(launch_clover_mul(0, g->nr, g->g, R.cl->a[0][q], P.dfull.h(q), P.efull.h(q), n, P.RS2, st));
+                d.self[q] = P.efull.h(q);
+            }
         }
         if ((rc = run_hop(g, R.ph, d, st))) return rc;
         const int nb2 = vec_grid(2 * P.H);
@@ -807,14 +832,14 @@ static int bi_finish(BiRun &R, double *x_out, hrw_solve_result *res, std::chrono
 
 int bicgstab_solve(const hrw_gauge *g, const hrw_solve_params *prm, int n_rhs, const double *kappa,
                    const double *b_in, double *x_out, hrw_solve_result *res, void *ws, size_t ws_bytes,
-                   hipStream_t st)
+                   hipStream_t st, const hrw_clover *cl)
 {
     const auto t0 = std::chrono::steady_clock::now();
     Arena ar(ws, ws_bytes);
     BiPlan P;
-    plan_bicg(ar, g->g, g->nr, n_rhs, prm, P);
+    plan_bicg(ar, g->g, g->nr, n_rhs, prm, P, cl != nullptr);
     if (!ar.fits()) return fail(HRW_ENOMEM, "workspace too small: need %zu bytes, got %zu", ar.off + 256, ws_bytes);
-    BiRun R{g, &P, make_phases(prm->theta), n_rhs, st, vec_grid(P.H)};
+    BiRun R{g, &P, make_phases(prm->theta), n_rhs, st, vec_grid(P.H), cl};
     int rc;
     double kv[MAX_RHS], k2[MAX_RHS], mk[MAX_RHS];
     for (int j = 0; j < n_rhs; ++j) {
@@ -830,8 +855,9 @@ int bicgstab_solve(const hrw_gauge *g, const hrw_solve_params *prm, int n_rhs, c
     if (P.sys == HRW_SYS_DHAT_EO) {
         HRW_HIP(launch_pack_spinor(0, g->nr, g->g, false, 0, n_rhs, b_in, P.b.h(0), nullptr, P.RS, st));
     } else {
-        // b'_e = b_e + kappa H_eo b_o
+        // b'_e = b_e + kappa H_eo b_o (with a clover term: b_e + kappa H_eo A_oo^-1 b_o)
         HRW_HIP(launch_pack_spinor(0, g->nr, g->g, true, 0, n_rhs, b_in, P.bfull.h(0), P.bfull.h(1), P.RS2, st));
+        if (cl) HRW_HIP(launch_clover_mul(0, g->nr, g->g, cl->inv[0][1], P.bfull.h(1), P.efull.h(1), n_rhs, P.RS2, st));
         HopCall c;
         c.dt = 0;
         c.n_rhs = n_rhs;
@@ -839,7 +865,7 @@ int bicgstab_solve(const hrw_gauge *g, const hrw_solve_params *prm, int n_rhs, c
         c.parity = 0;
         c.epi = EPI_AXPY;
         c.coef = P.coef_mk;
-        c.in[1] = P.bfull.h(1);
+        c.in[1] = cl ? P.efull.h(1) : P.bfull.h(1);
         c.self[0] = P.bfull.h(0);
         c.out[0] = P.dfull.h(0);
         if ((rc = run_hop(g, R.ph, c, st))) return rc;

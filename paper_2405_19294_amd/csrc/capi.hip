@@ -348,6 +348,45 @@ int hrw_dsw_eo_apply(const hrw_clover *c, const double theta[4], int dtype, int 
     });
 }
 
+static int check_bicg_params(const hrw_solve_params *params, int n_rhs)
+{
+    int rc;
+    if ((rc = check_params(params)) || (rc = check_rhs(n_rhs))) return rc;
+    if (params->system != HRW_SYS_DHAT_EO && params->system != HRW_SYS_D_EO)
+        return fail(HRW_EINVAL, "BiCGstab solves HRW_SYS_DHAT_EO or HRW_SYS_D_EO, got system %d", params->system);
+    if (params->inner_dtype != HRW_F64 && params->inner_dtype != HRW_F32)
+        return fail(HRW_EUNSUPPORTED, "BiCGstab runs with FP64 or FP32 inner fields");
+    return HRW_OK;
+}
+
+int hrw_clover_workspace_size(const hrw_clover *c, int n_rhs, const hrw_solve_params *params, size_t *bytes)
+{
+    return guarded([&] {
+        int rc;
+        if (!c || !bytes) return fail(HRW_EINVAL, "null pointer");
+        if ((rc = check_bicg_params(params, n_rhs))) return rc;
+        return bicg_workspace(c->g->g, c->g->nr, n_rhs, params, bytes, true);
+    });
+}
+
+int hrw_clover_bicgstab_solve(const hrw_clover *c, const hrw_solve_params *params, int n_rhs, const double *b,
+                              double *x, hrw_solve_result *res, void *workspace, size_t ws_bytes, void *stream)
+{
+    return guarded([&] {
+        int rc;
+        if (!c) return fail(HRW_EINVAL, "null clover");
+        if ((rc = check_bicg_params(params, n_rhs))) return rc;
+        if (!b || !x || !res || !workspace) return fail(HRW_EINVAL, "null pointer");
+        if (b == x) return fail(HRW_EINVAL, "b and x must not overlap");
+        const int dl = params->inner_dtype;
+        if (!c->g->blocks[dl][0] || !c->a[dl][0] || !c->a[0][0])
+            return fail(HRW_EUNSUPPORTED, "links and clover blocks needed in FP64 and in the inner dtype");
+        double k[MAX_RHS];
+        for (int j = 0; j < n_rhs; ++j) k[j] = c->kappa;
+        return bicgstab_solve(c->g, params, n_rhs, k, b, x, res, workspace, ws_bytes, (hipStream_t)stream, c);
+    });
+}
+
 int hrw_cg_session_create(const hrw_gauge *g, const hrw_solve_params *params, int n_slots, void *workspace,
                           size_t ws_bytes, void *stream, hrw_cg_session **out)
 {

@@ -144,10 +144,10 @@ int deo_apply(const hrw_gauge *g, const double *kappa, const double theta[4], in
 int cg_solve(const hrw_gauge *g, const hrw_solve_params *p, int n_rhs, const double *kappa,
              const double *b, double *x, hrw_solve_result *res, void *ws, size_t ws_bytes,
              hipStream_t st);
-int bicg_workspace(const Geom &g, int nr, int n_rhs, const hrw_solve_params *p, size_t *bytes);
+int bicg_workspace(const Geom &g, int nr, int n_rhs, const hrw_solve_params *p, size_t *bytes, bool clover = false);
 int bicgstab_solve(const hrw_gauge *g, const hrw_solve_params *p, int n_rhs, const double *kappa,
                    const double *b, double *x, hrw_solve_result *res, void *ws, size_t ws_bytes,
-                   hipStream_t st);
+                   hipStream_t st, const hrw_clover *cl = nullptr);
 int clover_storage_bytes(const hrw_gauge *g, unsigned mask, size_t *bytes);
 int clover_create(const hrw_gauge *g, double kappa, double csw, unsigned mask, void *storage, size_t storage_bytes,
                   hipStream_t st, hrw_clover **out);

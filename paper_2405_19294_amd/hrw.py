@@ -73,6 +73,9 @@ SIGNATURES = {
     "hrw_clover_destroy": (I, [P]),
     "hrw_dsw_apply": (I, [P, DP, I, I, I, P, P, P, SZ, P]),
     "hrw_dsw_eo_apply": (I, [P, DP, I, I, I, P, P, P, SZ, P]),
+    "hrw_clover_workspace_size": (I, [P, I, ctypes.POINTER(SolveParams), SZP]),
+    "hrw_clover_bicgstab_solve": (I, [P, ctypes.POINTER(SolveParams), I, P, P, ctypes.POINTER(SolveResult), P, SZ,
+                                      P]),
     "hrw_cg_session_create": (I, [P, ctypes.POINTER(SolveParams), I, P, SZ, P, ctypes.POINTER(P)]),
     "hrw_cg_session_load": (I, [P, I, I, DP, P]),
     "hrw_cg_session_step": (I, [P, I, IP]),
@@ -370,6 +373,23 @@ def bicgstab_solve(g: Gauge, b: torch.Tensor, kappa, params: SolveParams, x=None
     res = (SolveResult * n)()
     rc = load().hrw_bicgstab_solve(g.handle, ctypes.byref(params), n, _doubles(ks), _dev_field(b, "b"),
                                    _dev_field(x, "x"), res, ws.buf.data_ptr(), ws.nbytes, _stream(stream))
+    if rc < 0 and rc != EBREAKDOWN:
+        _check(rc)
+    return x, [r.as_dict() for r in res], rc
+
+
+def clover_bicgstab_solve(c: Clover, b: torch.Tensor, params: SolveParams, x=None, stream=None):
+    """BiCGstab with the clover term for n_rhs stacked systems at the clover's kappa
+    ("dhat_eo": even half fields, "d_eo": full-lattice fields); returns (x, results, status)."""
+    g = c.g
+    n = _n_rhs(b, _system_field(g, params.system))
+    x = torch.empty_like(b) if x is None else x
+    out = ctypes.c_size_t()
+    _check(load().hrw_clover_workspace_size(c.handle, n, ctypes.byref(params), ctypes.byref(out)))
+    ws = Workspace(out.value, g.device)
+    res = (SolveResult * n)()
+    rc = load().hrw_clover_bicgstab_solve(c.handle, ctypes.byref(params), n, _dev_field(b, "b"), _dev_field(x, "x"),
+                                          res, ws.buf.data_ptr(), ws.nbytes, _stream(stream))
     if rc < 0 and rc != EBREAKDOWN:
         _check(rc)
     return x, [r.as_dict() for r in res], rc
