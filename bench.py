@@ -19,7 +19,8 @@ The default workload (c2) is the one the headline numbers are quoted on; the
 others print the same kind of JSON line for the remaining configurations:
 c1 SU(2) fund 4^4 (latency-bound), c3 SU(2) adj / SU(4) asym 24^3x48 mixed
 precision, c4 SU(3) sym 32^4 multi-source, c5 the serving stream, ops the operator table
-over the four representations, bicgstab the default request solved by BiCGstab.
+over the four representations, bicgstab the default request solved by BiCGstab, clover the
+same request with the clover term (c_sw = 1) solved by BiCGstab.
 """
 
 from __future__ import annotations
@@ -74,7 +75,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=0, help="oracle CG iterations in the CPU sample (0 = auto)")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "ops", "bicgstab"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "ops", "bicgstab", "clover"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is not part of it",
@@ -82,7 +83,7 @@ def main():
         sys.exit(2)
     if args.workload != "c2":
         out = {"c1": workload_c1, "c3": workload_c3, "c4": workload_c4, "c5": workload_c5,
-               "ops": workload_ops, "bicgstab": workload_bicgstab}[args.workload](args)
+               "ops": workload_ops, "bicgstab": workload_bicgstab, "clover": workload_clover}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
 
@@ -222,6 +223,87 @@ def workload_bicgstab(args):
     m = rows["f32"]
     return _line(m["solves_per_s"], "solves/s", args.steps, 1, m["ms_per_solve"], "f32", cfg, roof,
                  bicgstab=rows, fp64_cg_solves_per_s=round(1.0 / per_cg, 3))
+
+
+def workload_clover(args):
+    """The default workload's gauge field and source with the clover term (c_sw = 1): clover setup,
+    D_sw and D_hat_sw applies in FP64 and FP32, and D_sw x = b by BiCGstab on D_hat_sw (FP64, and
+    FP32 inner fields with FP64 reliable updates; the line's value) beside the same request
+    without the clover term."""
+    import torch
+
+    import fixtures as fx
+    from paper_2405_19294_amd import hrw
+    dev = torch.device("cuda:0")
+    dims = tuple(WORKLOAD["lattice"])
+    kappa, csw, theta = WORKLOAD["kappa"], 1.0, (np.pi, 0.0, 0.0, 0.0)
+    uf_d = torch.from_numpy(fx.gauge_field(dims, 3, "thermal", seed=2, eps=0.3)).to(dev)
+    b_d = torch.from_numpy(fx.gaussian_spinor(dims, 3, seed=3)).to(dev)
+    g = hrw.Gauge(dims, 3, "fund", uf_d, dtypes=("f64", "f32"))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c = hrw.Clover(g, kappa, csw, dtypes=("f64", "f32"))
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    v = int(np.prod(dims))
+    pe = b_d[: v // 2].contiguous()
+    ops = {}
+    for dt in ("f64", "f32"):
+        for name, fn, arg in (("dsw", hrw.dsw_apply, b_d), ("dsw_eo", hrw.dsw_eo_apply, pe)):
+            out = torch.empty_like(arg)
+            ws = hrw.Workspace.for_apply(g, 1)
+            for _ in range(3):
+                fn(c, arg, theta, dt, out=out, ws=ws)
+            torch.cuda.synchronize()
+            hrw.timing_enable(True)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(20):
+                fn(c, arg, theta, dt, out=out, ws=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            hop = hrw.timing_read(0)
+            hrw.timing_enable(False)
+            ops[f"{name}_{dt}"] = {"call_us": round(e0.elapsed_time(e1) * 1e3 / 20, 1),
+                                   "hop_us": round(hop["ms"] * 1e3 / 20, 1)}
+            log(f"clover {name} {dt}: {ops[f'{name}_{dt}']}")
+    rows, roof = {}, None
+    for inner in ("f32", "f64"):
+        prm = hrw.solve_params(tol=WORKLOAD["tol"], max_iter=5000, system="d_eo", inner_dtype=inner, theta=theta,
+                               reliable_delta=hrw.RELIABLE_DELTA[inner])
+        hrw.clover_bicgstab_solve(c, b_d, prm)
+        torch.cuda.synchronize()
+        if inner == "f32":
+            hrw.timing_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            x, res, rc = hrw.clover_bicgstab_solve(c, b_d, prm)
+            if rc != 0:
+                raise RuntimeError(f"clover solve failed: {res}")
+        torch.cuda.synchronize()
+        per = (time.perf_counter() - t0) / args.steps
+        if inner == "f32":
+            roof = _hop_roofline(hrw, "hop_kernel<N_R=3, RS=3, float> (with the FP64 launches of the updates)")
+            hrw.timing_enable(False)
+        r = res[0]
+        rows[inner] = {"solves_per_s": round(1.0 / per, 3), "ms_per_solve": round(per * 1e3, 2), "iters": r["iters"],
+                       "reliable_updates": r["reliable_updates"], "restarts": r["restarts"],
+                       "true_rel_resid": r["true_rel_resid"], "d_rel_resid": r["d_rel_resid"]}
+        log(f"clover BiCGstab {inner}: {rows[inner]}")
+    c.close()
+    # the same request without the clover term
+    prm = hrw.solve_params(tol=WORKLOAD["tol"], max_iter=5000, system="d_eo", inner_dtype="f32", theta=theta,
+                           reliable_delta=hrw.RELIABLE_DELTA["f32"])
+    _, res0, per0, _ = _solve_timed(hrw, torch, g, b_d, kappa, prm, max(1, args.steps // 2), 1,
+                                    solver=hrw.bicgstab_solve)
+    g.close()
+    cfg = dict(WORKLOAD, workload="su3_fund_32^4_clover_eo_bicgstab_mixed_f32", c_sw=csw,
+               system="D_sw x = b via even/odd Schur complement (A_ee - kappa^2 H_eo A_oo^-1 H_oe), BiCGstab",
+               inner_dtype="f32", reliable_every=50, reliable_delta=1e-3)
+    m = rows["f32"]
+    return _line(m["solves_per_s"], "solves/s", args.steps, 1, m["ms_per_solve"], "f32", cfg, roof,
+                 clover_setup_ms=round(setup_ms, 1), operators=ops, bicgstab=rows,
+                 without_clover_f32={"solves_per_s": round(1.0 / per0, 3), "iters": res0[0]["iters"]})
 
 
 def bicgstab_rows(torch, hrw, dev, dims, nc, rep, uf_d, b_d, kappa, theta, cg_value, steps,

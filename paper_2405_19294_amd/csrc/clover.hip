@@ -16,6 +16,11 @@
 // The blocks and their inverses are built once per (gauge field, kappa, c_sw)
 // by a setup kernel in FP64 (Gauss-Jordan with partial pivoting per block)
 // and kept resident in the site-blocked layout, in FP64 and optionally FP32.
+// Both are Hermitian, so a block of size M = 2 N_R is stored as M^2 / 2
+// complex slots: the M real diagonal entries in pairs (slot r/2, real part for
+// even r, imaginary part for odd r) followed by the strictly upper triangle
+// row by row; the site-local multiply reads every slot once and uses it for
+// both (r, c) and (c, r).
 // The operator applies compose the existing hopping kernels with a site-local
 // block multiply:
 //   D_sw psi      = (A psi) - kappa H psi                    (axpy epilogue, self = A psi)
@@ -33,10 +38,12 @@ struct Z {
 };
 __device__ inline Z zmul(Z a, Z b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
 __device__ inline Z zmulc(Z a, Z b) { return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im}; }  // a conj(b)
-__device__ inline Z zcmul(Z a, Z b) { return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re}; }  // conj(a) b
 
-// elements of one packed clover block field: per site 2 chirality blocks of (2 N_R)^2
-inline size_t clover_elems(const Geom &g, int nr) { return (size_t)g.nblk * BLK * 2 * (2 * nr) * (2 * nr); }
+// elements of one packed clover block field: per site 2 chirality blocks of (2 N_R)^2 / 2 slots
+inline size_t clover_elems(const Geom &g, int nr) { return (size_t)g.nblk * BLK * (2 * nr) * (2 * nr); }
+
+// slot of the upper entry (r, c), r < c, of a packed Hermitian M x M block
+__host__ __device__ constexpr int herm_slot(int m, int r, int c) { return m / 2 + r * m - r * (r + 1) / 2 + (c - r - 1); }
 
 template <int NR>
 __device__ inline void fetch_link(const Geom &g, const cpx<double> *const blk[2], int y0, int y1, int y2, int y3,
@@ -122,13 +129,30 @@ struct CloverOut {
     cpx<float> *a32[2], *inv32[2];   // optional
 };
 
+// upper triangle and real diagonal of a Hermitian block, in FP64 and (if p32) FP32
+template <int M>
+__device__ inline void store_packed(cpx<double> *p64, cpx<float> *p32, int i, int chi, const Z (&a)[M][M])
+{
+    constexpr int BS = M * M / 2;
+    for (int r = 0; r < M; r += 2) {
+        const size_t o = lay(i, chi * BS + r / 2, 2 * BS);
+        p64[o] = {a[r][r].re, a[r + 1][r + 1].re};
+        if (p32) p32[o] = {(float)a[r][r].re, (float)a[r + 1][r + 1].re};
+    }
+    for (int r = 0; r < M; ++r)
+        for (int c = r + 1; c < M; ++c) {
+            const size_t o = lay(i, chi * BS + herm_slot(M, r, c), 2 * BS);
+            p64[o] = {a[r][c].re, a[r][c].im};
+            if (p32) p32[o] = {(float)a[r][c].re, (float)a[r][c].im};
+        }
+}
+
 // One thread per site: the two chirality blocks of A and of A^-1.
 template <int NR>
 __global__ void __launch_bounds__(64) clover_build_kernel(Geom g, const cpx<double> *blk0, const cpx<double> *blk1,
                                                           double kc, CloverOut out)
 {
     constexpr int M = 2 * NR;
-    constexpr int NCOMP = 2 * M * M;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 2 * g.half) return;
     const int q = t >= g.half ? 1 : 0;
@@ -158,13 +182,9 @@ __global__ void __launch_bounds__(64) clover_build_kernel(Geom g, const cpx<doub
                 a[r][NR + c] = {-kc * (-g1.im + g2.re), -kc * (g1.re + g2.im)};  // -kc (i G1 + G2)
                 a[NR + r][c] = {-kc * (-g1.im - g2.re), -kc * (g1.re - g2.im)};  // -kc (i G1 - G2)
             }
+        store_packed(out.a64[q], out.a32[q], i, chi, a);
         for (int r = 0; r < M; ++r)
-            for (int c = 0; c < M; ++c) {
-                const size_t o = lay(i, chi * M * M + r * M + c, NCOMP);
-                out.a64[q][o] = {a[r][c].re, a[r][c].im};
-                if (out.a32[q]) out.a32[q][o] = {(float)a[r][c].re, (float)a[r][c].im};
-                inv[r][c] = {r == c ? 1.0 : 0.0, 0.0};
-            }
+            for (int c = 0; c < M; ++c) inv[r][c] = {r == c ? 1.0 : 0.0, 0.0};
         // Gauss-Jordan elimination with partial pivoting
         for (int c = 0; c < M; ++c) {
             int piv = c;
@@ -203,12 +223,7 @@ __global__ void __launch_bounds__(64) clover_build_kernel(Geom g, const cpx<doub
                 }
             }
         }
-        for (int r = 0; r < M; ++r)
-            for (int c = 0; c < M; ++c) {
-                const size_t o = lay(i, chi * M * M + r * M + c, NCOMP);
-                out.inv64[q][o] = {inv[r][c].re, inv[r][c].im};
-                if (out.inv32[q]) out.inv32[q][o] = {(float)inv[r][c].re, (float)inv[r][c].im};
-            }
+        store_packed(out.inv64[q], out.inv32[q], i, chi, inv);
     }
 }
 
@@ -220,29 +235,44 @@ __global__ void __launch_bounds__(WG) clover_mul_kernel(const cpx<S> *__restrict
 {
     typedef typename acc_of<S>::type A;
     constexpr int M = 2 * NR;
-    constexpr int NCOMP = 2 * M * M;
+    constexpr int BS = M * M / 2;
     constexpr int NC = 4 * NR;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= half) return;
     const int chi = blockIdx.z;
     const size_t ro = (size_t)blockIdx.y * rstride;
-    A vr[M], vi[M];
+    const cpx<S> *blk = bm;
+    A vr[M], vi[M], sr[M], si[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) load_c(in + ro + lay(i, chi * M + c, NC), vr[c], vi[c]);
+    // diagonal (real)
 #pragma unroll
-    for (int r = 0; r < M; ++r) {
-        A sr = 0, si = 0;
-#pragma unroll
-        for (int c = 0; c < M; ++c) {
-            A mr, mi;
-            load_c(bm + lay(i, chi * M * M + r * M + c, NCOMP), mr, mi);
-            sr = fmac(mr, vr[c], sr);
-            sr = fmac(-mi, vi[c], sr);
-            si = fmac(mr, vi[c], si);
-            si = fmac(mi, vr[c], si);
-        }
-        store_c(out + ro + lay(i, chi * M + r, NC), sr, si);
+    for (int r = 0; r < M; r += 2) {
+        A d0, d1;
+        load_c(blk + lay(i, chi * BS + r / 2, 2 * BS), d0, d1);
+        sr[r] = d0 * vr[r];
+        si[r] = d0 * vi[r];
+        sr[r + 1] = d1 * vr[r + 1];
+        si[r + 1] = d1 * vi[r + 1];
     }
+    // each upper slot m = B(r, c) serves out_r += m v_c and out_c += conj(m) v_r
+#pragma unroll
+    for (int r = 0; r < M; ++r)
+#pragma unroll
+        for (int c = r + 1; c < M; ++c) {
+            A mr, mi;
+            load_c(blk + lay(i, chi * BS + herm_slot(M, r, c), 2 * BS), mr, mi);
+            sr[r] = fmac(mr, vr[c], sr[r]);
+            sr[r] = fmac(-mi, vi[c], sr[r]);
+            si[r] = fmac(mr, vi[c], si[r]);
+            si[r] = fmac(mi, vr[c], si[r]);
+            sr[c] = fmac(mr, vr[r], sr[c]);
+            sr[c] = fmac(mi, vi[r], sr[c]);
+            si[c] = fmac(mr, vi[r], si[c]);
+            si[c] = fmac(-mi, vr[r], si[c]);
+        }
+#pragma unroll
+    for (int r = 0; r < M; ++r) store_c(out + ro + lay(i, chi * M + r, NC), sr[r], si[r]);
 }
 
 hipError_t launch_clover_mul(int dt, int nr, const Geom &g, const void *bm, const void *in, void *out, int n_rhs,
