@@ -271,6 +271,17 @@ int hrw_cg_solve(const hrw_gauge *g, const hrw_solve_params *params, int n_rhs, 
     });
 }
 
+static int check_bicg_params(const hrw_solve_params *params, int n_rhs)
+{
+    int rc;
+    if ((rc = check_params(params)) || (rc = check_rhs(n_rhs))) return rc;
+    if (params->system != HRW_SYS_DHAT_EO && params->system != HRW_SYS_D_EO)
+        return fail(HRW_EINVAL, "BiCGstab solves HRW_SYS_DHAT_EO or HRW_SYS_D_EO, got system %d", params->system);
+    if (params->inner_dtype != HRW_F64 && params->inner_dtype != HRW_F32)
+        return fail(HRW_EUNSUPPORTED, "BiCGstab runs with FP64 or FP32 inner fields");
+    return HRW_OK;
+}
+
 int hrw_bicgstab_solve(const hrw_gauge *g, const hrw_solve_params *params, int n_rhs, const double *kappa_per_rhs,
                        const double *b, double *x, hrw_solve_result *res, void *workspace, size_t ws_bytes,
                        void *stream)
@@ -278,11 +289,7 @@ int hrw_bicgstab_solve(const hrw_gauge *g, const hrw_solve_params *params, int n
     return guarded([&] {
         int rc;
         if (!g) return fail(HRW_EINVAL, "null gauge");
-        if ((rc = check_params(params)) || (rc = check_rhs(n_rhs))) return rc;
-        if (params->system != HRW_SYS_DHAT_EO && params->system != HRW_SYS_D_EO)
-            return fail(HRW_EINVAL, "BiCGstab solves HRW_SYS_DHAT_EO or HRW_SYS_D_EO, got system %d", params->system);
-        if (params->inner_dtype != HRW_F64 && params->inner_dtype != HRW_F32)
-            return fail(HRW_EUNSUPPORTED, "BiCGstab runs with FP64 or FP32 inner fields");
+        if ((rc = check_bicg_params(params, n_rhs))) return rc;
         if (!kappa_per_rhs || !b || !x || !res || !workspace) return fail(HRW_EINVAL, "null pointer");
         if (b == x) return fail(HRW_EINVAL, "b and x must not overlap");
         if (!g->blocks[0][0]) return fail(HRW_EUNSUPPORTED, "BiCGstab needs FP64 links (HRW_STORE_F64)");
@@ -346,17 +353,6 @@ int hrw_dsw_eo_apply(const hrw_clover *c, const double theta[4], int dtype, int 
         if ((rc = check_clover_apply(c, dtype, n_rhs, in_e, out_e, workspace))) return rc;
         return dsw_eo_apply(c, theta, dtype, n_rhs, dagger, in_e, out_e, workspace, ws_bytes, (hipStream_t)stream);
     });
-}
-
-static int check_bicg_params(const hrw_solve_params *params, int n_rhs)
-{
-    int rc;
-    if ((rc = check_params(params)) || (rc = check_rhs(n_rhs))) return rc;
-    if (params->system != HRW_SYS_DHAT_EO && params->system != HRW_SYS_D_EO)
-        return fail(HRW_EINVAL, "BiCGstab solves HRW_SYS_DHAT_EO or HRW_SYS_D_EO, got system %d", params->system);
-    if (params->inner_dtype != HRW_F64 && params->inner_dtype != HRW_F32)
-        return fail(HRW_EUNSUPPORTED, "BiCGstab runs with FP64 or FP32 inner fields");
-    return HRW_OK;
 }
 
 int hrw_clover_workspace_size(const hrw_clover *c, int n_rhs, const hrw_solve_params *params, size_t *bytes)
