@@ -66,6 +66,7 @@ def _load():
             "orc_cg": (I, [P, I, P, D, P, I, P, P, D, I, P, P, P]),
             "orc_bicgstab": (I, [P, I, P, D, P, I, P, P, D, I, P]),
             "orc_bicgstab_sw": (I, [P, I, P, D, D, P, I, P, P, D, I, P]),
+            "orc_qmr_g5": (I, [P, I, P, D, P, I, P, P, D, I, P]),
             "orc_clover": (I, [P, I, P, D, D, P]),
             "orc_clover_apply": (I, [P, I, P, D, D, I, I, P, P]),
             "orc_dsw": (I, [P, I, P, D, D, P, I, P, P]),
@@ -312,6 +313,19 @@ def solve_d_eo_bicgstab(dims, u_r, kappa, b, theta=None, tol=1e-10, max_iter=100
     xe, info = bicgstab(dims, u_r, kappa, bpe, theta, BICG_EO, tol, max_iter)
     xo = bo + kappa * hop_eo(dims, u_r, xe, 1, theta)
     return merge_eo(dims, xe, xo), info
+
+
+def qmr_g5(dims, u_r, kappa, b, theta=None, system=BICG_EO, tol=1e-10, max_iter=10000):
+    """QMR on the g5-symmetric Lanczos process for D x = b or D_hat x_e = b_e from x = 0
+    (the QMR-g5 inverter of Sec. 3.3).  Returns (x, info) as bicgstab."""
+    u, bb = _c128(u_r), _c128(b)
+    x = np.zeros_like(bb)
+    info = np.zeros(3)
+    rc = _load().orc_qmr_g5(_ptr(_dims(dims)), _nr_of(u), _ptr(u), float(kappa), _ptr(_theta(theta)),
+                            int(system), _ptr(bb), _ptr(x), float(tol), int(max_iter), _ptr(info))
+    _check(rc if rc != -5 else 0, "qmr_g5")
+    return x, {"status": int(rc), "iters": int(info[0]), "true_rel_resid": float(info[1]),
+               "restarts": int(info[2])}
 
 
 # ---------------------------------------------------------------- clover (Sheikholeslami-Wohlert)

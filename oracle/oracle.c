@@ -13,8 +13,8 @@
  *     any N_c and higher representations, with even/odd preconditioning
  *     (Sec. 3.1); the spinor carries ~N_f colour components and the
  *     represented link is an N_f x N_f matrix (Sec. 3.1.2);
- *   - the inverters are CG and BiCGstab (Sec. 3.3); inner products and norms
- *     are global reductions (Sec. 3.2).
+ *   - the inverters are CG, BiCGstab and QMR-g5 (Sec. 3.3); inner products and
+ *     norms are global reductions (Sec. 3.2).
  * The paper prints no formula for D, the gamma basis, the representation
  * bases or the boundary-phase placement; the readings fixed here are:
  *   - Euclidean chiral gamma basis, gamma_5 = g0 g1 g2 g3 = diag(1,1,-1,-1);
@@ -992,6 +992,156 @@ static int bicgstab_run(op_ctx c, const double *b_in, double *x_out, double tol,
     free(v);
     free(s);
     free(t);
+    return status;
+}
+
+/* ------------------------------------------------------------------ QMR-g5 */
+
+/* out = g5 in on n_sites sites (literal 4x4 product with gamma_5) */
+static void g5_apply(long n_sites, int nr, const cplx *in, cplx *out)
+{
+    init_gamma();
+    for (long s = 0; s < n_sites; ++s)
+        for (int al = 0; al < 4; ++al)
+            for (int a = 0; a < nr; ++a) {
+                cplx z = 0;
+                for (int be = 0; be < 4; ++be) z += G[4][al][be] * in[(s * 4 + be) * nr + a];
+                out[(s * 4 + al) * nr + a] = z;
+            }
+}
+
+/* [a, b] = <a, g5 b> = sum conj(a) (g5 b) */
+static cplx g5_dot(long n_sites, int nr, const cplx *a, const cplx *b, cplx *tmp)
+{
+    g5_apply(n_sites, nr, b, tmp);
+    return cdot(n_sites * 4 * nr, a, tmp);
+}
+
+/*
+ * QMR on the g5-symmetric Lanczos process (the QMR-g5 inverter of Sec. 3.3):
+ * D and D_hat satisfy A^+ = g5 A g5, so A is self-adjoint in the indefinite
+ * form [a, b] = <a, g5 b> and the two-sided Lanczos process needs one product
+ * with A per step.  With v_1 = r_0 / |r_0|, delta_n = [v_n, v_n]:
+ *   alpha_n = [v_n, A v_n] / delta_n,   beta_n = rho_n delta_n / delta_{n-1}  (beta_1 = 0)
+ *   w = A v_n - alpha_n v_n - beta_n v_{n-1},  rho_{n+1} = |w|,  v_{n+1} = w / rho_{n+1}
+ * so that A V_n = V_{n+1} T_n with T_n real tridiagonal ((n+1) x n).  The
+ * iterate x_n = x_0 + V_n y_n minimises the quasi-residual |rho_1 e_1 - T_n y|,
+ * updated with Givens rotations and three-term direction vectors; the true
+ * residual satisfies |r_n| <= sqrt(n + 1) |quasi-residual|.  When the
+ * quasi-residual reaches tol |b| (or [v, v] or rho vanishes) the true residual
+ * is recomputed; above tol the process starts again from it.  system 0: D on
+ * the full lattice, 1: D_hat on the even sites.  info as orc_bicgstab.
+ */
+int orc_qmr_g5(const int *dims, int nr, const double *u, double kappa, const double *theta, int system,
+               const double *b_in, double *x_out, double tol, int max_iter, double *info)
+{
+    if (!check_dims(dims, nr) || (system != 0 && system != 1) || !b_in || !x_out) return ORC_EINVAL;
+    if (system == 1 && !even_dims(dims)) return ORC_EINVAL;
+    op_ctx c = {dims, nr, u, kappa, theta, system, NULL, 0.0};
+    const long sites = system == 0 ? vol(dims) : vol(dims) / 2;
+    const long n = sites * 4 * nr;
+    const size_t bytes = sizeof(cplx) * (size_t)n;
+    cplx *x = (cplx *)x_out;
+    cplx *r = (cplx *)malloc(bytes), *v = (cplx *)malloc(bytes), *vp = (cplx *)malloc(bytes),
+         *w = (cplx *)malloc(bytes), *d1 = (cplx *)malloc(bytes), *d2 = (cplx *)malloc(bytes),
+         *tmp = (cplx *)malloc(bytes);
+    const cplx *b = (const cplx *)b_in;
+    memset(x, 0, bytes);
+    memcpy(r, b, bytes);
+    const double bb = norm2(n, b);
+    int it = 0, restarts = 0, status = ORC_NOT_CONVERGED;
+    double rr_true = bb;
+    if (!isfinite(bb)) status = ORC_BREAKDOWN;
+    else if (bb == 0) status = ORC_OK;
+    while (status == ORC_NOT_CONVERGED && it < max_iter) {
+        /* start (or start again) from the residual r */
+        const double rho1 = sqrt(norm2(n, r));
+        for (long i = 0; i < n; ++i) {
+            v[i] = r[i] / rho1;
+            vp[i] = 0;
+            d1[i] = 0;
+            d2[i] = 0;
+        }
+        double delta = creal(g5_dot(sites, nr, v, v, tmp));
+        double beta = 0;
+        double c1 = 1, s1 = 0, c2 = 1, s2 = 0; /* rotations G_{n-1}, G_{n-2} */
+        double tau = rho1;                     /* rotated right-hand side, current row */
+        int check = 0;
+        while (it < max_iter) {
+            if (delta == 0 || !isfinite(delta)) {
+                check = 1;
+                break;
+            }
+            apply_op(&c, v, w);
+            const double alpha = creal(g5_dot(sites, nr, v, w, tmp)) / delta;
+            for (long i = 0; i < n; ++i) w[i] -= alpha * v[i] + beta * vp[i];
+            const double rho_next = sqrt(norm2(n, w));
+            /* column n of T: beta (row n-1), alpha (row n), rho_next (row n+1) */
+            const double e = s2 * beta;
+            const double f0 = c2 * beta;
+            const double f = c1 * f0 + s1 * alpha;
+            const double g0 = -s1 * f0 + c1 * alpha;
+            const double rr = sqrt(g0 * g0 + rho_next * rho_next);
+            const double cn = g0 / rr, sn = rho_next / rr;
+            for (long i = 0; i < n; ++i) {
+                const cplx dn = (v[i] - f * d1[i] - e * d2[i]) / rr;
+                d2[i] = d1[i];
+                d1[i] = dn;
+                x[i] += cn * tau * dn;
+            }
+            tau = -sn * tau;
+            ++it;
+            c2 = c1;
+            s2 = s1;
+            c1 = cn;
+            s1 = sn;
+            if (fabs(tau) * fabs(tau) <= tol * tol * bb || rho_next == 0 || !isfinite(rho_next)) {
+                check = 1;
+                break;
+            }
+            /* next Lanczos vector */
+            for (long i = 0; i < n; ++i) {
+                vp[i] = v[i];
+                v[i] = w[i] / rho_next;
+            }
+            const double delta_next = creal(g5_dot(sites, nr, v, v, tmp));
+            beta = rho_next * delta_next / delta;
+            delta = delta_next;
+        }
+        if (!check) break; /* max_iter */
+        apply_op(&c, x, tmp);
+        for (long i = 0; i < n; ++i) r[i] = b[i] - tmp[i];
+        rr_true = norm2(n, r);
+        if (!isfinite(rr_true)) {
+            status = ORC_BREAKDOWN;
+            break;
+        }
+        if (rr_true <= tol * tol * bb) {
+            status = ORC_OK;
+            break;
+        }
+        if (++restarts > 100) {
+            status = ORC_BREAKDOWN;
+            break;
+        }
+    }
+    if (status == ORC_NOT_CONVERGED) {
+        apply_op(&c, x, tmp);
+        for (long i = 0; i < n; ++i) r[i] = b[i] - tmp[i];
+        rr_true = norm2(n, r);
+    }
+    if (info) {
+        info[0] = it;
+        info[1] = bb > 0 ? sqrt(rr_true / bb) : 0.0;
+        info[2] = restarts;
+    }
+    free(r);
+    free(v);
+    free(vp);
+    free(w);
+    free(d1);
+    free(d2);
+    free(tmp);
     return status;
 }
 

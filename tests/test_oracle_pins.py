@@ -459,6 +459,67 @@ def test_bicgstab_and_cg_solve_the_same_system():
     assert 2 * ib["iters"] < 2 * ic["iters"]
 
 
+# ----------------------------------------------------------------- QMR-g5
+
+def test_qmr_g5_iterates_match_explicit_least_squares():
+    """After n steps the oracle's QMR-g5 iterate equals V_n y with y the least-squares solution of
+    |rho_1 e_1 - T y|, where V is built here independently by g5-Gram-Schmidt of the Krylov vectors
+    b, A b, A^2 b, ... (normalised in the 2-norm) and T = [V_{n+1}, A V_n]_g5 / [v_i, v_i]_g5; and
+    the converged solution equals a dense solve, for D_hat and for D."""
+    dims = (4, 2, 2, 4)
+    ur = _random_setup(dims, 2, "fund", seed=65)
+    kappa, v = 0.13, fx.volume(dims)
+    dhat = dense(lambda f: orc.deo(dims, ur, kappa, f, THETA_AP), v // 2, 2)
+    g5 = np.kron(np.eye(v // 2), np.kron(orc.gamma(4), np.eye(2)))
+    jdot = lambda a, c: np.vdot(a, g5 @ c)
+    be = orc.split_eo(dims, fx.gaussian_spinor(dims, 2, seed=66))[0]
+    b = be.reshape(-1)
+    basis = []
+    k = b.copy()
+    for _ in range(9):
+        w = k.copy()
+        for q in basis:
+            w = w - jdot(q, w) / jdot(q, q) * q
+        basis.append(w / np.linalg.norm(w))
+        k = dhat @ basis[-1]
+    for n in (1, 2, 4, 8):
+        vn = np.stack(basis[:n], axis=1)
+        vn1 = np.stack(basis[:n + 1], axis=1)
+        avn = dhat @ vn
+        t = np.array([[jdot(vn1[:, i], avn[:, j]) / jdot(vn1[:, i], vn1[:, i]) for j in range(n)]
+                      for i in range(n + 1)])
+        rhs = np.zeros(n + 1, complex)
+        rhs[0] = np.linalg.norm(b)
+        y = np.linalg.lstsq(t, rhs, rcond=None)[0]
+        x, info = orc.qmr_g5(dims, ur, kappa, be, THETA_AP, orc.BICG_EO, tol=0.0, max_iter=n)
+        assert info["iters"] == n
+        assert rel(x.reshape(-1), vn @ y) < 1e-10, n
+    x, info = orc.qmr_g5(dims, ur, kappa, be, THETA_AP, orc.BICG_EO, tol=1e-12)
+    assert info["status"] == 0 and rel(x.reshape(-1), np.linalg.solve(dhat, b)) <= np.linalg.cond(dhat) * 1e-12
+    dm = dense(lambda f: orc.dw(dims, ur, kappa, f, THETA_AP), v, 2)
+    bf = fx.gaussian_spinor(dims, 2, seed=67)
+    x, info = orc.qmr_g5(dims, ur, kappa, bf, THETA_AP, orc.BICG_FULL, tol=1e-12)
+    assert info["status"] == 0
+    assert rel(x.reshape(-1), np.linalg.solve(dm, bf.reshape(-1))) <= np.linalg.cond(dm) * 1e-12
+
+
+def test_qmr_g5_special_cases():
+    """kappa = 0: one step returns b; zero and non-finite sources; agreement with BiCGstab."""
+    dims = (4, 4, 2, 4)
+    ur = _random_setup(dims, 3, "fund", seed=68, kind="thermal")
+    be = orc.split_eo(dims, fx.gaussian_spinor(dims, 3, seed=69))[0]
+    x, info = orc.qmr_g5(dims, ur, 0.0, be, THETA_AP)
+    assert info["iters"] == 1 and info["status"] == 0 and rel(x, be) < 1e-15
+    x, info = orc.qmr_g5(dims, ur, 0.12, np.zeros_like(be), THETA_AP)
+    assert info["status"] == 0 and info["iters"] == 0 and not np.abs(x).max()
+    bad = be.copy()
+    bad[0, 0, 0] = np.inf
+    assert orc.qmr_g5(dims, ur, 0.12, bad, THETA_AP)[1]["status"] == -5
+    xq, iq = orc.qmr_g5(dims, ur, 0.135, be, THETA_AP, tol=1e-12)
+    xb, ib = orc.bicgstab(dims, ur, 0.135, be, THETA_AP, tol=1e-12)
+    assert iq["status"] == 0 and rel(xq, xb) < 1e-9
+
+
 # ----------------------------------------------------------------- clover (Sheikholeslami-Wohlert)
 
 def _gauge_transformed(dims, nc, uf, gt):
