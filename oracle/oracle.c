@@ -1027,9 +1027,12 @@ static cplx g5_dot(long n_sites, int nr, const cplx *a, const cplx *b, cplx *tmp
  * so that A V_n = V_{n+1} T_n with T_n real tridiagonal ((n+1) x n).  The
  * iterate x_n = x_0 + V_n y_n minimises the quasi-residual |rho_1 e_1 - T_n y|,
  * updated with Givens rotations and three-term direction vectors; the true
- * residual satisfies |r_n| <= sqrt(n + 1) |quasi-residual|.  When the
- * quasi-residual reaches tol |b| (or [v, v] or rho vanishes) the true residual
- * is recomputed; above tol the process starts again from it.  system 0: D on
+ * residual satisfies |r_n| <= sqrt(k + 1) |quasi-residual| after k steps from
+ * the last start.  When that bound reaches tol |b| (or [v, v] or rho vanishes)
+ * the true residual is recomputed; above tol the process starts again from it.
+ * (Stopping on the quasi-residual alone can stall: a start from a residual at
+ * rounding level has [v, v] near zero, the Lanczos step is then almost empty
+ * and the quasi-residual still passes.)  system 0: D on
  * the full lattice, 1: D_hat on the even sites.  info as orc_bicgstab.
  */
 int orc_qmr_g5(const int *dims, int nr, const double *u, double kappa, const double *theta, int system,
@@ -1066,7 +1069,7 @@ int orc_qmr_g5(const int *dims, int nr, const double *u, double kappa, const dou
         double beta = 0;
         double c1 = 1, s1 = 0, c2 = 1, s2 = 0; /* rotations G_{n-1}, G_{n-2} */
         double tau = rho1;                     /* rotated right-hand side, current row */
-        int check = 0;
+        int check = 0, k = 0;                  /* k: steps since this start */
         while (it < max_iter) {
             if (delta == 0 || !isfinite(delta)) {
                 check = 1;
@@ -1091,11 +1094,12 @@ int orc_qmr_g5(const int *dims, int nr, const double *u, double kappa, const dou
             }
             tau = -sn * tau;
             ++it;
+            ++k;
             c2 = c1;
             s2 = s1;
             c1 = cn;
             s1 = sn;
-            if (fabs(tau) * fabs(tau) <= tol * tol * bb || rho_next == 0 || !isfinite(rho_next)) {
+            if ((k + 1) * tau * tau <= tol * tol * bb || rho_next == 0 || !isfinite(rho_next)) {
                 check = 1;
                 break;
             }

@@ -503,6 +503,17 @@ def test_qmr_g5_iterates_match_explicit_least_squares():
     assert rel(x.reshape(-1), np.linalg.solve(dm, bf.reshape(-1))) <= np.linalg.cond(dm) * 1e-12
 
 
+def test_qmr_g5_stops_on_the_residual_bound():
+    """Regression: stopping on the quasi-residual alone left this system restarting from a residual
+    at rounding level (where [v, v]_g5 is near zero and a step is almost empty) until it gave up;
+    stopping when sqrt(k + 1) times the quasi-residual reaches tol converges without a restart."""
+    dims = (4, 4, 4, 8)
+    ur = orc.rep_map(3, "fund", fx.gauge_field(dims, 3, "thermal", seed=93))
+    be = orc.split_eo(dims, fx.gaussian_spinor(dims, 3, seed=95, n_rhs=3))[0][1]
+    x, info = orc.qmr_g5(dims, ur, 0.125, be, THETA_AP, tol=1e-10)
+    assert info["status"] == 0 and info["restarts"] == 0 and info["true_rel_resid"] <= 1e-10
+
+
 def test_qmr_g5_special_cases():
     """kappa = 0: one step returns b; zero and non-finite sources; agreement with BiCGstab."""
     dims = (4, 4, 2, 4)
