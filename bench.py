@@ -217,6 +217,17 @@ def workload_bicgstab(args):
     rows = bicgstab_rows(torch, hrw, dev, dims, 3, "fund", uf_d, b_d, kappa, theta, 1.0 / per_cg, args.steps,
                          order=("f32", "f64"), timed="f32")
     roof = rows.pop("roofline")
+    # the same request by QMR-g5 (FP64, one D_hat application per iteration)
+    g = hrw.Gauge(dims, 3, "fund", uf_d, dtypes=("f64",))
+    prm_q = hrw.solve_params(tol=WORKLOAD["tol"], max_iter=5000, system="d_eo", theta=theta)
+    _, res_q, per_q, _ = _solve_timed(hrw, torch, g, b_d, kappa, prm_q, max(1, args.steps // 2), 1,
+                                      solver=hrw.qmr_g5_solve)
+    g.close()
+    rows["qmr_g5_f64"] = {"solves_per_s": round(1.0 / per_q, 3), "ms_per_solve": round(per_q * 1e3, 2),
+                          "iters": res_q[0]["iters"], "dhat_applies": res_q[0]["iters"],
+                          "restarts": res_q[0]["restarts"], "true_rel_resid": res_q[0]["true_rel_resid"],
+                          "d_rel_resid": res_q[0]["d_rel_resid"], "vs_fp64_cg": round(per_cg / per_q, 3)}
+    log(f"QMR-g5 f64: {rows['qmr_g5_f64']}")
     cfg = dict(WORKLOAD, workload="su3_fund_32^4_eo_bicgstab_mixed_f32",
                system="D x = b via even/odd Schur complement, BiCGstab on D_hat", inner_dtype="f32",
                reliable_every=50, reliable_delta=1e-3)

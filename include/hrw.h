@@ -246,6 +246,20 @@ int hrw_bicgstab_solve(const hrw_gauge *g, const hrw_solve_params *params, int n
                        const double *kappa_per_rhs, const double *b, double *x, hrw_solve_result *res,
                        void *workspace, size_t ws_bytes, void *stream);
 
+/* QMR on the g5-symmetric Lanczos process (QMR-g5, one of the inverters of
+ * Sec. 3.3) for the same systems as hrw_bicgstab_solve (HRW_SYS_DHAT_EO,
+ * HRW_SYS_D_EO), in FP64 (inner_dtype HRW_F64; others HRW_EUNSUPPORTED).
+ * D_hat^+ = g5 D_hat g5, so the Lanczos process takes one D_hat application
+ * per iteration (res.iters counts them) and its coefficients are real; the
+ * iterate minimises the quasi-residual.  When sqrt(k + 1) x quasi-residual
+ * (k steps since the last start: a bound on the true residual) reaches tol
+ * (or a Lanczos coefficient vanishes) the FP64 true residual is computed;
+ * above tol the process starts again from it (res.restarts).  Workspace:
+ * hrw_workspace_size with the same params (the BiCGstab size covers it). */
+int hrw_qmr_g5_solve(const hrw_gauge *g, const hrw_solve_params *params, int n_rhs, const double *kappa_per_rhs,
+                     const double *b, double *x, hrw_solve_result *res, void *workspace, size_t ws_bytes,
+                     void *stream);
+
 /* ---------------------------------------------------------------- clover term
  * Sheikholeslami-Wohlert improvement (Sec. 3.1): D_sw = A - kappa H with the
  * site-local A(x) = 1 - kappa c_sw sum_{mu<nu} g_mu g_nu (x) F_mu,nu(x), F the

@@ -298,6 +298,22 @@ int hrw_bicgstab_solve(const hrw_gauge *g, const hrw_solve_params *params, int n
     });
 }
 
+int hrw_qmr_g5_solve(const hrw_gauge *g, const hrw_solve_params *params, int n_rhs, const double *kappa_per_rhs,
+                     const double *b, double *x, hrw_solve_result *res, void *workspace, size_t ws_bytes,
+                     void *stream)
+{
+    return guarded([&] {
+        int rc;
+        if (!g) return fail(HRW_EINVAL, "null gauge");
+        if ((rc = check_bicg_params(params, n_rhs))) return rc;
+        if (params->inner_dtype != HRW_F64) return fail(HRW_EUNSUPPORTED, "QMR-g5 runs in FP64");
+        if (!kappa_per_rhs || !b || !x || !res || !workspace) return fail(HRW_EINVAL, "null pointer");
+        if (b == x) return fail(HRW_EINVAL, "b and x must not overlap");
+        if (!g->blocks[0][0]) return fail(HRW_EUNSUPPORTED, "QMR-g5 needs FP64 links (HRW_STORE_F64)");
+        return qmr_g5_solve(g, params, n_rhs, kappa_per_rhs, b, x, res, workspace, ws_bytes, (hipStream_t)stream);
+    });
+}
+
 int hrw_clover_storage_size(const hrw_gauge *g, unsigned storage_mask, size_t *bytes)
 {
     return guarded([&] {

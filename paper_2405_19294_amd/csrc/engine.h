@@ -148,6 +148,8 @@ int bicg_workspace(const Geom &g, int nr, int n_rhs, const hrw_solve_params *p, 
 int bicgstab_solve(const hrw_gauge *g, const hrw_solve_params *p, int n_rhs, const double *kappa,
                    const double *b, double *x, hrw_solve_result *res, void *ws, size_t ws_bytes,
                    hipStream_t st, const hrw_clover *cl = nullptr);
+int qmr_g5_solve(const hrw_gauge *g, const hrw_solve_params *p, int n_rhs, const double *kappa, const double *b,
+                 double *x, hrw_solve_result *res, void *ws, size_t ws_bytes, hipStream_t st);
 int clover_storage_bytes(const hrw_gauge *g, unsigned mask, size_t *bytes);
 int clover_create(const hrw_gauge *g, double kappa, double csw, unsigned mask, void *storage, size_t storage_bytes,
                   hipStream_t st, hrw_clover **out);

@@ -68,6 +68,7 @@ SIGNATURES = {
     "hrw_cg_solve": (I, [P, ctypes.POINTER(SolveParams), I, DP, P, P, ctypes.POINTER(SolveResult), P, SZ, P]),
     "hrw_bicgstab_solve": (I, [P, ctypes.POINTER(SolveParams), I, DP, P, P, ctypes.POINTER(SolveResult), P, SZ,
                                P]),
+    "hrw_qmr_g5_solve": (I, [P, ctypes.POINTER(SolveParams), I, DP, P, P, ctypes.POINTER(SolveResult), P, SZ, P]),
     "hrw_clover_storage_size": (I, [P, ctypes.c_uint, SZP]),
     "hrw_clover_create": (I, [P, D, D, ctypes.c_uint, P, SZ, P, ctypes.POINTER(P)]),
     "hrw_clover_destroy": (I, [P]),
@@ -274,6 +275,21 @@ def deo_apply(g: Gauge, kappa, psi_e: torch.Tensor, theta=(0, 0, 0, 0), dtype="f
 # takes 67 iterations to 1e-10, the 1e-3 trigger the same 51 as plain FP64.
 # The coarser 16-bit formats get correspondingly larger factors.
 RELIABLE_DELTA = {"f64": 0.0, "f32": 1e-3, "f16": 1e-2, "bf16": 1e-1}
+
+
+def qmr_g5_solve(g: Gauge, b: torch.Tensor, kappa, params: SolveParams, x=None, ws: Workspace | None = None,
+                 stream=None):
+    """QMR-g5 for n_rhs stacked systems ("dhat_eo" or "d_eo", FP64); returns (x, results, status)."""
+    n = _n_rhs(b, _system_field(g, params.system))
+    ks = [kappa] * n if isinstance(kappa, (int, float)) else list(kappa)
+    x = torch.empty_like(b) if x is None else x
+    ws = ws or cg_workspace(g, params, n)
+    res = (SolveResult * n)()
+    rc = load().hrw_qmr_g5_solve(g.handle, ctypes.byref(params), n, _doubles(ks), _dev_field(b, "b"),
+                                 _dev_field(x, "x"), res, ws.buf.data_ptr(), ws.nbytes, _stream(stream))
+    if rc < 0 and rc != EBREAKDOWN:
+        _check(rc)
+    return x, [r.as_dict() for r in res], rc
 
 
 class Clover:
