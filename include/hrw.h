@@ -98,8 +98,11 @@ enum hrw_dtype { HRW_F64 = 0, HRW_F32 = 1, HRW_BF16 = 2, HRW_F16 = 3 };
  * the others.  Results agree with the stored-U_R path to rounding (U_R is
  * evaluated in the arithmetic precision of the hop).  Multi-source launches,
  * and 16-bit-storage hops with N_R = 6 (where the extra arithmetic outweighs
- * the saved bytes), keep using the stored U_R.  Sec. 3.1.2 (the represented
- * link is built from the fundamental one). */
+ * the saved bytes), keep using the stored U_R; so on such a field a system's
+ * result depends, at rounding level, on how many systems share its launches
+ * (the batched == single bitwise guarantee of the solvers and sessions holds
+ * only without this flag).  Sec. 3.1.2 (the represented link is built from
+ * the fundamental one). */
 #define HRW_STORE_FUND_HOP (1u << 4)
 
 /* Linear systems: 0-2 for hrw_cg_solve (Hermitian positive definite normal
