@@ -4,8 +4,9 @@ The inputs are the benchmarks' own seeded fields (fixtures); the references come
 either on the whole field (it finishes in seconds at these sizes) or through properties the oracle
 recomputes (the residual of a solve):
   * SU(3) fund 32^4 (default workload): D_hat and D_hat^+ in FP64 to 1e-13, the full-lattice D_W in
-    FP32 within the a-priori bound, and the |b - D x| / |b| of the FP64 CG solve and of the BiCGstab
-    solves (FP64 and FP32 inner) recomputed by the oracle;
+    FP32 within the a-priori bound, and the |b - D x| / |b| of the FP64 CG solve, of the BiCGstab
+    solves (FP64 and FP32 inner) and of the QMR-g5 solve recomputed by the oracle; with the clover
+    term (c_sw = 1), D_hat_sw in FP64 and the FP32-inner BiCGstab solve of D_sw x = b;
   * SU(2) adj and SU(4) asym 24^3x48, with stored U_R and with the representation map fused into the
     hop: D_hat in FP64, and the FP32-inner mixed solve's residual of the even/odd normal equations
     recomputed by the oracle;
@@ -79,6 +80,39 @@ def test_c2_bicgstab_residual_by_oracle(c2_field, inner):
     d_res = rel(orc.dw(C2, ur, KAPPA, x.cpu().numpy(), THETA_AP), b)
     assert abs(d_res - res[0]["d_rel_resid"]) <= 1e-3 * d_res
     assert d_res < 1e-9
+
+
+def test_c2_qmr_g5_residual_by_oracle(c2_field):
+    """The default workload's system solved by QMR-g5 (FP64): |b - D x| / |b| recomputed by the oracle."""
+    ur, g = c2_field
+    b = fx.gaussian_spinor(C2, 3, seed=3)
+    prm = hrw.solve_params(tol=1e-10, max_iter=5000, system="d_eo", theta=THETA_AP)
+    x, res, rc = hrw.qmr_g5_solve(g, to_dev(b), KAPPA, prm)
+    assert rc == 0 and res[0]["true_rel_resid"] <= 1e-10
+    d_res = rel(orc.dw(C2, ur, KAPPA, x.cpu().numpy(), THETA_AP), b)
+    assert abs(d_res - res[0]["d_rel_resid"]) <= 1e-3 * d_res
+    assert d_res < 1e-9
+
+
+def test_c2_clover_full_size(c2_field):
+    """The clover workload (c_sw = 1): D_hat_sw in FP64 against the oracle, and the FP32-inner BiCGstab
+    solve of D_sw x = b with |b - D_sw x| / |b| recomputed by the oracle."""
+    ur, g = c2_field
+    c = hrw.Clover(g, KAPPA, 1.0, dtypes=("f64", "f32"))
+    try:
+        pe = _even(C2, fx.gaussian_spinor(C2, 3, seed=5))
+        fp64_close(hrw.dsw_eo_apply(c, to_dev(pe), THETA_AP, "f64").cpu().numpy(),
+                   orc.dsw_eo(C2, ur, KAPPA, 1.0, pe, THETA_AP))
+        b = fx.gaussian_spinor(C2, 3, seed=3)
+        prm = hrw.solve_params(tol=1e-10, max_iter=5000, system="d_eo", inner_dtype="f32", theta=THETA_AP,
+                               reliable_delta=hrw.RELIABLE_DELTA["f32"])
+        x, res, rc = hrw.clover_bicgstab_solve(c, to_dev(b), prm)
+        assert rc == 0 and res[0]["true_rel_resid"] <= 1e-10
+        d_res = rel(orc.dsw(C2, ur, KAPPA, 1.0, x.cpu().numpy(), THETA_AP), b)
+        assert abs(d_res - res[0]["d_rel_resid"]) <= 1e-3 * d_res
+        assert d_res < 1e-9
+    finally:
+        c.close()
 
 
 @pytest.mark.parametrize("fused", [False, True], ids=["stored_links", "fused_rep_map"])
