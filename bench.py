@@ -198,9 +198,10 @@ def main():
 
 
 def workload_bicgstab(args):
-    """The default workload's request solved by BiCGstab on D_hat (FP32 inner fields with FP64
-    reliable updates as the line's value, plain FP64 beside it), against FP64 CG on the normal
-    equations; the roofline is that of the hopping kernel inside the mixed solves."""
+    """The default workload's request solved by BiCGstab on D_hat (BF16 inner storage with FP32
+    arithmetic and FP64 reliable updates as the line's value; FP32 inner and plain FP64 beside it),
+    against FP64 CG on the normal equations; the roofline is that of the hopping kernel inside the
+    BF16-inner solves."""
     import torch
 
     import fixtures as fx
@@ -215,7 +216,7 @@ def workload_bicgstab(args):
     _, _, per_cg, _ = _solve_timed(hrw, torch, g, b_d, kappa, prm, max(1, args.steps // 2), 1)
     g.close()
     rows = bicgstab_rows(torch, hrw, dev, dims, 3, "fund", uf_d, b_d, kappa, theta, 1.0 / per_cg, args.steps,
-                         order=("f32", "f64"), timed="f32")
+                         order=("bf16", "f32", "f64"), timed="bf16")
     roof = rows.pop("roofline")
     # the same request by QMR-g5 (FP64, one D_hat application per iteration)
     g = hrw.Gauge(dims, 3, "fund", uf_d, dtypes=("f64",))
@@ -228,11 +229,12 @@ def workload_bicgstab(args):
                           "restarts": res_q[0]["restarts"], "true_rel_resid": res_q[0]["true_rel_resid"],
                           "d_rel_resid": res_q[0]["d_rel_resid"], "vs_fp64_cg": round(per_cg / per_q, 3)}
     log(f"QMR-g5 f64: {rows['qmr_g5_f64']}")
-    cfg = dict(WORKLOAD, workload="su3_fund_32^4_eo_bicgstab_mixed_f32",
-               system="D x = b via even/odd Schur complement, BiCGstab on D_hat", inner_dtype="f32",
-               reliable_every=50, reliable_delta=1e-3)
-    m = rows["f32"]
-    return _line(m["solves_per_s"], "solves/s", args.steps, 1, m["ms_per_solve"], "f32", cfg, roof,
+    cfg = dict(WORKLOAD, workload="su3_fund_32^4_eo_bicgstab_mixed_bf16",
+               system="D x = b via even/odd Schur complement, BiCGstab on D_hat",
+               inner_dtype="bf16 storage, f32 arithmetic", reliable_every=50,
+               reliable_delta=hrw.RELIABLE_DELTA["bf16"])
+    m = rows["bf16"]
+    return _line(m["solves_per_s"], "solves/s", args.steps, 1, m["ms_per_solve"], "bf16", cfg, roof,
                  bicgstab=rows, fp64_cg_solves_per_s=round(1.0 / per_cg, 3))
 
 
@@ -321,11 +323,11 @@ def bicgstab_rows(torch, hrw, dev, dims, nc, rep, uf_d, b_d, kappa, theta, cg_va
                   order=("f64", "f32"), timed=None):
     """The same request (D x = b through the even/odd Schur complement, |b'_e - D_hat x_e| <= 1e-10
     |b'_e| in FP64) solved by BiCGstab on D_hat itself: plain FP64, and FP32 inner fields with FP64
-    reliable updates.  A step is the whole request as in the main line (gauge field built, solve,
+    reliable updates (BF16 storage with FP32 arithmetic likewise).  A step is the whole request as in the main line (gauge field built, solve,
     reconstruction, |b - D x|); solves/s beside CG's."""
     rows = {}
     for inner in order:
-        dtypes = ("f64",) if inner == "f64" else ("f64", "f32")
+        dtypes = ("f64",) if inner == "f64" else ("f64", inner)
         prm = hrw.solve_params(tol=WORKLOAD["tol"], max_iter=5000, system="d_eo", inner_dtype=inner, theta=theta,
                                reliable_delta=hrw.RELIABLE_DELTA[inner])
         ws = hrw.Workspace(hrw.workspace_size(dims, nc, rep, 1, prm), dev)
@@ -349,7 +351,9 @@ def bicgstab_rows(torch, hrw, dev, dims, nc, rep, uf_d, b_d, kappa, theta, cg_va
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         if timed == inner:
-            rows["roofline"] = _hop_roofline(hrw, "hop_kernel<N_R=3, RS=3, float> (the class also holds the few FP64 launches of the reliable updates)")
+            kt = {"f64": "double", "f32": "float", "bf16": "bf16"}[inner]
+            extra = "" if inner == "f64" else " (the class also holds the few FP64 launches of the reliable updates)"
+            rows["roofline"] = _hop_roofline(hrw, f"hop_kernel<N_R=3, RS=3, {kt}>{extra}")
             hrw.timing_enable(False)
         rows[inner] = {"solves_per_s": round(steps / el, 3), "ms_per_solve": round(el / steps * 1e3, 2),
                        "iters": r["iters"], "dhat_applies": 2 * r["iters"],

@@ -237,14 +237,15 @@ int hrw_cg_solve(const hrw_gauge *g, const hrw_solve_params *params, int n_rhs,
  * starting residual is the shadow vector, and each system stops on its FP64
  * true relative residual |b_e - D_hat x_e| / |b_e| <= tol.  inner_dtype
  * HRW_F64 runs plain FP64 (the true residual is checked at recursive
- * convergence; above tol the iteration starts again from it); HRW_F32 runs
- * the recurrences on FP32 fields with FP64 reliable updates (reliable_every,
+ * convergence; above tol the iteration starts again from it); HRW_F32 (or
+ * HRW_BF16: BF16 storage, FP32 arithmetic) runs the recurrences on the
+ * low-precision fields with FP64 reliable updates (reliable_every,
  * reliable_delta, and at recursive convergence), the solution accumulating in
  * FP64.  A vanished coefficient (rho, <r0, D_hat p> or omega) also starts
  * again; more than 100 new starts end as HRW_EBREAKDOWN.  res.iters counts
  * BiCGstab iterations (two D_hat applications each).  Workspace:
  * hrw_workspace_size with the same params.  Returns as hrw_cg_solve;
- * EUNSUPPORTED for 16-bit inner storage, EINVAL for systems 0-2. */
+ * EUNSUPPORTED for FP16 inner storage, EINVAL for systems 0-2. */
 int hrw_bicgstab_solve(const hrw_gauge *g, const hrw_solve_params *params, int n_rhs,
                        const double *kappa_per_rhs, const double *b, double *x, hrw_solve_result *res,
                        void *workspace, size_t ws_bytes, void *stream);

@@ -11,8 +11,9 @@
 // host-mapped flags two iterations behind the launches, and systems that are
 // not iterating skipped by every hop and vector kernel.
 //
-// Mixed precision (inner FP32): the recurrences run on FP32 fields while the
-// solution accumulates in FP64.  Every `reliable_every` iterations, when |r|
+// Mixed precision (inner FP32, or BF16 storage with FP32 arithmetic): the
+// recurrences run on the low-precision fields while the solution accumulates
+// in FP64.  Every `reliable_every` iterations, when |r|
 // fell by `reliable_delta` since the last update, or at recursive
 // convergence, the inner solution is folded into the FP64 one and the FP64
 // true residual b - D_hat x replaces the recursive residual; rho is then
@@ -241,10 +242,12 @@ __global__ void __launch_bounds__(WG) bi_xr_kernel(cpx<S> *__restrict__ x, cpx<S
         xi += (ar * pi + ai * pr) + (wr * si + wi * sr);
         const A nr = sr - (wr * tr - wi * ti), ni = si - (wr * ti + wi * tr);
         store_c(x + o + e, xr, xi);
-        store_c(r + o + e, nr, ni);  // S is double or float: stored exactly as computed
-        nn += (double)nr * nr + (double)ni * ni;
-        dr += (double)hr * nr + (double)hi * ni;
-        di += (double)hr * ni - (double)hi * nr;
+        store_c(r + o + e, nr, ni);
+        // the partials see the stored residual (rounded for 16-bit storage)
+        const A qr = conv<S>::to_acc(conv<S>::from_acc(nr)), qi = conv<S>::to_acc(conv<S>::from_acc(ni));
+        nn += (double)qr * qr + (double)qi * qi;
+        dr += (double)hr * qr + (double)hi * qi;
+        di += (double)hr * qi - (double)hi * qr;
     }
     const double a = wg_sum(nn, sh), b = wg_sum(dr, sh), c = wg_sum(di, sh);
     if (threadIdx.x == 0) {
@@ -897,11 +900,12 @@ int bicgstab_solve(const hrw_gauge *g, const hrw_solve_params *prm, int n_rhs, c
     HRW_HIP(hipStreamSynchronize(st));
     bool ok = dispatch_dtype(P.dl, [&](auto sv) {
         typedef decltype(sv) S;
-        if constexpr (std::is_same<S, double>::value || std::is_same<S, float>::value) {
+        if constexpr (std::is_same<S, double>::value || std::is_same<S, float>::value ||
+                      std::is_same<S, bf16_t>::value) {
             rc = bi_run<S>(R, prm, hf, ev);
             if (!rc) rc = bi_finish<S>(R, x_out, res, t0);
         } else {
-            rc = fail(HRW_EUNSUPPORTED, "BiCGstab runs with FP64 or FP32 inner fields");
+            rc = fail(HRW_EUNSUPPORTED, "BiCGstab runs with FP64, FP32 or BF16 inner fields");
         }
     });
     if (!ok) return fail(HRW_EINVAL, "bad inner dtype");

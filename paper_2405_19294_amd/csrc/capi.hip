@@ -277,8 +277,8 @@ static int check_bicg_params(const hrw_solve_params *params, int n_rhs)
     if ((rc = check_params(params)) || (rc = check_rhs(n_rhs))) return rc;
     if (params->system != HRW_SYS_DHAT_EO && params->system != HRW_SYS_D_EO)
         return fail(HRW_EINVAL, "BiCGstab solves HRW_SYS_DHAT_EO or HRW_SYS_D_EO, got system %d", params->system);
-    if (params->inner_dtype != HRW_F64 && params->inner_dtype != HRW_F32)
-        return fail(HRW_EUNSUPPORTED, "BiCGstab runs with FP64 or FP32 inner fields");
+    if (params->inner_dtype == HRW_F16)
+        return fail(HRW_EUNSUPPORTED, "BiCGstab runs with FP64, FP32 or BF16 inner fields");
     return HRW_OK;
 }
 
@@ -391,6 +391,7 @@ int hrw_clover_bicgstab_solve(const hrw_clover *c, const hrw_solve_params *param
         if (!b || !x || !res || !workspace) return fail(HRW_EINVAL, "null pointer");
         if (b == x) return fail(HRW_EINVAL, "b and x must not overlap");
         const int dl = params->inner_dtype;
+        if (dl > HRW_F32) return fail(HRW_EUNSUPPORTED, "clover BiCGstab runs with FP64 or FP32 inner fields");
         if (!c->g->blocks[dl][0] || !c->a[dl][0] || !c->a[0][0])
             return fail(HRW_EUNSUPPORTED, "links and clover blocks needed in FP64 and in the inner dtype");
         double k[MAX_RHS];

@@ -9,6 +9,9 @@ Tolerances (the solution is unique, so every correct solver meets them):
   * plain FP64 iteration counts within 5 % (+2) of the oracle's (the two
     reduce in different orders, so the paths part at rounding level);
   * several right-hand sides in one call give bitwise the single-system results.
+BF16 inner storage (FP32 arithmetic, FP64 reliable updates every tenfold drop)
+is held to the same FP64 tolerances: the reliable updates make the final
+residual an FP64 one whatever the inner precision.
 """
 
 import numpy as np
@@ -48,10 +51,10 @@ def dhat_resid(dims, ur, kappa, x, b, theta):
 
 
 @pytest.mark.parametrize("case", CASES, ids=ids)
-@pytest.mark.parametrize("inner", ["f64", "f32"])
+@pytest.mark.parametrize("inner", ["f64", "f32", "bf16"])
 def test_bicgstab_dhat_matches_oracle(case, inner):
     dims, nc, rep, kappa = case
-    uf, ur, g = setup(dims, nc, rep, "thermal", seed=81, dtypes=("f64", "f32"))
+    uf, ur, g = setup(dims, nc, rep, "thermal", seed=81, dtypes=tuple(dict.fromkeys(("f64", inner))))
     be = orc.split_eo(dims, fx.gaussian_spinor(dims, g.nr, seed=82))[0]
     prm = hrw.solve_params(tol=1e-10, system="dhat_eo", inner_dtype=inner, theta=THETA_AP,
                            reliable_delta=hrw.RELIABLE_DELTA[inner])
@@ -71,12 +74,12 @@ def test_bicgstab_dhat_matches_oracle(case, inner):
         assert res[0]["reliable_updates"] >= 1
 
 
-@pytest.mark.parametrize("inner", ["f64", "f32"])
+@pytest.mark.parametrize("inner", ["f64", "f32", "bf16"])
 def test_bicgstab_full_system_through_schur(inner):
     """D x = b (system d_eo): |b - D x| / |b| recomputed by the oracle equals the reported
     d_rel_resid, and x matches the oracle's BiCGstab route and its CG route."""
     dims, kappa = (4, 4, 4, 8), 0.13
-    uf, ur, g = setup(dims, 3, "fund", "thermal", seed=83, dtypes=("f64", "f32"))
+    uf, ur, g = setup(dims, 3, "fund", "thermal", seed=83, dtypes=("f64", "f32", "bf16"))
     b = fx.gaussian_spinor(dims, 3, seed=84)
     prm = hrw.solve_params(tol=1e-10, system="d_eo", inner_dtype=inner, theta=THETA_TW,
                            reliable_delta=hrw.RELIABLE_DELTA[inner])
@@ -94,10 +97,10 @@ def test_bicgstab_full_system_through_schur(inner):
 
 def test_bicgstab_multi_rhs_bitwise_equals_single():
     dims = (4, 4, 4, 4)
-    uf, ur, g = setup(dims, 3, "fund", "thermal", seed=85, dtypes=("f64", "f32"))
+    uf, ur, g = setup(dims, 3, "fund", "thermal", seed=85, dtypes=("f64", "f32", "bf16"))
     b = orc.split_eo(dims, fx.gaussian_spinor(dims, 3, seed=86, n_rhs=4))[0]
     ks = [0.12, 0.125, 0.13, 0.135]
-    for inner in ("f64", "f32"):
+    for inner in ("f64", "f32", "bf16"):
         prm = hrw.solve_params(tol=1e-10, system="dhat_eo", inner_dtype=inner, theta=THETA_AP,
                                reliable_delta=hrw.RELIABLE_DELTA[inner])
         xm, resm, rc = hrw.bicgstab_solve(g, to_dev(b), ks, prm)
@@ -144,7 +147,7 @@ def test_bicgstab_edge_cases():
     x, res, rc = hrw.bicgstab_solve(g, to_dev(np.stack([b, nan])), [0.12, 0.12], prm)
     assert rc == hrw.EBREAKDOWN and res[0]["status"] == 0 and res[1]["status"] == hrw.EBREAKDOWN
     assert dhat_resid(dims, ur, 0.12, x[0].cpu().numpy(), b, THETA_AP) <= 1.01e-10
-    # systems 0-2 are CG's; 16-bit inner storage is not offered
+    # systems 0-2 are CG's; FP16 inner storage is not offered
     with pytest.raises(hrw.HrwError) as e:
         hrw.bicgstab_solve(g, to_dev(b), 0.12, hrw.solve_params(system="ddag_d_eo"))
     assert e.value.code == hrw.EINVAL
@@ -152,5 +155,5 @@ def test_bicgstab_edge_cases():
         hrw.cg_solve(g, to_dev(b), 0.12, hrw.solve_params(system="dhat_eo"))
     assert e.value.code == hrw.EINVAL
     with pytest.raises(hrw.HrwError) as e:
-        hrw.bicgstab_solve(g, to_dev(b), 0.12, hrw.solve_params(system="dhat_eo", inner_dtype="bf16"))
+        hrw.bicgstab_solve(g, to_dev(b), 0.12, hrw.solve_params(system="dhat_eo", inner_dtype="f16"))
     assert e.value.code == hrw.EUNSUPPORTED
