@@ -51,6 +51,7 @@ WORKLOAD = {
     "system": "D x = b via even/odd Schur complement, CG on its normal equations",
     "inner_dtype": "f64",
     "tol": 1e-10,
+    "links": "SU(3) two-row: the hops read two rows of each link and rebuild the third",
 }
 
 
@@ -113,7 +114,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step():
-        g = hrw.Gauge(dims, nc, rep, uf_d, dtypes=("f64",))
+        g = hrw.Gauge(dims, nc, rep, uf_d, dtypes=("f64",), two_rows=True)
         x, res, rc = hrw.cg_solve(g, b_d, kappa, prm, x=x_d, ws=ws)
         g.close()
         if rc != 0:
@@ -150,10 +151,10 @@ def main():
     # with the current kernel sources (None otherwise)
     from paper_2405_19294_amd import profsum
     epi_tag = {"hop_plain": ", 0>", "hop_axpy": ", 1>", "hop_cg": ", 2>"}[dom_name]
-    traffic = profsum.traffic_for("hop_kernel<3, 3, double, false" + epi_tag, TRAFFIC_RECORD)
+    traffic = profsum.traffic_for("hop_su3_kernel<double, false" + epi_tag, TRAFFIC_RECORD)
     roofline = {
         "bound": "hbm",
-        "kernel": f"hop_kernel<N_R=3, RS=3, double, {dom_name[4:]} epilogue>",
+        "kernel": f"hop_su3_kernel<double, {dom_name[4:]} epilogue> (two rows of each link read, third rebuilt)",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
@@ -187,6 +188,8 @@ def main():
         "solve": {"iters": r["iters"], "true_rel_resid": r["true_rel_resid"], "d_rel_resid": r["d_rel_resid"]},
     }
 
+    out["stored_links"] = stored_link_row(torch, hrw, dims, nc, rep, uf_d, b_d, kappa, prm, ws, x_d, out["value"],
+                                          max(2, min(args.steps, 5)))
     out["hbm_copy_reference"] = copy_reference(torch, dev)
     out["operators"] = operator_table(torch, hrw, dev, dims, nc, rep, uf_d, kappa, theta,
                                       out["hbm_copy_reference"]["gbs"])
@@ -212,14 +215,14 @@ def workload_bicgstab(args):
     uf_d = torch.from_numpy(fx.gauge_field(dims, 3, "thermal", seed=2, eps=0.3)).to(dev)
     b_d = torch.from_numpy(fx.gaussian_spinor(dims, 3, seed=3)).to(dev)
     prm = hrw.solve_params(tol=WORKLOAD["tol"], max_iter=5000, system="d_cgnr_eo", inner_dtype="f64", theta=theta)
-    g = hrw.Gauge(dims, 3, "fund", uf_d, dtypes=("f64",))
+    g = hrw.Gauge(dims, 3, "fund", uf_d, dtypes=("f64",), two_rows=True)
     _, _, per_cg, _ = _solve_timed(hrw, torch, g, b_d, kappa, prm, max(1, args.steps // 2), 1)
     g.close()
     rows = bicgstab_rows(torch, hrw, dev, dims, 3, "fund", uf_d, b_d, kappa, theta, 1.0 / per_cg, args.steps,
                          order=("bf16", "f32", "f64"), timed="bf16")
     roof = rows.pop("roofline")
     # the same request by QMR-g5 (FP64, one D_hat application per iteration)
-    g = hrw.Gauge(dims, 3, "fund", uf_d, dtypes=("f64",))
+    g = hrw.Gauge(dims, 3, "fund", uf_d, dtypes=("f64",), two_rows=True)
     prm_q = hrw.solve_params(tol=WORKLOAD["tol"], max_iter=5000, system="d_eo", theta=theta)
     _, res_q, per_q, _ = _solve_timed(hrw, torch, g, b_d, kappa, prm_q, max(1, args.steps // 2), 1,
                                       solver=hrw.qmr_g5_solve)
@@ -312,15 +315,44 @@ def workload_clover(args):
     g.close()
     cfg = dict(WORKLOAD, workload="su3_fund_32^4_clover_eo_bicgstab_mixed_f32", c_sw=csw,
                system="D_sw x = b via even/odd Schur complement (A_ee - kappa^2 H_eo A_oo^-1 H_oe), BiCGstab",
-               inner_dtype="f32", reliable_every=50, reliable_delta=1e-3)
+               inner_dtype="f32", reliable_every=50, reliable_delta=1e-3,
+               links="stored: the hops read all three rows of each link")
     m = rows["f32"]
     return _line(m["solves_per_s"], "solves/s", args.steps, 1, m["ms_per_solve"], "f32", cfg, roof,
                  clover_setup_ms=round(setup_ms, 1), operators=ops, bicgstab=rows,
                  without_clover_f32={"solves_per_s": round(1.0 / per0, 3), "iters": res0[0]["iters"]})
 
 
+def stored_link_row(torch, hrw, dims, nc, rep, uf_d, b_d, kappa, prm, ws, x_d, two_row_value, steps):
+    """The same FP64 CG request with the hops reading all three stored rows of each link (the
+    paper's full-link storage), beside the line's two-row solve."""
+    def step():
+        g = hrw.Gauge(dims, nc, rep, uf_d, dtypes=("f64",))
+        x, res, rc = hrw.cg_solve(g, b_d, kappa, prm, x=x_d, ws=ws)
+        g.close()
+        if rc != 0:
+            raise RuntimeError(f"stored-link solve failed: {res}")
+        return res[0]
+
+    step()
+    torch.cuda.synchronize()
+    hrw.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    roof = _hop_roofline(hrw, "hop_kernel<N_R=3, RS=3, double> (all three rows read)")
+    hrw.timing_enable(False)
+    row = {"solves_per_s": round(steps / el, 3), "ms_per_solve": round(el / steps * 1e3, 2), "iters": r["iters"],
+           "true_rel_resid": r["true_rel_resid"], "d_rel_resid": r["d_rel_resid"],
+           "two_row_speedup": round(two_row_value / (steps / el), 3), "steps": steps, "hop_roofline": roof}
+    log(f"FP64 CG, stored links (three rows): {row}")
+    return row
+
+
 def bicgstab_rows(torch, hrw, dev, dims, nc, rep, uf_d, b_d, kappa, theta, cg_value, steps,
-                  order=("f64", "f32"), timed=None):
+                  order=("f64", "f32"), timed=None, two_rows=True):
     """The same request (D x = b through the even/odd Schur complement, |b'_e - D_hat x_e| <= 1e-10
     |b'_e| in FP64) solved by BiCGstab on D_hat itself: plain FP64, and FP32 inner fields with FP64
     reliable updates (BF16 storage with FP32 arithmetic likewise).  A step is the whole request as in the main line (gauge field built, solve,
@@ -334,7 +366,7 @@ def bicgstab_rows(torch, hrw, dev, dims, nc, rep, uf_d, b_d, kappa, theta, cg_va
         x_d = torch.empty_like(b_d)
 
         def step():
-            g = hrw.Gauge(dims, nc, rep, uf_d, dtypes=dtypes)
+            g = hrw.Gauge(dims, nc, rep, uf_d, dtypes=dtypes, two_rows=two_rows)
             x, res, rc = hrw.bicgstab_solve(g, b_d, kappa, prm, x=x_d, ws=ws)
             g.close()
             if rc != 0:
@@ -353,7 +385,8 @@ def bicgstab_rows(torch, hrw, dev, dims, nc, rep, uf_d, b_d, kappa, theta, cg_va
         if timed == inner:
             kt = {"f64": "double", "f32": "float", "bf16": "bf16"}[inner]
             extra = "" if inner == "f64" else " (the class also holds the few FP64 launches of the reliable updates)"
-            rows["roofline"] = _hop_roofline(hrw, f"hop_kernel<N_R=3, RS=3, {kt}>{extra}")
+            name = f"hop_su3_kernel<{kt}> (two rows of each link read)" if two_rows else f"hop_kernel<N_R=3, RS=3, {kt}>"
+            rows["roofline"] = _hop_roofline(hrw, name + extra)
             hrw.timing_enable(False)
         rows[inner] = {"solves_per_s": round(steps / el, 3), "ms_per_solve": round(el / steps * 1e3, 2),
                        "iters": r["iters"], "dhat_applies": 2 * r["iters"],

@@ -105,6 +105,19 @@ enum hrw_dtype { HRW_F64 = 0, HRW_F32 = 1, HRW_BF16 = 2, HRW_F16 = 3 };
  * the fundamental one). */
 #define HRW_STORE_FUND_HOP (1u << 4)
 
+/* Storage flag for SU(3) fundamental fields: the caller asserts that every
+ * link is special unitary (to the working precision), and single-source hops
+ * then read only the first two rows of each link and rebuild the third as
+ * conj(u_0 x u_1), 2/3 of the link bytes (the classic two-row compression of
+ * SU(3) links; the paper stores full links, Sec. 3.1).  The storage itself is
+ * unchanged and keeps all three rows; a link that is not special unitary
+ * enters the hops through its rebuilt row, so any deviation from SU(3) goes
+ * straight into the result.  Multi-source launches read the stored rows.
+ * hrw_gauge_create returns HRW_EUNSUPPORTED for other groups or
+ * representations.  Single-source and batched results differ at rounding
+ * level, as for HRW_STORE_FUND_HOP. */
+#define HRW_STORE_SU3_TWO_ROWS (1u << 5)
+
 /* Linear systems: 0-2 for hrw_cg_solve (Hermitian positive definite normal
  * equations), 3-4 for hrw_bicgstab_solve (the operator itself). */
 enum hrw_system {

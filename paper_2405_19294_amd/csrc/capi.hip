@@ -57,9 +57,11 @@ int check_dtype(int dt)
 
 int check_storage_mask(int nc, int rep, unsigned mask)
 {
-    if (!(mask & 0xf) || (mask & ~0x1fu)) return fail(HRW_EINVAL, "bad storage mask 0x%x", mask);
+    if (!(mask & 0xf) || (mask & ~0x3fu)) return fail(HRW_EINVAL, "bad storage mask 0x%x", mask);
     if ((mask & HRW_STORE_FUND_HOP) && !hop_fused_supported(nc, rep))
         return fail(HRW_EUNSUPPORTED, "the fused representation map is built for SU(2) adj/sym, SU(3) sym, SU(4) asym");
+    if ((mask & HRW_STORE_SU3_TWO_ROWS) && !(nc == 3 && rep == HRW_REP_FUND))
+        return fail(HRW_EUNSUPPORTED, "two-row links are for SU(3) fundamental fields");
     return HRW_OK;
 }
 

@@ -92,7 +92,8 @@ struct Phases {
 Phases make_phases(const double theta[4]);
 
 // algorithmic bytes of one hop launch (min-traffic model)
-double hop_bytes(const Geom &g, int nr, int dt, int parity, int epi, int n_rhs, int fused_nc = 0);
+double hop_bytes(const Geom &g, int nr, int dt, int parity, int epi, int n_rhs, int fused_nc = 0,
+                 bool two_rows = false);
 
 // generic hop launch with timing, dtype-erased pointers
 struct HopCall {

@@ -113,12 +113,13 @@ Phases make_phases(const double theta[4])
     return p;
 }
 
-double hop_bytes(const Geom &g, int nr, int dt, int parity, int epi, int n_rhs, int fused_nc)
+double hop_bytes(const Geom &g, int nr, int dt, int parity, int epi, int n_rhs, int fused_nc, bool two_rows)
 {
     const double sites = (double)g.half * (parity < 0 ? 2 : 1);
     const double cb = (double)dtype_cbytes(dt);
-    // the fused representation map streams the N x N fundamental links
-    const double links = 8.0 * (fused_nc ? fused_nc * fused_nc : nr * nr) * cb;
+    // the fused representation map streams the N x N fundamental links; the
+    // SU(3) two-row hop reads 6 of the 9 entries of each link
+    const double links = 8.0 * (fused_nc ? fused_nc * fused_nc : two_rows ? 6 : nr * nr) * cb;
     const double sp = 4.0 * nr * cb;
     double per = sp;  // neighbour spinors (each input spinor once)
     if (epi == EPI_PLAIN) per += sp;            // out
@@ -136,6 +137,8 @@ int run_hop(const hrw_gauge *g, const Phases &ph, const HopCall &c, hipStream_t 
     // the multi-source kernel keeps its LDS copy of the stored U_R
     const int fused_nc =
         (g->fblocks[c.dt][0] && hop_fused_pays(g->nr, c.dt) && !hop_uses_mrhs(g->nr, c.dt, c.n_rhs)) ? g->nc : 0;
+    // SU(3) fundamental fields flagged special unitary: single-source hops read two rows per link
+    const bool two_rows = !fused_nc && (g->mask & HRW_STORE_SU3_TWO_ROWS) && !hop_uses_mrhs(g->nr, c.dt, c.n_rhs);
     hipEvent_t ev;
     const bool tm = timed_begin(st, &ev);
     hipError_t err = hipErrorInvalidValue;
@@ -166,13 +169,14 @@ int run_hop(const hrw_gauge *g, const Phases &ph, const HopCall &c, hipStream_t 
         a.run = c.run;
         a.partial = c.partial;
         a.pstride = c.pstride;
-        err = fused_nc ? launch_hop_fused<S>(g->nc, g->rep, c.dagger, c.epi, a, st)
-                       : launch_hop<S>(g->nr, c.dagger, c.epi, a, st);
+        err = fused_nc   ? launch_hop_fused<S>(g->nc, g->rep, c.dagger, c.epi, a, st)
+              : two_rows ? launch_hop_su3<S>(c.dagger, c.epi, a, st)
+                         : launch_hop<S>(g->nr, c.dagger, c.epi, a, st);
     });
     if (err != hipSuccess) return fail(HRW_EDEVICE, "hop launch failed: %s", hipGetErrorString(err));
     if (tm)
         timed_end(st, ev, KC_HOP, KC_HOP_PLAIN + c.epi,
-                  hop_bytes(g->g, g->nr, c.dt, c.parity, c.epi, c.n_rhs, fused_nc));
+                  hop_bytes(g->g, g->nr, c.dt, c.parity, c.epi, c.n_rhs, fused_nc, two_rows));
     return HRW_OK;
 }
 

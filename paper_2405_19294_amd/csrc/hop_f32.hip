@@ -14,4 +14,9 @@ hipError_t launch_hop_fused<float>(int nc, int rep, bool dagger, int epi, const 
 {
     return launch_hop_fused_impl<float>(nc, rep, dagger, epi, a, st);
 }
+template <>
+hipError_t launch_hop_su3<float>(bool dagger, int epi, const HopArgs<float> &a, hipStream_t st)
+{
+    return launch_hop_su3_impl<float>(dagger, epi, a, st);
+}
 }  // namespace hrw

@@ -149,12 +149,34 @@ struct GlobalLinks {
     static constexpr bool REAL = false;
     static constexpr int NF = 1;
     static constexpr int REPID = 0;
+    static constexpr bool RECON = false;
     const cpx<S> *__restrict__ g;
     int i;
     __device__ __forceinline__ void load(int comp, typename acc_of<S>::type &re,
                                          typename acc_of<S>::type &im) const
     {
         load_c_nt(g + lay(i, comp, 8 * NR * NR), re, im);
+    }
+};
+
+// SU(3) fundamental links in HBM of which only the first two rows are read:
+// the rows of a special unitary 3 x 3 matrix satisfy u_2 = conj(u_0 x u_1),
+// so the third row is rebuilt in registers and 2/3 of the link bytes cross
+// HBM.  The stored blocks keep all three rows (other kernels read them).
+template <class S>
+struct Su3Links {
+    static constexpr bool ROWWISE = false;
+    static constexpr bool FUSED = false;
+    static constexpr bool REAL = false;
+    static constexpr int NF = 1;
+    static constexpr int REPID = 0;
+    static constexpr bool RECON = true;
+    const cpx<S> *__restrict__ g;
+    int i;
+    __device__ __forceinline__ void load(int comp, typename acc_of<S>::type &re,
+                                         typename acc_of<S>::type &im) const
+    {
+        load_c_nt(g + lay(i, comp, 8 * 9), re, im);
     }
 };
 
@@ -165,6 +187,7 @@ struct LdsLinks {
     static constexpr bool REAL = false;
     static constexpr int NF = 1;
     static constexpr int REPID = 0;
+    static constexpr bool RECON = false;
     const cpx<S> *l;  // [comp][MR_SITES]
     int s;
     __device__ __forceinline__ void load(int comp, typename acc_of<S>::type &re,
@@ -185,6 +208,7 @@ struct RepLinks {
     static constexpr bool REAL = REP == 1;  // the adjoint representation is real
     static constexpr int NF = N;
     static constexpr int REPID = REP;
+    static constexpr bool RECON = false;
     const cpx<S> *__restrict__ g;
     int i;
     template <class A>
@@ -320,6 +344,22 @@ __device__ __forceinline__ void link_row_real(const A (&ur)[NR], const A (&hr)[2
     }
 }
 
+// third row of a special unitary 3 x 3 matrix from its first two:
+// u_2c = conj(u_0a u_1b - u_0b u_1a) with (a, b) = (c+1, c+2) mod 3
+template <class A, int RS, int NR>
+__device__ __forceinline__ void su3_third_row(A (&ur)[RS][NR], A (&ui)[RS][NR])
+{
+    static_assert(RS == 3 && NR == 3, "SU(3) fundamental rows");
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int a = (c + 1) % 3, b = (c + 2) % 3;
+        const A re = (ur[0][a] * ur[1][b] - ui[0][a] * ui[1][b]) - (ur[0][b] * ur[1][a] - ui[0][b] * ui[1][a]);
+        const A im = (ur[0][a] * ui[1][b] + ui[0][a] * ur[1][b]) - (ur[0][b] * ui[1][a] + ui[0][b] * ur[1][a]);
+        ur[2][c] = re;
+        ui[2][c] = -im;
+    }
+}
+
 // one direction (forward or backward) of one mu, for colour rows r0 .. r0+RS-1
 template <int MU, int DIR, bool DAG, int NR, int RS, class S, class LS>
 __device__ __forceinline__ void hop_dir(const HopArgs<S> &a, const cpx<S> *__restrict__ in,
@@ -353,8 +393,10 @@ __device__ __forceinline__ void hop_dir(const HopArgs<S> &a, const cpx<S> *__res
     // before any arithmetic waits on them (unused when links come from LDS)
     A ur[LS::ROWWISE ? 1 : RS][NR], ui[LS::ROWWISE ? 1 : RS][NR];
     if constexpr (!LS::ROWWISE) {
+        // rows read from memory (two of an SU(3) link when its third row is rebuilt)
+        constexpr int RL = LS::RECON ? 2 : RS;
 #pragma unroll
-        for (int r = 0; r < RS; ++r)
+        for (int r = 0; r < RL; ++r)
 #pragma unroll
             for (int c = 0; c < NR; ++c) links.load(DD * NR * NR + (r0 + r) * NR + c, ur[r][c], ui[r][c]);
     }
@@ -394,6 +436,7 @@ __device__ __forceinline__ void hop_dir(const HopArgs<S> &a, const cpx<S> *__res
                                     ai[2][r], ar[3][r], ai[3][r]);
         }
     } else {
+        if constexpr (LS::RECON) su3_third_row(ur, ui);
         A gr[2][RS], gi[2][RS];
 #pragma unroll
         for (int r = 0; r < RS; ++r) link_row(ur[r], ui[r], hr, hi, gr[0][r], gi[0][r], gr[1][r], gi[1][r]);
@@ -588,6 +631,34 @@ __global__ void __launch_bounds__(WG) hop_fused_kernel(const HopArgs<S> a)
         const double t = group_sum<G>(nrm, sh);
         const int grp = i / PG_SITES;
         if ((threadIdx.x & (PG_SITES * G - 1)) == 0 && grp < a.ngroups)
+            a.partial[(size_t)rhs * a.pstride + (a.parity < 0 ? parity * a.ngroups : 0) + grp] = t;
+    }
+}
+
+// The single-source kernel for SU(3) fundamental links read as two rows per
+// link (Su3Links); one thread per site, as hop_kernel at N_R = 3.
+template <class S, bool DAG, int EPI>
+__global__ void __launch_bounds__(WG) hop_su3_kernel(const HopArgs<S> a)
+{
+    __shared__ double sh[WG / 64];
+    int parity = a.parity, bx = blockIdx.x;
+    if (parity < 0) {
+        parity = bx >= a.grid_half;
+        if (parity) bx -= a.grid_half;
+    }
+    bx = tile_remap(xcd_remap(bx, a.grid_half), a.grid_half, a.tile_ts, a.tile_c);
+    const int rhs = blockIdx.y;
+    if (a.run && !a.run[rhs]) return;
+    const int i = bx * WG + threadIdx.x;
+    double nrm = 0;
+    if (i < a.g.half) {
+        Su3Links<S> links{a.gauge[parity], i};
+        nrm = site_hop<3, 3, S, DAG, EPI>(a, parity, i, 0, rhs, links);
+    }
+    if (EPI != EPI_PLAIN && a.partial) {
+        const double t = group_sum<1>(nrm, sh);
+        const int grp = i / PG_SITES;
+        if ((threadIdx.x & (PG_SITES - 1)) == 0 && grp < a.ngroups)
             a.partial[(size_t)rhs * a.pstride + (a.parity < 0 ? parity * a.ngroups : 0) + grp] = t;
     }
 }
@@ -929,6 +1000,31 @@ hipError_t launch_hop_fused_impl(int nc, int rep, bool dagger, int epi, const Ho
     else if (nc == 3 && rep == 2) go(std::integral_constant<int, 3>{}, std::integral_constant<int, 2>{});
     else if (nc == 4 && rep == 3) go(std::integral_constant<int, 4>{}, std::integral_constant<int, 3>{});
     if (!ok) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// SU(3) fundamental links read as two rows: same grid, tiling and partial-sum
+// groups as hop_kernel at N_R = 3.
+template <class S>
+hipError_t launch_hop_su3_impl(bool dagger, int epi, const HopArgs<S> &a, hipStream_t st)
+{
+    static_assert(hop_rows(3, dtype_id<S>()) == 3, "one thread per site");
+    if (epi == EPI_CG && !dagger) return hipErrorInvalidValue;
+    HopArgs<S> b = a;
+    b.ngroups = hop_groups(a.g);
+    const int gh = hop_grid(a.g, 1);
+    b.grid_half = gh;
+    hop_tiling(a.g, WG, &b.tile_ts, &b.tile_c);
+    dim3 grid(a.parity < 0 ? 2 * gh : gh, a.n_rhs);
+    if (epi == EPI_PLAIN) {
+        if (dagger) hop_su3_kernel<S, true, EPI_PLAIN><<<grid, WG, 0, st>>>(b);
+        else hop_su3_kernel<S, false, EPI_PLAIN><<<grid, WG, 0, st>>>(b);
+    } else if (epi == EPI_AXPY) {
+        if (dagger) hop_su3_kernel<S, true, EPI_AXPY><<<grid, WG, 0, st>>>(b);
+        else hop_su3_kernel<S, false, EPI_AXPY><<<grid, WG, 0, st>>>(b);
+    } else {
+        hop_su3_kernel<S, true, EPI_CG><<<grid, WG, 0, st>>>(b);
+    }
     return hipGetLastError();
 }
 

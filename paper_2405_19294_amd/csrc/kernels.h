@@ -96,6 +96,9 @@ constexpr bool hop_fused_supported(int nc, int rep)
 }
 template <class S>
 hipError_t launch_hop_fused(int nc, int rep, bool dagger, int epi, const HopArgs<S> &a, hipStream_t st);
+// SU(3) fundamental hop reading two rows of each link (third row rebuilt)
+template <class S>
+hipError_t launch_hop_su3(bool dagger, int epi, const HopArgs<S> &a, hipStream_t st);
 
 // Whether a single-source hop of a field that keeps its fundamental links
 // builds U_R in registers.  Building a row costs about as much arithmetic as

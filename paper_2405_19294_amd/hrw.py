@@ -152,15 +152,17 @@ def rep_map(nc: int, rep: str, u_f: torch.Tensor, stream=None) -> torch.Tensor:
 
 
 STORE_FUND_HOP = 1 << 4  # keep the fundamental links too: single-source hops build U_R in registers
+STORE_SU3_TWO_ROWS = 1 << 5  # SU(3) fundamental links are special unitary: hops read two rows per link
 
 
-def _storage_mask(dtypes, fused: bool) -> int:
-    return sum(1 << DTYPES[d] for d in dtypes) | (STORE_FUND_HOP if fused else 0)
+def _storage_mask(dtypes, fused: bool, two_rows: bool = False) -> int:
+    return (sum(1 << DTYPES[d] for d in dtypes) | (STORE_FUND_HOP if fused else 0)
+            | (STORE_SU3_TWO_ROWS if two_rows else 0))
 
 
-def gauge_storage_size(dims, nc: int, rep: str, dtypes=("f64",), fused: bool = False) -> int:
+def gauge_storage_size(dims, nc: int, rep: str, dtypes=("f64",), fused: bool = False, two_rows: bool = False) -> int:
     out = ctypes.c_size_t()
-    _check(load().hrw_gauge_storage_size(_ints(dims), nc, REPS[rep], _storage_mask(dtypes, fused),
+    _check(load().hrw_gauge_storage_size(_ints(dims), nc, REPS[rep], _storage_mask(dtypes, fused, two_rows),
                                          ctypes.byref(out)))
     return out.value
 
@@ -169,14 +171,15 @@ class Gauge:
     """Resident represented gauge field: a handle plus the torch storage it lives in."""
 
     def __init__(self, dims, nc: int, rep: str, u_f: torch.Tensor, dtypes=("f64", "f32"), stream=None,
-                 fused: bool = False):
+                 fused: bool = False, two_rows: bool = False):
         self.dims = tuple(int(d) for d in dims)
         self.nc, self.rep = int(nc), rep
         self.nr = rep_dim(nc, rep)
         self.dtypes = tuple(dtypes)
         self.fused = bool(fused)
-        mask = _storage_mask(dtypes, fused)
-        nbytes = gauge_storage_size(dims, nc, rep, dtypes, fused)
+        self.two_rows = bool(two_rows)
+        mask = _storage_mask(dtypes, fused, two_rows)
+        nbytes = gauge_storage_size(dims, nc, rep, dtypes, fused, two_rows)
         self.storage = _alloc_bytes(nbytes, u_f.device)
         h = ctypes.c_void_p()
         _check(load().hrw_gauge_create(_ints(dims), nc, REPS[rep], _dev_field(u_f, "u_f"), mask,
@@ -201,8 +204,8 @@ class Gauge:
         return d[0] * d[1] * d[2] * d[3]
 
 
-def gauge_create(dims, nc, rep, u_f, dtypes=("f64", "f32"), stream=None, fused=False) -> Gauge:
-    return Gauge(dims, nc, rep, u_f, dtypes, stream, fused)
+def gauge_create(dims, nc, rep, u_f, dtypes=("f64", "f32"), stream=None, fused=False, two_rows=False) -> Gauge:
+    return Gauge(dims, nc, rep, u_f, dtypes, stream, fused, two_rows)
 
 
 def workspace_size(dims, nc: int, rep: str, n_rhs: int = 1, params: SolveParams | None = None) -> int:

@@ -64,7 +64,7 @@ def summarize(stats_csv, fetch_csv, write_csv, out_prefix, command=""):
     calls = {r["Name"]: int(r["Calls"]) for r in stats}
     rows = []
     for name in sorted(fetch, key=lambda k: -sum(fetch[k])):
-        if "hop_kernel" not in name and "hop_mrhs_kernel" not in name:
+        if not any(k in name for k in ("hop_kernel", "hop_mrhs_kernel", "hop_su3_kernel", "hop_fused_kernel")):
             continue
         fb = statistics.mean(fetch[name]) * (ff or 1.0)
         wb = statistics.mean(write.get(name, [0.0])) * (wf or 1.0)

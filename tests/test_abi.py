@@ -114,7 +114,21 @@ def test_fused_rep_map_storage_flag(lib):
             hrw.gauge_storage_size(dims, nc, rep, ("f64",), fused=True)
         assert e.value.code == hrw.EUNSUPPORTED
     with pytest.raises(hrw.HrwError) as e:
-        lib_mask = (1 << 5) | 1
+        lib_mask = (1 << 6) | 1
         out = ctypes.c_size_t()
         hrw._check(lib.hrw_gauge_storage_size((ctypes.c_int * 4)(*dims), 3, 2, lib_mask, ctypes.byref(out)))
     assert e.value.code == hrw.EINVAL
+
+
+def test_su3_two_row_storage_flag(lib):
+    """The two-row flag leaves the storage size unchanged (all rows stay stored) and is refused
+    for anything but SU(3) fundamental fields."""
+    from paper_2405_19294_amd import hrw
+    dims = (4, 4, 4, 4)
+    assert hrw.STORE_SU3_TWO_ROWS == 1 << 5
+    assert hrw.gauge_storage_size(dims, 3, "fund", ("f64", "f32"), two_rows=True) == \
+        hrw.gauge_storage_size(dims, 3, "fund", ("f64", "f32"))
+    for nc, rep in [(2, "fund"), (4, "fund"), (3, "sym"), (3, "adj")]:
+        with pytest.raises(hrw.HrwError) as e:
+            hrw.gauge_storage_size(dims, nc, rep, ("f64",), two_rows=True)
+        assert e.value.code == hrw.EUNSUPPORTED

@@ -6,7 +6,8 @@ recomputes (the residual of a solve):
   * SU(3) fund 32^4 (default workload): D_hat and D_hat^+ in FP64 to 1e-13, the full-lattice D_W in
     FP32 within the a-priori bound, and the |b - D x| / |b| of the FP64 CG solve, of the BiCGstab
     solves (FP64 and FP32 inner) and of the QMR-g5 solve recomputed by the oracle; with the clover
-    term (c_sw = 1), D_hat_sw in FP64 and the FP32-inner BiCGstab solve of D_sw x = b;
+    term (c_sw = 1), D_hat_sw in FP64 and the FP32-inner BiCGstab solve of D_sw x = b; with the
+    two-row SU(3) hop, D_hat in FP64 and the FP64 CG and BF16-inner BiCGstab solves;
   * SU(2) adj and SU(4) asym 24^3x48, with stored U_R and with the representation map fused into the
     hop: D_hat in FP64, and the FP32-inner mixed solve's residual of the even/odd normal equations
     recomputed by the oracle;
@@ -65,6 +66,32 @@ def test_c2_solve_residual_by_oracle(c2_field):
     d_res = rel(orc.dw(C2, ur, KAPPA, x.cpu().numpy(), THETA_AP), b)
     assert abs(d_res - res[0]["d_rel_resid"]) <= 1e-3 * d_res
     assert d_res < 1e-8
+
+
+def test_c2_two_row_links_full_size():
+    """The default workload's field with the SU(3) two-row hop (the bench's two-row rows): D_hat and
+    D_hat^+ in FP64 to 1e-13, and the FP64 CG and BF16-inner BiCGstab solves of D x = b with
+    |b - D x| / |b| recomputed by the oracle."""
+    uf = fx.gauge_field(C2, 3, "thermal", seed=2, eps=0.3)
+    ur = orc.rep_map(3, "fund", uf)
+    g = hrw.Gauge(C2, 3, "fund", to_dev(uf), dtypes=("f64", "bf16"), two_rows=True)
+    psi = fx.gaussian_spinor(C2, 3, seed=3)
+    pe = _even(C2, psi)
+    for dagger in (False, True):
+        out = hrw.deo_apply(g, KAPPA, to_dev(pe), THETA_AP, "f64", dagger=dagger).cpu().numpy()
+        fp64_close(out, orc.deo(C2, ur, KAPPA, pe, THETA_AP, dagger=dagger))
+    prm = hrw.solve_params(tol=1e-10, max_iter=5000, system="d_cgnr_eo", inner_dtype="f64", theta=THETA_AP)
+    x, res, rc = hrw.cg_solve(g, to_dev(psi), KAPPA, prm)
+    assert rc == 0 and res[0]["true_rel_resid"] <= 1e-10
+    d_res = rel(orc.dw(C2, ur, KAPPA, x.cpu().numpy(), THETA_AP), psi)
+    assert abs(d_res - res[0]["d_rel_resid"]) <= 1e-3 * d_res and d_res < 1e-8
+    prm = hrw.solve_params(tol=1e-10, max_iter=5000, system="d_eo", inner_dtype="bf16", theta=THETA_AP,
+                           reliable_delta=hrw.RELIABLE_DELTA["bf16"])
+    x, res, rc = hrw.bicgstab_solve(g, to_dev(psi), KAPPA, prm)
+    assert rc == 0, res
+    d_res = rel(orc.dw(C2, ur, KAPPA, x.cpu().numpy(), THETA_AP), psi)
+    assert abs(d_res - res[0]["d_rel_resid"]) <= 1e-3 * d_res and d_res < 1e-9
+    g.close()
 
 
 @pytest.mark.parametrize("inner", ["f64", "f32"])
