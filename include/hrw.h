@@ -188,7 +188,10 @@ int hrw_gauge_storage_size(const int dims[4], int nc, int rep, unsigned storage_
  * into each precision in storage_mask (must include HRW_STORE_F64 whenever
  * FP64 operators or solves will be used).  storage: caller-owned device
  * memory of at least hrw_gauge_storage_size bytes, alive until destroy.
- * On success *out receives the handle. */
+ * The flag bits HRW_STORE_FUND_HOP and HRW_STORE_SU3_TWO_ROWS select how
+ * single-source hops read the links (see their definitions); a mask with
+ * unknown bits is HRW_EINVAL, a flag the group or representation does not
+ * support is HRW_EUNSUPPORTED.  On success *out receives the handle. */
 int hrw_gauge_create(const int dims[4], int nc, int rep, const double *u_f,
                      unsigned storage_mask, void *storage, size_t storage_bytes, void *stream,
                      hrw_gauge **out);
