@@ -1103,15 +1103,23 @@ int session_read(hrw_cg_session *s, int slot, int n, double *x_out, hrw_solve_re
     mark_range_kernel<<<1, 64, 0, st>>>(V.active + MAX_RHS, n, 0, n);
     HRW_HIP(hipGetLastError());
     const int *due = V.active + MAX_RHS;
-    if (V.mixed) {
-        HRW_HIP(launch_fold(V.dl, V.x.base, (double *)V.x64.base, due, V.cs, s->E, V.RS, n, st));
-        if ((rc = true_residual(R, V.x64, V.r64, V.s64, V.t64, V.u64, V.q64))) return rc;
-    } else {
-        if ((rc = true_residual(R, V.x, V.r64, V.s, V.t, V.u, V.q64))) return rc;
+    // A slot that finished (CG_DONE) got there through an FP64 true-residual check of its
+    // current solution (or has b = 0) and has not moved since: its recorded residual is
+    // current.  Only when some read slot stopped otherwise is the check run again.
+    if ((rc = refresh_states(s))) return rc;
+    bool all_done = true;
+    for (int j = slot; j < slot + n; ++j) all_done = all_done && s->host_state[j].status == CG_DONE;
+    if (V.mixed) HRW_HIP(launch_fold(V.dl, V.x.base, (double *)V.x64.base, due, V.cs, s->E, V.RS, n, st));
+    if (!all_done) {
+        if (V.mixed) {
+            if ((rc = true_residual(R, V.x64, V.r64, V.s64, V.t64, V.u64, V.q64))) return rc;
+        } else {
+            if ((rc = true_residual(R, V.x, V.r64, V.s, V.t, V.u, V.q64))) return rc;
+        }
+        // record the FP64 residual of every read slot without changing decisions
+        cg_reliable_kernel<<<n, WG, 0, st>>>(V.cs, V.pb, V.pstride, s->nbv, due, V.active, 0, 1, 0.0);
+        HRW_HIP(hipGetLastError());
     }
-    // record the FP64 residual of every read slot without changing decisions
-    cg_reliable_kernel<<<n, WG, 0, st>>>(V.cs, V.pb, V.pstride, s->nbv, due, V.active, 0, 1, 0.0);
-    HRW_HIP(hipGetLastError());
     const Fld &X = V.mixed ? V.x64 : V.x;
     if (V.sys == HRW_SYS_DDAG_D_EO) {
         HRW_HIP(launch_unpack_spinor(0, nr, g->g, false, 0, n, X.h(0), nullptr, V.RS, x_out, st));
