@@ -245,7 +245,8 @@ def workload_clover(args):
     """The default workload's gauge field and source with the clover term (c_sw = 1): clover setup,
     D_sw and D_hat_sw applies in FP64 and FP32, and D_sw x = b by BiCGstab on D_hat_sw (FP64, and
     FP32 inner fields with FP64 reliable updates; the line's value) beside the same request
-    without the clover term."""
+    without the clover term.  The field is flagged special unitary: the hops read two rows of each
+    SU(3) link (the clover builder reads the stored three)."""
     import torch
 
     import fixtures as fx
@@ -255,7 +256,7 @@ def workload_clover(args):
     kappa, csw, theta = WORKLOAD["kappa"], 1.0, (np.pi, 0.0, 0.0, 0.0)
     uf_d = torch.from_numpy(fx.gauge_field(dims, 3, "thermal", seed=2, eps=0.3)).to(dev)
     b_d = torch.from_numpy(fx.gaussian_spinor(dims, 3, seed=3)).to(dev)
-    g = hrw.Gauge(dims, 3, "fund", uf_d, dtypes=("f64", "f32"))
+    g = hrw.Gauge(dims, 3, "fund", uf_d, dtypes=("f64", "f32"), two_rows=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     c = hrw.Clover(g, kappa, csw, dtypes=("f64", "f32"))
@@ -299,7 +300,8 @@ def workload_clover(args):
         torch.cuda.synchronize()
         per = (time.perf_counter() - t0) / args.steps
         if inner == "f32":
-            roof = _hop_roofline(hrw, "hop_kernel<N_R=3, RS=3, float> (with the FP64 launches of the updates)")
+            roof = _hop_roofline(hrw, "hop_su3_kernel<float> (two rows of each link read; with the FP64 launches "
+                                      "of the updates)")
             hrw.timing_enable(False)
         r = res[0]
         rows[inner] = {"solves_per_s": round(1.0 / per, 3), "ms_per_solve": round(per * 1e3, 2), "iters": r["iters"],
@@ -316,7 +318,7 @@ def workload_clover(args):
     cfg = dict(WORKLOAD, workload="su3_fund_32^4_clover_eo_bicgstab_mixed_f32", c_sw=csw,
                system="D_sw x = b via even/odd Schur complement (A_ee - kappa^2 H_eo A_oo^-1 H_oe), BiCGstab",
                inner_dtype="f32", reliable_every=50, reliable_delta=1e-3,
-               links="stored: the hops read all three rows of each link")
+               links="SU(3) two-row: the hops read two rows of each link and rebuild the third")
     m = rows["f32"]
     return _line(m["solves_per_s"], "solves/s", args.steps, 1, m["ms_per_solve"], "f32", cfg, roof,
                  clover_setup_ms=round(setup_ms, 1), operators=ops, bicgstab=rows,

@@ -134,3 +134,27 @@ def test_clover_bicgstab(inner, nc, rep, dims):
     assert d_res <= 1e-9 and abs(d_res - res[0]["d_rel_resid"]) <= 1e-3 * d_res + 1e-16
     xs, info = orc.solve_dsw_eo_bicgstab(dims, ur, KAPPA, CSW, b, THETA_AP, tol=1e-12)
     assert rel(x, xs) <= 1e-7
+
+
+def test_clover_two_row_links():
+    """The clover operator on an SU(3) fundamental field whose hops read two rows of each link:
+    D_sw and D_hat_sw in FP64 against the oracle to 1e-13, and the FP32-inner BiCGstab solve of
+    D_sw x = b with |b - D_sw x| / |b| recomputed by the oracle."""
+    dims = (4, 4, 4, 8)
+    uf = fx.gauge_field(dims, 3, "thermal", seed=49)
+    ur = orc.rep_map(3, "fund", uf)
+    g = hrw.Gauge(dims, 3, "fund", to_dev(uf), dtypes=("f64", "f32"), two_rows=True)
+    c = hrw.Clover(g, KAPPA, CSW, dtypes=("f64", "f32"))
+    psi = fx.gaussian_spinor(dims, 3, seed=50)
+    fp64_close(hrw.dsw_apply(c, to_dev(psi), THETA_AP, "f64").cpu().numpy(),
+               orc.dsw(dims, ur, KAPPA, CSW, psi, THETA_AP))
+    pe = orc.split_eo(dims, psi)[0]
+    fp64_close(hrw.dsw_eo_apply(c, to_dev(pe), THETA_AP, "f64").cpu().numpy(),
+               orc.dsw_eo(dims, ur, KAPPA, CSW, pe, THETA_AP))
+    prm = hrw.solve_params(tol=1e-10, system="d_eo", inner_dtype="f32", theta=THETA_AP,
+                           reliable_delta=hrw.RELIABLE_DELTA["f32"])
+    x, res, rc = hrw.clover_bicgstab_solve(c, to_dev(psi), prm)
+    assert rc == 0, res
+    d_res = rel(orc.dsw(dims, ur, KAPPA, CSW, x.cpu().numpy(), THETA_AP), psi)
+    assert d_res <= 1e-9 and abs(d_res - res[0]["d_rel_resid"]) <= 1e-3 * d_res + 1e-16
+
