@@ -356,10 +356,11 @@ hipError_t launch_gauge_pack(int nc, int rep, int nr, const Geom &g, const doubl
     GaugeBlocks gb;
     for (int d = 0; d < 4; ++d)
         for (int q = 0; q < 2; ++q) gb.p[d][q] = blocks[d][q];
-    // zero the padding lanes first so every stored word is defined
+    // zero the padding lanes first so every stored word is defined (the packing below writes
+    // every entry of every site, so a half lattice of whole 64-site blocks has nothing to clear)
     for (int d = 0; d < 4; ++d)
         for (int q = 0; q < 2; ++q)
-            if (gb.p[d][q]) {
+            if (gb.p[d][q] && g.half % BLK) {
                 const size_t bytes = gauge_block_elems(g, nr) * dtype_cbytes(d);
                 hipError_t e = launch_zero(gb.p[d][q], bytes, st);
                 if (e != hipSuccess) return e;
