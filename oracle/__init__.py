@@ -64,6 +64,8 @@ def _load():
             "orc_hop_eo": (I, [P, I, P, P, I, I, P, P]),
             "orc_deo": (I, [P, I, P, D, P, I, P, P]),
             "orc_cg": (I, [P, I, P, D, P, I, P, P, D, I, P, P, P]),
+            "orc_cg_mixed": (I, [P, I, P, D, P, I, P, P, D, I, I, I, D, P, P, I, P]),
+            "orc_set_mixed_mutation": (None, [I]),
             "orc_bicgstab": (I, [P, I, P, D, P, I, P, P, D, I, P]),
             "orc_bicgstab_sw": (I, [P, I, P, D, D, P, I, P, P, D, I, P]),
             "orc_qmr_g5": (I, [P, I, P, D, P, I, P, P, D, I, P]),
@@ -244,6 +246,47 @@ def cg(dims, u_r, kappa, eta, theta=None, system=SYSTEM_EO, tol=1e-10, max_iter=
     it = int(info[0])
     return x, {"status": int(rc), "iters": it, "true_rel_resid": float(info[1]),
                "restarts": int(info[2]), "alpha": alpha[:it].copy(), "beta": beta[:it].copy()}
+
+
+MIXED_FMT = {"f64": -1, "f32": 0, "bf16": 1, "f16": 2}
+UPDATE_CAUSE = {1: "every", 2: "delta", 3: "converged"}
+
+
+def cg_mixed(dims, u_r, kappa, eta, theta=None, system=SYSTEM_EO, tol=1e-10, max_iter=10000, inner="f32",
+             every=50, delta=0.0):
+    """CG with reliable updates in mixed precision, emulated on the CPU (the
+    mixed-precision form of the Sec. 3.3 CG; reliable updates after Clark et
+    al., CPC 181 (2010)).  The inner iteration stores its fields in ``inner``
+    ("f32", "bf16", "f16"; "f64" for plain FP64 arithmetic) with float
+    arithmetic; every ``every`` iterations, when |r| fell by ``delta`` since
+    the last update, or when the recursion meets ``tol``, the solution is
+    folded into FP64 and the residual recomputed in FP64 (see orc_cg_mixed).
+
+    Returns (x, info): info = {"status", "iters", "true_rel_resid",
+    "restarts", "updates", "log", "drop"}; log rows are (iteration, cause,
+    |r64|/|eta|) per update, drop[k] = |r|^2 after iteration k+1 over |r|^2
+    at the last update.
+    """
+    u, b = _c128(u_r), _c128(eta)
+    x = np.zeros_like(b)
+    info = np.zeros(5)
+    cap = max_iter + 64
+    log = np.zeros((cap, 3))
+    drop = np.zeros(max_iter)
+    rc = _load().orc_cg_mixed(_ptr(_dims(dims)), _nr_of(u), _ptr(u), float(kappa), _ptr(_theta(theta)),
+                              int(system), _ptr(b), _ptr(x), float(tol), int(max_iter), MIXED_FMT[inner],
+                              int(every), float(delta), _ptr(info), _ptr(log), cap, _ptr(drop))
+    _check(rc if rc != -5 else 0, "cg_mixed")
+    it, nlog = int(info[0]), int(info[4])
+    rows = [(int(a), UPDATE_CAUSE[int(c)], float(t)) for a, c, t in log[:nlog]]
+    return x, {"status": int(rc), "iters": it, "true_rel_resid": float(info[1]), "restarts": int(info[2]),
+               "updates": int(info[3]), "log": rows, "drop": drop[:it].copy()}
+
+
+def set_mixed_mutation(k: int) -> None:
+    """Plant mistake k (0 = none) in the mixed-precision CG emulation.  For the
+    tests that show the emulation's pins reject each planted mistake."""
+    _load().orc_set_mixed_mutation(int(k))
 
 
 def lanczos_extremes(alpha, beta):
@@ -434,6 +477,55 @@ def hop_abs(dims, u_r_abs, psi_abs) -> np.ndarray:
         tb = np.einsum("...ba,...sb->...sa", ub, pb)
         out += np.einsum("st,...tc->...sc", proj, tf + tb)
     return out.reshape(np.asarray(psi_abs).shape)
+
+
+def hop_abs_real(dims, u_r, psi, theta=None, dagger=False) -> np.ndarray:
+    """Per real component of H psi (or H^+ psi), the sum of the absolute values of
+    its real monomials: every complex product expanded into real products, each
+    taken with its absolute value (the real-arithmetic |H||psi| of a rounding-error
+    analysis, Higham, Accuracy and Stability of Numerical Algorithms, Sec. 3.6).
+
+    Returned as one complex array: the real part bounds the real components, the
+    imaginary part the imaginary components.  A computed evaluation whose every
+    monomial passes through at most m roundings then satisfies, per real
+    component, |fl(H psi) - H psi| <= gamma_m (this array's component).
+    """
+    d = tuple(int(v) for v in dims)
+    nr = np.asarray(psi).shape[-1]
+    u = _c128(u_r).reshape(d + (4, nr, nr))
+    p = _c128(psi).reshape(d + (4, nr))
+    th = _theta(theta)
+    ar, ai = np.abs(p.real), np.abs(p.imag)
+    out_r = np.zeros(ar.shape)
+    out_i = np.zeros(ar.shape)
+    x = np.indices(d)
+    sign = -1.0 if dagger else 1.0
+    for mu in range(4):
+        g = gamma(mu)
+        for fwd in (True, False):
+            if fwd:
+                link = u[..., mu, :, :]
+                pr, pi_ = np.roll(ar, -1, axis=mu), np.roll(ai, -1, axis=mu)
+                wrap = x[mu] == d[mu] - 1
+                proj = np.eye(4) - sign * g
+                ph = np.exp(1j * th[mu])
+            else:
+                link = np.conj(np.swapaxes(np.roll(u[..., mu, :, :], 1, axis=mu), -1, -2))
+                pr, pi_ = np.roll(ar, 1, axis=mu), np.roll(ai, 1, axis=mu)
+                wrap = x[mu] == 0
+                proj = np.eye(4) + sign * g
+                ph = np.exp(-1j * th[mu])
+            lr, li = np.abs(link.real), np.abs(link.imag)
+            tr = np.einsum("...ab,...sb->...sa", lr, pr) + np.einsum("...ab,...sb->...sa", li, pi_)
+            ti = np.einsum("...ab,...sb->...sa", li, pr) + np.einsum("...ab,...sb->...sa", lr, pi_)
+            qr, qi = np.abs(proj.real), np.abs(proj.imag)
+            sr = np.einsum("st,...tc->...sc", qr, tr) + np.einsum("st,...tc->...sc", qi, ti)
+            si = np.einsum("st,...tc->...sc", qi, tr) + np.einsum("st,...tc->...sc", qr, ti)
+            c, sn = abs(ph.real), abs(ph.imag)
+            w = wrap[..., None, None]
+            out_r += np.where(w, c * sr + sn * si, sr)
+            out_i += np.where(w, sn * sr + c * si, si)
+    return (out_r + 1j * out_i).reshape(np.asarray(psi).shape)
 
 
 def gamma_k(k: int, unit_roundoff: float) -> float:

@@ -834,6 +834,380 @@ int orc_cg(const int *dims, int nr, const double *u, double kappa, const double 
     return status;
 }
 
+/* ------------------------------------------------------------------ mixed-precision CG */
+
+/*
+ * CG with reliable updates (Clark et al., "Solving lattice QCD systems of
+ * equations using mixed precision solvers on GPUs", Comput. Phys. Commun. 181
+ * (2010) 1517), emulated on the CPU.  The paper's CG (Sec. 3.3) runs in one
+ * precision; this is the mixed-precision form of it: the iteration runs on
+ * fields stored in a low-precision format with single-precision arithmetic,
+ * and every so often the solution is folded into an FP64 accumulator and the
+ * residual is recomputed in FP64 from it.
+ *
+ * Emulation of the low precision:
+ *   - arithmetic of the inner iteration (the operator, the vector updates) is
+ *     C float arithmetic; the links are the FP64 links rounded once to the
+ *     storage format;
+ *   - every field the iteration stores (x, r, p and the operator's
+ *     intermediate fields) is rounded to the storage format after each float
+ *     result: binary32 leaves float values as they are, bfloat16 and binary16
+ *     round them to nearest even;
+ *   - inner products and norms accumulate the float values in FP64; alpha and
+ *     beta are FP64 and enter the float updates rounded to float;
+ *   - |r|^2 is taken from the float residual before it is stored.
+ * With fmt = ORC_FMT_F64 the inner iteration is plain FP64 arithmetic; with
+ * reliable updates off it is then the same computation as orc_cg.
+ *
+ * Reliable-update step (the readings this build fixes where the method is
+ * stated loosely): a system is due after `every` of its own iterations
+ * (0: never), when |r| fell below delta |r| at the last update (delta = 0:
+ * never), or when its recursion meets tol.  A due system first completes its
+ * iteration (p = r + beta p), then in FP64
+ *     x64 += x_lo / s,  x_lo = 0,  r64 = eta - A x64;
+ * if |r64| <= tol |eta| it stops; otherwise p_lo = s' (p_lo / s + (r64 -
+ * r_lo / s)) and r_lo = s' r64, so p = r + beta p_prev still holds for the
+ * replaced residual, and beta at the next iteration uses |r64|^2.  The inner
+ * fields hold s times the true vectors: s = 1, except for binary16 storage
+ * where s = sqrt(2 n / |r|^2) (n complex entries) is chosen at the start and
+ * at every update so that the stored entries have RMS 1 (binary16 ends near
+ * 6e-8); CG is linear, so alpha and beta do not depend on s.  A system whose
+ * recursion met tol but whose FP64 residual did not is counted as a restart;
+ * more than 20 restarts end the solve.
+ *
+ * system: 0 = D^+D on the full lattice, 1 = D_hat^+ D_hat on the even sites.
+ * fmt: ORC_FMT_F64 (-1), 0 = binary32, 1 = bfloat16, 2 = binary16.
+ * info: [0] iterations, [1] final FP64 true relative residual, [2] restarts,
+ * [3] reliable updates (FP64 true-residual evaluations).
+ * log (may be NULL, log_cap entries of 3 doubles): per update, the iteration
+ * count at which it ran, its cause (1: every, 2: delta, 3: recursion met tol)
+ * and |r64| / |eta|.
+ * drop (may be NULL, max_iter entries): per iteration, |r|^2 / |r|^2 at the
+ * last update (the quantity the delta trigger compares with delta^2).
+ */
+#define ORC_FMT_F64 (-1)
+
+static double round_to_format(double x, int p, int emin, double maxfin);
+static int fmt_params(int fmt, int *p, int *emin, double *maxfin);
+
+/* one stored real: the value rounded to the storage format */
+static double store_real(int fmt, double v)
+{
+    int p, emin;
+    double maxfin;
+    if (fmt == ORC_FMT_F64 || fmt_params(fmt, &p, &emin, &maxfin)) return v;
+    return round_to_format(v, p, emin, maxfin);
+}
+
+static cplx store_c(int fmt, double re, double im) { return store_real(fmt, re) + I * store_real(fmt, im); }
+
+/* float-arithmetic hop (H or H^+) on the full lattice: the hop_full sums in float */
+typedef float complex fcplx;
+static void hop_full_f(const int d[4], int nr, const fcplx *u, const double theta[4], int sign, const fcplx *in,
+                       fcplx *out)
+{
+    init_gamma();
+    const long v = vol(d);
+    const int sp = 4 * nr;
+    const long ls = (long)nr * nr;
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < v; ++s) {
+        int x[4];
+        coords(d, s, x);
+        fcplx acc[4 * 16];
+        fcplx t[4 * 16];
+        for (int i = 0; i < sp; ++i) acc[i] = 0;
+        for (int mu = 0; mu < 4; ++mu) {
+            for (int dir = 0; dir < 2; ++dir) {
+                int y[4] = {x[0], x[1], x[2], x[3]};
+                fcplx ph = 1.0f;
+                const fcplx *link;
+                int adj;
+                if (dir == 0) {
+                    y[mu] = (x[mu] + 1) % d[mu];
+                    if (x[mu] == d[mu] - 1) ph = (float)cos(theta[mu]) + I * (float)sin(theta[mu]);
+                    link = u + (s * 4 + mu) * ls;
+                    adj = 0;
+                } else {
+                    y[mu] = (x[mu] + d[mu] - 1) % d[mu];
+                    if (x[mu] == 0) ph = (float)cos(theta[mu]) - I * (float)sin(theta[mu]);
+                    link = u + (index_of(d, y) * 4 + mu) * ls;
+                    adj = 1;
+                }
+                const fcplx *src = in + index_of(d, y) * sp;
+                for (int al = 0; al < 4; ++al)
+                    for (int a = 0; a < nr; ++a) {
+                        fcplx z = 0;
+                        for (int b = 0; b < nr; ++b) {
+                            fcplx l = adj ? conjf(link[b * nr + a]) : link[a * nr + b];
+                            z += l * src[al * nr + b];
+                        }
+                        t[al * nr + a] = z;
+                    }
+                const float gs = (dir == 0 ? -1.0f : 1.0f) * (float)sign;
+                for (int al = 0; al < 4; ++al)
+                    for (int a = 0; a < nr; ++a) {
+                        fcplx z = t[al * nr + a];
+                        for (int be = 0; be < 4; ++be) z += gs * (fcplx)G[mu][al][be] * t[be * nr + a];
+                        acc[al * nr + a] += ph * z;
+                    }
+            }
+        }
+        for (int i = 0; i < sp; ++i) out[s * sp + i] = acc[i];
+    }
+}
+
+typedef struct {
+    const int *dims;
+    int nr, system, fmt;
+    const double *theta;
+    double kappa;
+    const cplx *u64;   /* FP64 links */
+    fcplx *ulo;        /* links rounded to the storage format, as floats */
+    fcplx *fa, *fb;    /* full-lattice float scratch */
+    cplx *da;          /* full-lattice double scratch */
+    cplx *t1, *t2;     /* inner-field scratch (one system) */
+    long n;            /* complex entries of one system's field */
+} mixed_ctx;
+
+/* float hop of a field given by its stored values (full lattice, or the
+ * out_parity block from parity 1 - out_parity); out holds float values */
+static void lo_hop(mixed_ctx *m, int dag, int out_parity, const cplx *in, cplx *out)
+{
+    const long v = vol(m->dims);
+    const long nf = v * 4 * m->nr;
+    if (m->system == 0) {
+        for (long i = 0; i < nf; ++i) m->fa[i] = (float)creal(in[i]) + I * (float)cimag(in[i]);
+    } else {
+        embed(m->dims, m->nr, 1 - out_parity, in, m->da);
+        for (long i = 0; i < nf; ++i) m->fa[i] = (float)creal(m->da[i]) + I * (float)cimag(m->da[i]);
+    }
+    hop_full_f(m->dims, m->nr, m->ulo, m->theta, dag ? -1 : 1, m->fa, m->fb);
+    if (m->system == 0) {
+        for (long i = 0; i < nf; ++i) out[i] = crealf(m->fb[i]) + I * cimagf(m->fb[i]);
+    } else {
+        for (long i = 0; i < nf; ++i) m->da[i] = crealf(m->fb[i]) + I * cimagf(m->fb[i]);
+        extract(m->dims, m->nr, out_parity, m->da, out);
+    }
+}
+
+/* out = in - c * hop(in) in float, c rounded to float; store: round to the format */
+static void lo_axpy_hop(mixed_ctx *m, int dag, const cplx *in, cplx *out, int store)
+{
+    const float c = (float)(m->system == 0 ? m->kappa : m->kappa * m->kappa);
+    if (m->system == 0) {
+        lo_hop(m, dag, 0, in, m->t1);
+    } else {
+        lo_hop(m, dag, 1, in, m->t2);
+        for (long i = 0; i < m->n; ++i) m->t2[i] = store_c(m->fmt, creal(m->t2[i]), cimag(m->t2[i]));
+        lo_hop(m, dag, 0, m->t2, m->t1);
+    }
+    for (long i = 0; i < m->n; ++i) {
+        const float re = (float)creal(in[i]) - c * (float)creal(m->t1[i]);
+        const float im = (float)cimag(in[i]) - c * (float)cimag(m->t1[i]);
+        out[i] = store ? store_c(m->fmt, re, im) : (double)re + I * (double)im;
+    }
+}
+
+/* q = A p in the inner precision (D p stored, D^+ of it in float) */
+static void lo_apply_normal(mixed_ctx *m, const cplx *p, cplx *s, cplx *q)
+{
+    lo_axpy_hop(m, 0, p, s, 1);
+    lo_axpy_hop(m, 1, s, q, 0);
+}
+
+static int mixed_mutation = 0; /* planted mistakes for the pin tests; 0 = none */
+
+void orc_set_mixed_mutation(int k) { mixed_mutation = k; }
+
+int orc_cg_mixed(const int *dims, int nr, const double *u, double kappa, const double *theta, int system,
+                 const double *eta, double *x_out, double tol, int max_iter, int fmt, int every, double delta,
+                 double *info, double *log, int log_cap, double *drop)
+{
+    int fp, fe;
+    double fm;
+    if (!check_dims(dims, nr) || (system != 0 && system != 1) || !eta || !x_out || max_iter < 1)
+        return ORC_EINVAL;
+    if (fmt != ORC_FMT_F64 && fmt_params(fmt, &fp, &fe, &fm)) return ORC_EINVAL;
+    if (system == 1 && !even_dims(dims)) return ORC_EINVAL;
+    const long v = vol(dims);
+    const long n = (system == 0 ? v : v / 2) * 4 * nr;
+    const long nf = v * 4 * nr;
+    const size_t bytes = sizeof(cplx) * (size_t)n;
+    const int lo = fmt != ORC_FMT_F64;
+    mixed_ctx m = {dims, nr, system, fmt, theta, kappa, (const cplx *)u, NULL, NULL, NULL, NULL, NULL, NULL, n};
+    op_ctx c64 = {dims, nr, u, kappa, theta, system, (cplx *)malloc(bytes), 0.0};
+    cplx *x64 = (cplx *)x_out, *x = (cplx *)calloc(n, sizeof(cplx)), *r = (cplx *)malloc(bytes),
+         *p = (cplx *)malloc(bytes), *q = (cplx *)malloc(bytes), *s = (cplx *)malloc(bytes),
+         *r64 = (cplx *)malloc(bytes);
+    if (lo) {
+        const long nl = v * 4 * (long)nr * nr;
+        m.ulo = (fcplx *)malloc(sizeof(fcplx) * nl);
+        for (long i = 0; i < nl; ++i) {
+            const cplx z = store_c(fmt, creal(m.u64[i]), cimag(m.u64[i]));
+            m.ulo[i] = (float)creal(z) + I * (float)cimag(z);
+        }
+        m.fa = (fcplx *)malloc(sizeof(fcplx) * nf);
+        m.fb = (fcplx *)malloc(sizeof(fcplx) * nf);
+        m.da = (cplx *)malloc(sizeof(cplx) * nf);
+        m.t1 = (cplx *)malloc(bytes);
+        m.t2 = (cplx *)malloc(bytes);
+    }
+    const cplx *b = (const cplx *)eta;
+    memset(x64, 0, bytes);
+    const double bb = norm2(n, b);
+    /* inner fields hold sc times the true vectors (binary16: RMS 1) */
+    double sc = (fmt == 2 && bb > 0 && isfinite(bb) && mixed_mutation != 6) ? sqrt(2.0 * (double)n / bb) : 1.0;
+    for (long i = 0; i < n; ++i) {
+        r[i] = store_c(fmt, sc * creal(b[i]), sc * cimag(b[i]));
+        p[i] = r[i];
+    }
+    double rr = bb * sc * sc, rr_last = rr;
+    int it = 0, since = 0, restarts = 0, updates = 0, nlog = 0;
+    int status = bb > 0 ? ORC_NOT_CONVERGED : ORC_OK;
+    double true_rel = bb > 0 ? 1.0 : 0.0;
+    if (!isfinite(bb)) status = ORC_BREAKDOWN;
+    while (status == ORC_NOT_CONVERGED) {
+        /* q = A p, alpha = |r|^2 / <p, q> */
+        if (lo) lo_apply_normal(&m, p, s, q);
+        else apply_normal(&c64, p, q);
+        const double pq = re_dot(n, p, q);
+        if (!(pq > 0) || !isfinite(pq)) {
+            status = ORC_BREAKDOWN;
+            break;
+        }
+        const double a = rr / pq;
+        double rr_new;
+        if (lo) {
+            const float af = (float)a;
+            rr_new = 0;
+            for (long i = 0; i < n; ++i) {
+                const float xr = (float)creal(x[i]) + af * (float)creal(p[i]);
+                const float xi = (float)cimag(x[i]) + af * (float)cimag(p[i]);
+                const float rr_ = (float)creal(r[i]) - af * (float)creal(q[i]);
+                const float ri = (float)cimag(r[i]) - af * (float)cimag(q[i]);
+                x[i] = store_c(fmt, xr, xi);
+                r[i] = store_c(fmt, rr_, ri);
+                rr_new += (double)rr_ * rr_ + (double)ri * ri;
+            }
+        } else {
+            for (long i = 0; i < n; ++i) {
+                x[i] += a * p[i];
+                r[i] -= a * q[i];
+            }
+            rr_new = norm2(n, r);
+        }
+        const double bt = rr_new / rr;
+        ++it;
+        ++since;
+        rr = rr_new;
+        if (drop) drop[it - 1] = rr_new / rr_last;
+        int cause = 0;
+        if (!isfinite(rr_new)) {
+            status = ORC_BREAKDOWN;
+            break;
+        } else if (sqrt(rr_new / (bb * sc * sc)) <= tol) {
+            cause = 3;
+        } else if (it >= max_iter) {
+            break;
+        } else if (every > 0 && since >= every + (mixed_mutation == 5)) {
+            cause = 1;
+        } else if (delta > 0 && rr_new < delta * delta * rr_last) {
+            cause = 2;
+        }
+        /* p = r + beta p (also for a system that is now due) */
+        if (lo) {
+            const float bf = (float)bt;
+            for (long i = 0; i < n; ++i)
+                p[i] = store_c(fmt, (float)creal(r[i]) + bf * (float)creal(p[i]),
+                               (float)cimag(r[i]) + bf * (float)cimag(p[i]));
+        } else {
+            for (long i = 0; i < n; ++i) p[i] = r[i] + bt * p[i];
+        }
+        if (!cause) continue;
+        if (cause == 3 && mixed_mutation == 4) { /* planted: trust the recursion */
+            for (long i = 0; i < n; ++i) x64[i] += x[i] / sc;
+            status = ORC_OK;
+            break;
+        }
+        /* reliable update: fold x_lo into x64, FP64 true residual */
+        const double inv = 1.0 / sc;
+        for (long i = 0; i < n; ++i) {
+            const double fr = mixed_mutation == 2 ? 1.0 : inv;
+            x64[i] = creal(x64[i]) + creal(x[i]) * fr + I * (cimag(x64[i]) + cimag(x[i]) * fr);
+            if (mixed_mutation == 3) x64[i] = store_c(0, creal(x64[i]), cimag(x64[i]));
+            if (mixed_mutation != 1) x[i] = 0;
+        }
+        if (mixed_mutation == 7 && lo) lo_apply_normal(&m, x64, s, q);
+        else apply_normal(&c64, x64, q);
+        for (long i = 0; i < n; ++i) r64[i] = b[i] - q[i];
+        const double rt = norm2(n, r64);
+        ++updates;
+        since = 0;
+        true_rel = sqrt(rt / bb);
+        if (log && nlog < log_cap) {
+            log[3 * nlog] = it;
+            log[3 * nlog + 1] = cause;
+            log[3 * nlog + 2] = true_rel;
+            ++nlog;
+        }
+        if (true_rel <= tol) {
+            status = ORC_OK;
+            break;
+        }
+        if (!isfinite(rt)) {
+            status = ORC_BREAKDOWN;
+            break;
+        }
+        if (cause == 3 && ++restarts > 20) break;
+        /* resume from the true residual: keep p = r + beta p_prev valid */
+        const double sn = (fmt == 2 && mixed_mutation != 6) ? sqrt(2.0 * (double)n / rt) : 1.0;
+        const double rsc = mixed_mutation == 8 ? 1.0 : sn;
+        for (long i = 0; i < n; ++i) {
+            const cplx ro = r[i] * inv, po = p[i] * inv;
+            r[i] = store_c(fmt, rsc * creal(r64[i]), rsc * cimag(r64[i]));
+            const cplx pn = po + (r64[i] - ro);
+            p[i] = store_c(fmt, sn * creal(pn), sn * cimag(pn));
+        }
+        sc = sn;
+        rr = rt * sc * sc;
+        rr_last = rr;
+    }
+    if (status == ORC_NOT_CONVERGED || status == ORC_BREAKDOWN) {
+        for (long i = 0; i < n; ++i) x64[i] += x[i] / sc;
+        apply_normal(&c64, x64, q);
+        for (long i = 0; i < n; ++i) r64[i] = b[i] - q[i];
+        true_rel = bb > 0 ? sqrt(norm2(n, r64) / bb) : 0.0;
+    } else if (mixed_mutation == 4) {
+        apply_normal(&c64, x64, q);
+        for (long i = 0; i < n; ++i) r64[i] = b[i] - q[i];
+        true_rel = sqrt(norm2(n, r64) / bb);
+    }
+    if (info) {
+        info[0] = it;
+        info[1] = true_rel;
+        info[2] = restarts;
+        info[3] = updates;
+        info[4] = nlog;
+    }
+    free(c64.tmp);
+    free(x);
+    free(r);
+    free(p);
+    free(q);
+    free(s);
+    free(r64);
+    if (lo) {
+        free(m.ulo);
+        free(m.fa);
+        free(m.fb);
+        free(m.da);
+        free(m.t1);
+        free(m.t2);
+    }
+    return status;
+}
+
 /* ------------------------------------------------------------------ BiCGstab */
 
 /* D (system 0, full lattice) or D_hat (system 1, even sites) applied to in. */
@@ -1170,17 +1544,24 @@ static double round_to_format(double x, int p, int emin, double maxfin)
     return r;
 }
 
-/* fmt: 0 = IEEE binary32, 1 = bfloat16, 2 = IEEE binary16. In-place on n doubles. */
+/* fmt: 0 = IEEE binary32, 1 = bfloat16, 2 = IEEE binary16: significand bits,
+ * smallest normal exponent and largest finite value (nonzero: unknown fmt) */
+static int fmt_params(int fmt, int *p, int *emin, double *maxfin)
+{
+    switch (fmt) {
+    case 0: *p = 24; *emin = -126; *maxfin = ldexp(2.0 - ldexp(1.0, -23), 127); return 0;
+    case 1: *p = 8; *emin = -126; *maxfin = ldexp(2.0 - ldexp(1.0, -7), 127); return 0;
+    case 2: *p = 11; *emin = -14; *maxfin = 65504.0; return 0;
+    }
+    return 1;
+}
+
+/* Round n doubles in place to format fmt (as fmt_params). */
 int orc_round(int fmt, long n, double *a)
 {
     int p, emin;
     double maxfin;
-    switch (fmt) {
-    case 0: p = 24; emin = -126; maxfin = ldexp(2.0 - ldexp(1.0, -23), 127); break;
-    case 1: p = 8; emin = -126; maxfin = ldexp(2.0 - ldexp(1.0, -7), 127); break;
-    case 2: p = 11; emin = -14; maxfin = 65504.0; break;
-    default: return ORC_EINVAL;
-    }
+    if (fmt_params(fmt, &p, &emin, &maxfin)) return ORC_EINVAL;
     for (long i = 0; i < n; ++i) a[i] = round_to_format(a[i], p, emin, maxfin);
     return ORC_OK;
 }

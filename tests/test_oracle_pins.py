@@ -664,8 +664,10 @@ def test_round_bf16_ties_and_torch_cast():
 def test_pins_catch_planted_mistakes():
     """Plant typical mistakes in a numpy re-statement of the hop and check the pins reject them.
 
-    The mutants are written here (CPU only); the oracle itself is untouched.  Each
-    mutant must fail the free-field, gamma_5 or covariance check.
+    The mutants are written here (CPU only); the oracle itself is untouched.  The
+    unmutated re-statement passes the free-field, gamma_5 and gauge-covariance
+    checks; each mutant must fail at least one of them.  Agreement with the
+    oracle is not one of the criteria, so the pins alone reject every mutant.
     """
     dims = (4, 2, 2, 4)
     nc = 2
@@ -715,11 +717,19 @@ def test_pins_catch_planted_mistakes():
         g5 = orc.gamma5
         rhs = inner(g5(dw_variant(uf, kappa, g5(chi), THETA_TW, mutant)), psi)
         ok &= abs(lhs - rhs) < 1e-12 * abs(lhs)
-        # agreement with the oracle on random links
-        ok &= rel(dw_variant(uf, kappa, psi, THETA_TW, mutant), orc.dw(dims, uf, kappa, psi, THETA_TW)) < 1e-13
+        # gauge covariance: D[U^g] g psi = g D[U] psi
+        ugf = np.empty_like(uf)
+        for mu in range(4):
+            ugf[:, mu] = gt @ uf[:, mu] @ np.conj(np.swapaxes(gt[fwd[mu]], 1, 2))
+        rot = lambda f: np.einsum("sab,sib->sia", gt, f)
+        ok &= rel(dw_variant(ugf, kappa, rot(psi), THETA_TW, mutant),
+                  rot(dw_variant(uf, kappa, psi, THETA_TW, mutant))) < 1e-13
         return bool(ok)
 
+    gt = fx.random_gauge_transform(dims, nc, seed=95)
     assert passes_all(None)
+    # the unmutated re-statement is the oracle's operator (a check of the re-statement, not a criterion)
+    assert rel(dw_variant(uf, kappa, psi, THETA_TW, None), orc.dw(dims, uf, kappa, psi, THETA_TW)) < 1e-13
     for m in ["transposed_gamma", "gamma_sign", "backward_link_at_x", "backward_no_dagger", "no_phase"]:
         assert not passes_all(m), m
 
@@ -738,3 +748,45 @@ def test_hop_abs_bounds_the_hop():
     # free field, positive spinor: projector entries (1 -+ g) have mixed signs, so
     # only the diagonal spin part is exact; check the scale instead
     assert np.allclose(orc.hop_abs(dims, unit, pos).sum(), 2 * 8 * pos.sum(), rtol=1e-12)
+
+
+def test_hop_abs_real_bounds_the_hop_and_free_field_closed_form():
+    """The real-arithmetic |H||psi| (oracle.hop_abs_real): it bounds |Re H psi| and |Im H psi|
+    componentwise and is at least the sum of the absolute entries of the real embedding of H (built
+    column by column, brute force); on unit links, zero phases and a real non-negative spinor it has
+    a closed form: the real part collects, per direction, the spinor's own spin component and the
+    partner spin of a real gamma entry (mu = 0, 2); the imaginary part the partner of an imaginary
+    entry (mu = 1, 3)."""
+    dims = (2, 2, 2, 4)
+    ur = _random_setup(dims, 3, "fund", seed=97)
+    psi = fx.gaussian_spinor(dims, 3, seed=98)
+    for dagger in (False, True):
+        h = orc.hop(dims, ur, psi, THETA_TW, dagger)
+        b = orc.hop_abs_real(dims, ur, psi, THETA_TW, dagger)
+        assert np.all(np.abs(h.real) <= b.real * (1 + 1e-12)) and np.all(np.abs(h.imag) <= b.imag * (1 + 1e-12))
+    n = psi.size
+    cols = []
+    for j in range(n):
+        e = np.zeros(n, complex)
+        e[j] = 1
+        cols.append(orc.hop(dims, ur, e.reshape(psi.shape), THETA_TW).reshape(-1))
+    hm = np.stack(cols, axis=1)
+    pr, pi_ = np.abs(psi.real).reshape(-1), np.abs(psi.imag).reshape(-1)
+    b = orc.hop_abs_real(dims, ur, psi, THETA_TW).reshape(-1)
+    assert np.all(np.abs(hm.real) @ pr + np.abs(hm.imag) @ pi_ <= b.real * (1 + 1e-12))
+    assert np.all(np.abs(hm.imag) @ pr + np.abs(hm.real) @ pi_ <= b.imag * (1 + 1e-12))
+    # free field, real non-negative spinor: partner spin of spin s under gamma_mu
+    unit = fx.unit_gauge(dims, 3)
+    pos = np.abs(psi.real)
+    b = orc.hop_abs_real(dims, unit, pos)
+    p4 = pos.reshape(tuple(dims) + (4, 3))
+    partner = {0: [2, 3, 0, 1], 1: [3, 2, 1, 0], 2: [3, 2, 1, 0], 3: [2, 3, 0, 1]}
+    er = np.zeros_like(p4)
+    ei = np.zeros_like(p4)
+    for mu in range(4):
+        for sh in (-1, 1):
+            q = np.roll(p4, sh, axis=mu)
+            er += q + (q[..., partner[mu], :] if mu in (0, 2) else 0)
+            ei += q[..., partner[mu], :] if mu in (1, 3) else 0
+    assert np.allclose(b.real, er.reshape(pos.shape), rtol=1e-14)
+    assert np.allclose(b.imag, ei.reshape(pos.shape), rtol=1e-14, atol=0)
