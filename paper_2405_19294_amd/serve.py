@@ -7,19 +7,25 @@ running session as soon as enough slots are free, its iterations share every
 operator launch with the requests already there, and it leaves the session
 when its own systems have converged.  Sessions of different gauge fields run
 on their own HIP streams from their own host threads, so their work overlaps
-on the device.  A new session is opened only when its workspace fits the HBM
-budget (admission by footprint); a request that can never fit is refused.
+on the device.  Admission is by HBM footprint: the resident gauge fields and
+the open sessions' workspaces together stay within the budget.  A session is
+opened only when its workspace, plus its gauge field if that is not resident
+yet, fits; idle sessions are closed and the gauge fields of keys without a
+session are evicted, least recently used first, to make room; a request that
+cannot fit even on an empty device is refused.
 
 Each request's result is the same as a standalone solve of that request,
 because every slot keeps its own recurrence (see ``hrw.Session``).
 
 The backend is pluggable: ``GpuBackend`` drives libhrw.  Any object with the
-same methods (gauge, gauge_bytes, session_bytes, sources, open_session,
-solve_alone) can stand in for it, e.g. to test the scheduling on a CPU.
+same methods (gauge, gauge_bytes, drop_gauge, session_bytes, sources,
+open_session, solve_alone) can stand in for it, e.g. to test the scheduling on
+a CPU.
 """
 
 from __future__ import annotations
 
+import collections
 import dataclasses
 import json
 import math
@@ -131,6 +137,14 @@ class GpuBackend:
     def gauge_bytes(self, key):
         dims, nc, rep = key
         return self.hrw.gauge_storage_size(dims, nc, rep, ("f64", self.inner))
+
+    def drop_gauge(self, key):
+        """Release a resident gauge field (its key has no open session)."""
+        with self.lock:
+            g = self.gauges.pop(key, None)
+        if g is not None:
+            g.close()
+            g.storage = None  # its session has closed and synchronised: nothing reads it any more
 
     def session_bytes(self, key, n_slots):
         dims, nc, rep = key
@@ -262,18 +276,20 @@ class _Worker(threading.Thread):
 class Server:
     """Continuous-batching server over a backend.
 
-    hbm_budget: bytes the sessions' workspaces may occupy (the resident gauge
-    fields are counted when first used); n_slots: slots per session;
-    step_iters: CG iterations per session step (requests join and leave
-    between steps)."""
+    hbm_budget: bytes that the resident gauge fields and the sessions'
+    workspaces may occupy together (a gauge field is charged when the first
+    session of its key opens and released when it is evicted); n_slots: slots
+    per session; step_iters: CG iterations per session step (requests join and
+    leave between steps)."""
 
     def __init__(self, backend, hbm_budget: int, n_slots: int = 12, step_iters: int = 20, keep_x: bool = False,
                  idle_close: float = 0.5):
         self.be, self.budget, self.n_slots = backend, int(hbm_budget), int(n_slots)
         self.step_iters, self.keep_x, self.idle_close = int(step_iters), keep_x, idle_close
         self.workers = {}
-        self.used = 0
-        self.gauge_used = 0
+        self.used = 0                           # bytes of open sessions' workspaces
+        self.gauge_used = 0                     # bytes of resident gauge fields
+        self.resident = collections.OrderedDict()  # key -> gauge bytes, least recently used first
         self.session_cost = {}
         self.parked = []          # requests waiting for HBM to open their session
         self.done = []
@@ -292,40 +308,53 @@ class Server:
         return self.session_cost[key]
 
     def _route(self, req):
-        """Admission by footprint: returns 'queued', 'parked' or 'refused'."""
+        """Admission by footprint: returns 'queued', 'parked', 'refused' or 'failed'."""
         key = req.key
         if req.n_rhs > self.n_slots or self._cost(key) + self.be.gauge_bytes(key) > self.budget:
             return "refused"
         w = self.workers.get(key)
         if w is None:
-            need = self._cost(key)
-            if self.used + need > self.budget:
-                self._close_idle(need)
-            if self.used + need > self.budget:
+            need = self._cost(key) + (0 if key in self.resident else self.be.gauge_bytes(key))
+            if self.used + self.gauge_used + need > self.budget:
+                self._make_room(need, key)
+            if self.used + self.gauge_used + need > self.budget:
                 return "parked"
             try:
                 sess = self.be.open_session(key, self.n_slots)
             except Exception as e:
                 req.status, req.t_done = f"failed: {e}", time.perf_counter()
                 return "failed"
-            self.used += need
-            self.peak_used = max(self.peak_used, self.used)
+            if key not in self.resident:
+                self.resident[key] = self.be.gauge_bytes(key)
+                self.gauge_used += self.resident[key]
+            self.used += self._cost(key)
+            self.peak_used = max(self.peak_used, self.used + self.gauge_used)
             w = _Worker(self, key, sess, self.n_slots)
             self.workers[key] = w
             w.start()
+        self.resident.move_to_end(key)
         w.q.put(req)
         return "queued"
 
-    def _close_idle(self, need):
-        now = time.perf_counter()
-        for key, w in list(self.workers.items()):
-            if self.used + need <= self.budget:
-                break
-            if w.idle() and now - w.last_busy > 0:
+    def _make_room(self, need, keep):
+        """Close idle sessions, then evict the gauge fields of keys without a
+        session (least recently used first, never ``keep``), until ``need``
+        more bytes fit or nothing more can go."""
+        for key, w in sorted(self.workers.items(), key=lambda kw: kw[1].last_busy):
+            if self.used + self.gauge_used + need <= self.budget:
+                return
+            if w.idle():
                 w.stop_flag = True
                 w.join()
                 del self.workers[key]
                 self.used -= self._cost(key)
+        for key in list(self.resident):
+            if self.used + self.gauge_used + need <= self.budget:
+                return
+            if key == keep or key in self.workers:
+                continue
+            self.gauge_used -= self.resident.pop(key)
+            self.be.drop_gauge(key)
 
     def run(self, requests: list, realtime: bool = True, on_progress: Callable | None = None) -> dict:
         """Replay the stream (sleeping until each arrival when realtime) and wait
@@ -398,7 +427,7 @@ class Server:
             "service_s": {"p50": float(np.percentile(svc, 50)) if len(svc) else None,
                           "p99": float(np.percentile(svc, 99)) if len(svc) else None},
             "hbm_budget": self.budget,
-            "hbm_peak_sessions": self.peak_used,
+            "hbm_peak": self.peak_used,
             "max_true_rel_resid": max((max(r.true_rel_resid) for r in ok), default=None),
         }
 

@@ -24,6 +24,7 @@ class OracleBackend:
         self.tol, self.per_slot, self.fail_keys = tol, session_bytes_per_slot, set(fail_keys)
         self.theta, self.iters_per_step = theta, iters_per_step
         self.gauges = {}
+        self.dropped = []   # keys whose gauge field the server evicted, in order
 
     def gauge(self, key):
         if key not in self.gauges:
@@ -35,6 +36,10 @@ class OracleBackend:
     def gauge_bytes(self, key):
         dims, nc, rep = key
         return int(np.prod(dims)) * 4 * self.orc.rep_dim(nc, rep) ** 2 * 16 * 2
+
+    def drop_gauge(self, key):
+        self.gauges.pop(key, None)
+        self.dropped.append(key)
 
     def session_bytes(self, key, n_slots):
         return n_slots * self.per_slot

@@ -47,7 +47,43 @@ def test_admission_by_footprint_parks_then_serves():
     srv = serve.Server(be, hbm_budget=budget, n_slots=4)
     rep = srv.run(reqs, realtime=False)
     assert rep["done"] == len(reqs)
-    assert rep["hbm_peak_sessions"] <= budget
+    assert rep["hbm_peak"] <= budget
+
+
+def test_resident_gauges_count_against_the_budget():
+    """Gauge fields are charged when their first session opens: a budget that holds one
+    gauge field and one session serves two keys one after the other, evicting the first
+    key's gauge field for the second, and the peak of sessions plus gauges stays within it."""
+    be = OracleBackend(session_bytes_per_slot=100)
+    a, b = serve.poisson_stream(2, rate=200.0, seed=3, volumes=[(4, 4, 4, 4)], reps=[(2, "fund")], max_rhs=2)
+    b.dims = (2, 4, 4, 4)
+    b.arrival = a.arrival + 1e-3
+    big = max(be.gauge_bytes(a.key), be.gauge_bytes(b.key))
+    budget = 4 * 100 + big
+    srv = serve.Server(be, hbm_budget=budget, n_slots=4)
+    rep = srv.run([a, b], realtime=False)
+    assert rep["done"] == 2 and rep["refused"] == 0
+    assert rep["hbm_peak"] <= budget
+    assert be.dropped == [a.key]                      # evicted to admit the second key
+    assert list(srv.resident) == [b.key] and srv.gauge_used == be.gauge_bytes(b.key)
+    # both gauges fit: nothing is evicted and both stay resident
+    be2 = OracleBackend(session_bytes_per_slot=100)
+    a2, b2 = serve.poisson_stream(2, rate=200.0, seed=3, volumes=[(4, 4, 4, 4)], reps=[(2, "fund")], max_rhs=2)
+    b2.dims = (2, 4, 4, 4)
+    srv2 = serve.Server(be2, hbm_budget=2 * (4 * 100) + be2.gauge_bytes(a2.key) + be2.gauge_bytes(b2.key),
+                        n_slots=4)
+    rep2 = srv2.run([a2, b2], realtime=False)
+    assert rep2["done"] == 2 and be2.dropped == [] and len(srv2.resident) == 2
+
+
+def test_gauge_larger_than_budget_is_refused():
+    be = OracleBackend(session_bytes_per_slot=100)
+    reqs = stream(n=4)
+    k = reqs[0].key
+    srv = serve.Server(be, hbm_budget=be.gauge_bytes(k) + 4 * 100 - 1, n_slots=4)  # session fits, gauge + session do not
+    srv.run([reqs[0]], realtime=False)
+    assert reqs[0].status == "refused"
+    assert srv.gauge_used == 0 and not srv.resident
 
 
 def test_refusals():
