@@ -670,11 +670,15 @@ __global__ void __launch_bounds__(WG) hop_su3_kernel(const HopArgs<S> a)
 // (source, site, row group) items, up to MR_MAX_THREADS per round (see
 // mr_threads), so a round is never partly idle.  Thread t keeps its site and
 // row group in every round; only the source advances.
-template <class S, int NR> struct MRW { static constexpr int value = NR <= 6 ? 3 : 2; };
-template <int NR> struct MRW<double, NR> { static constexpr int value = 2; };
+// Waves per SIMD the instance is compiled for: 32-bit N_R <= 6 fits three
+// (168 VGPRs), except the fused CG update at N_R = 6, whose epilogue operands
+// (self, r, x, p for 4 N_R components) need more registers: at three waves it
+// spilled 28-164 bytes per lane, so it is compiled for two.
+template <class S, int NR, int EPI> struct MRW { static constexpr int value = NR < 6 || (NR == 6 && EPI != EPI_CG) ? 3 : 2; };
+template <int NR, int EPI> struct MRW<double, NR, EPI> { static constexpr int value = 2; };
 
 template <int NR, int RS, class S, bool DAG, int EPI>
-__global__ void __launch_bounds__(MR_MAX_THREADS) __attribute__((amdgpu_waves_per_eu(MRW<S, NR>::value)))
+__global__ void __launch_bounds__(MR_MAX_THREADS) __attribute__((amdgpu_waves_per_eu(MRW<S, NR, EPI>::value)))
 hop_mrhs_kernel(const HopArgs<S> a)
 {
     constexpr int G = NR / RS;

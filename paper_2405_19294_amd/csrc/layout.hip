@@ -165,10 +165,12 @@ __device__ void rep_column(const C64 (&u)[N][N], int b, C64 *col)
 {
     constexpr int NR = REP == 0 ? N : REP == 1 ? N * N - 1 : REP == 2 ? N * (N + 1) / 2 : N * (N - 1) / 2;
     if (REP == 0) {
+        #pragma unroll
         for (int a = 0; a < NR; ++a) col[a] = u[a][b];
     } else if (REP == 3) {
         int l, m;
         nth_pair(N, b, false, l, m);
+        #pragma unroll
         for (int a = 0; a < NR; ++a) {
             int j, k;
             nth_pair(N, a, false, j, k);
@@ -178,6 +180,7 @@ __device__ void rep_column(const C64 (&u)[N][N], int b, C64 *col)
         int l, m;
         nth_pair(N, b, true, l, m);
         const double clm = l == m ? 0.5 : M_SQRT1_2;
+        #pragma unroll
         for (int a = 0; a < NR; ++a) {
             int j, k;
             nth_pair(N, a, true, j, k);
@@ -191,7 +194,9 @@ __device__ void rep_column(const C64 (&u)[N][N], int b, C64 *col)
         if (b < 2 * NP) {
             int j, k;
             nth_pair(N, b < NP ? b : b - NP, false, j, k);
+            #pragma unroll
             for (int r = 0; r < N; ++r)
+                #pragma unroll
                 for (int c = 0; c < N; ++c) {
                     const C64 jk = cmulc(u[r][j], u[c][k]);  // (u_j u_k^+)_rc
                     const C64 kj = cmulc(u[r][k], u[c][j]);
@@ -205,14 +210,18 @@ __device__ void rep_column(const C64 (&u)[N][N], int b, C64 *col)
         } else {
             const int l = b - 2 * NP + 1;
             const double cl = 1.0 / sqrt(2.0 * l * (l + 1));
+            #pragma unroll
             for (int r = 0; r < N; ++r)
+                #pragma unroll
                 for (int c = 0; c < N; ++c) {
                     C64 s = {0, 0};
+                    #pragma unroll
                     for (int m = 0; m < l; ++m) s = cadd(s, cmulc(u[r][m], u[c][m]));
                     s = csub(s, cscale(cmulc(u[r][l], u[c][l]), (double)l));
                     mm[r][c] = cscale(s, cl);
                 }
         }
+        #pragma unroll
         for (int a = 0; a < NR; ++a) {
             double v;
             if (a < NP) {
@@ -227,6 +236,7 @@ __device__ void rep_column(const C64 (&u)[N][N], int b, C64 *col)
                 const int l = a - 2 * NP + 1;
                 const double cl = 1.0 / sqrt(2.0 * l * (l + 1));
                 double s = 0;
+                #pragma unroll
                 for (int m = 0; m < l; ++m) s += mm[m][m].re;
                 v = 2.0 * cl * (s - l * mm[l][l].re);
             }
@@ -238,7 +248,9 @@ __device__ void rep_column(const C64 (&u)[N][N], int b, C64 *col)
 template <int N>
 __device__ inline void load_link(const double *p, C64 (&u)[N][N])
 {
+    #pragma unroll
     for (int r = 0; r < N; ++r)
+        #pragma unroll
         for (int c = 0; c < N; ++c) u[r][c] = {p[2 * (r * N + c)], p[2 * (r * N + c) + 1]};
 }
 
@@ -253,8 +265,10 @@ __global__ void __launch_bounds__(WG) rep_map_kernel(long long n_links, const do
     load_link<N>(uf + l * 2 * N * N, u);
     C64 col[NR];
     double *o = ur + l * 2 * NR * NR;
+    #pragma unroll
     for (int b = 0; b < NR; ++b) {
         rep_column<N, REP>(u, b, col);
+        #pragma unroll
         for (int a = 0; a < NR; ++a) {
             o[2 * (a * NR + b)] = col[a].re;
             o[2 * (a * NR + b) + 1] = col[a].im;
@@ -339,8 +353,10 @@ __global__ void __launch_bounds__(WG) gauge_pack_kernel(Geom g, const double *__
     C64 u[N][N];
     load_link<N>(uf + (s * 4 + mu) * 2 * N * N, u);
     C64 col[NR];
+    #pragma unroll
     for (int b = 0; b < NR; ++b) {
         rep_column<N, REP>(u, b, col);
+        #pragma unroll
         for (int a = 0; a < NR; ++a) {
             // forward slot of x: direction mu, entry (a, b)
             put_all(gb, q, lay(i, mu * NR * NR + a * NR + b, GC), col[a]);
@@ -368,8 +384,13 @@ hipError_t launch_gauge_pack(int nc, int rep, int nr, const Geom &g, const doubl
     const long long total = 8LL * g.half;
     const long long blocks_ = (total + WG - 1) / WG;
     bool ok = dispatch_rep(nc, rep, [&](auto nv, auto rv) {
-        gauge_pack_kernel<decltype(nv)::value, decltype(rv)::value><<<(unsigned)blocks_, WG, 0, st>>>(g, uf, gb);
+        constexpr int N = decltype(nv)::value, REP = decltype(rv)::value;
+        constexpr int NR = REP == 0 ? N : REP == 1 ? N * N - 1 : REP == 2 ? N * (N + 1) / 2 : N * (N - 1) / 2;
+        // only representations with hopping kernels are ever packed (SU(4) adjoint
+        // and symmetric, N_R = 15 and 10, are not)
+        if constexpr (NR <= 8) gauge_pack_kernel<N, REP><<<(unsigned)blocks_, WG, 0, st>>>(g, uf, gb);
     });
+    if (!nr_supported(nr)) return hipErrorInvalidValue;
     if (!ok) return hipErrorInvalidValue;
     return hipGetLastError();
 }

@@ -98,7 +98,10 @@ def test_session_failure_isolated():
 
 def test_served_stream_results_equal_standalone():
     """A small Poisson stream through the continuous-batching server on the GPU:
-    each request's solution equals its standalone solve bit for bit."""
+    each request's solution equals its standalone solve bit for bit, and the
+    oracle, given the request's links and sources copied to the host, finds every
+    source's FP64 true residual within the tolerance and the solution within
+    cond(A) tol of its own FP64 CG solution."""
     from paper_2405_19294_amd import serve
     be = serve.GpuBackend(inner_dtype="f32", tol=1e-10)
     reqs = serve.poisson_stream(10, rate=100.0, seed=9, volumes=[(4, 4, 4, 8), (8, 4, 4, 4)],
@@ -106,8 +109,20 @@ def test_served_stream_results_equal_standalone():
     srv = serve.Server(be, hbm_budget=8 << 30, n_slots=6, step_iters=10, keep_x=True)
     rep = srv.run(reqs, realtime=True)
     assert rep["done"] == len(reqs), rep
+    theta = be.theta
     for r in reqs:
         x, res, rc = be.solve_alone(r)
         assert rc == 0
-        assert np.array_equal(r.x.cpu().numpy(), x.cpu().numpy()), r.rid
+        xs = r.x.cpu().numpy()
+        assert np.array_equal(xs, x.cpu().numpy()), r.rid
         assert max(r.true_rel_resid) <= 1e-10
+        ur = orc.rep_map(r.nc, r.rep, be._links(r.dims, r.nc).cpu().numpy())
+        b = be.sources(r).cpu().numpy()
+        xs = xs.reshape(b.shape)
+        for j in range(r.n_rhs):
+            d = orc.deo(r.dims, ur, r.kappa, xs[j], theta)
+            ax = orc.deo(r.dims, ur, r.kappa, d, theta, dagger=True)
+            assert np.linalg.norm(ax - b[j]) <= 1.01e-10 * np.linalg.norm(b[j]), (r.rid, j)
+            xo, info = orc.cg(r.dims, ur, r.kappa, b[j], theta, orc.SYSTEM_EO, tol=1e-12)
+            lo, hi = orc.lanczos_extremes(info["alpha"], info["beta"])
+            assert np.linalg.norm(xs[j] - xo) <= (hi / lo) * 1e-10 * np.linalg.norm(xo), (r.rid, j)
