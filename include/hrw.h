@@ -11,7 +11,12 @@
  *
  * Conventions (the paper leaves them open; these readings are binding):
  *   - Lattice extents dims[0..3]; dims[0] is time; site index lexicographic
- *     with x3 fastest.  Every extent must be even and >= 2.
+ *     with x3 fastest.  Every extent must be even and >= 2 for every call,
+ *     the full-lattice ones included: the library keeps every field, and the
+ *     hopping blocks of the links, split by parity (Sec. 3.1, even/odd
+ *     preconditioning), and a site's index within its parity is its
+ *     lexicographic index halved only when all extents are even.  Odd
+ *     extents are HRW_EINVAL.
  *   - Euclidean chiral gamma basis, gamma_5 = g0 g1 g2 g3 = diag(1,1,-1,-1):
  *       g0 = [[0,-1],[-1,0]],  gk = [[0,-i s_k],[i s_k,0]]  (2x2 blocks).
  *   - (H psi)(x) = sum_mu ph+_mu(x) (1 - g_mu) U_mu(x) psi(x+mu)
@@ -105,17 +110,19 @@ enum hrw_dtype { HRW_F64 = 0, HRW_F32 = 1, HRW_BF16 = 2, HRW_F16 = 3 };
  * the fundamental one). */
 #define HRW_STORE_FUND_HOP (1u << 4)
 
-/* Storage flag for SU(3) fundamental fields: the caller asserts that every
- * link is special unitary (to the working precision), and single-source hops
- * then read only the first two rows of each link and rebuild the third as
- * conj(u_0 x u_1), 2/3 of the link bytes (the classic two-row compression of
- * SU(3) links; the paper stores full links, Sec. 3.1).  The storage itself is
- * unchanged and keeps all three rows; a link that is not special unitary
- * enters the hops through its rebuilt row, so any deviation from SU(3) goes
- * straight into the result.  Multi-source launches read the stored rows.
- * hrw_gauge_create returns HRW_EUNSUPPORTED for other groups or
- * representations.  Single-source and batched results differ at rounding
- * level, as for HRW_STORE_FUND_HOP. */
+/* Storage flag for SU(3) fundamental fields whose links are special unitary:
+ * single-source hops read only the first two rows of each link and rebuild
+ * the third as conj(u_0 x u_1), 2/3 of the link bytes (the classic two-row
+ * compression of SU(3) links; the paper stores full links, Sec. 3.1).  The
+ * storage itself keeps all three rows (plus 8 bytes for the check below);
+ * multi-source launches read the stored rows.  Because a link that is not
+ * special unitary would enter the hops through its rebuilt row,
+ * hrw_gauge_create measures max |u_2 - conj(u_0 x u_1)| over all links of
+ * u_f (one reduction and a host synchronisation of the stream) and returns
+ * HRW_EINVAL when it exceeds 1e-12 with FP64 storage in the mask, else 4
+ * units of the most precise stored format.  HRW_EUNSUPPORTED for other
+ * groups or representations.  Single-source and batched results differ at
+ * rounding level, as for HRW_STORE_FUND_HOP. */
 #define HRW_STORE_SU3_TWO_ROWS (1u << 5)
 
 /* Linear systems: 0-2 for hrw_cg_solve (Hermitian positive definite normal
@@ -183,7 +190,10 @@ int hrw_gauge_storage_size(const int dims[4], int nc, int rep, unsigned storage_
                            size_t *bytes);
 
 /* Build a resident represented gauge field from fundamental links u_f
- * (device, canonical [V][4][nc][nc] complex FP64).  The representation map
+ * (device, canonical [V][4][nc][nc] complex FP64): the links U_R the fermions
+ * of representation R hop with (Sec. 3.1; Sec. 3.1.2 for their N_R x N_R
+ * size), kept on the device for every later operator and solve (the paper's
+ * fields are likewise resident in GPU memory, Sec. 2.1).  The representation map
  * runs on the device in FP64 and the result is rounded once (ties to even)
  * into each precision in storage_mask (must include HRW_STORE_F64 whenever
  * FP64 operators or solves will be used).  storage: caller-owned device
@@ -204,8 +214,12 @@ int hrw_gauge_info(const hrw_gauge *g, int dims[4], int *nc, int *rep, int *n_r,
                    unsigned *storage_mask);
 
 /* Workspace bytes for the operator applies (params == NULL) or for
- * hrw_cg_solve with these params, for n_rhs right-hand sides.  This is also
- * the per-request device footprint the serving loop admits by. */
+ * hrw_cg_solve with these params, for n_rhs right-hand sides: the packed
+ * fields of the Sec. 3.3 CG (x, r, p, A p and the temporaries of the two
+ * D_hat applications per iteration, Sec. 3.1), the low-precision copies of
+ * a mixed solve and the partial sums of the Sec. 3.2 reductions.  This is
+ * also the per-request device footprint the serving loop admits by.
+ * bytes receives the size; EINVAL / EUNSUPPORTED as hrw_gauge_create. */
 int hrw_workspace_size(const int dims[4], int nc, int rep, int n_rhs,
                        const hrw_solve_params *params, size_t *bytes);
 
@@ -227,7 +241,13 @@ int hrw_hop_eo(const hrw_gauge *g, int out_parity, const double theta[4], int dt
                size_t ws_bytes, void *stream);
 
 /* out_e = D_hat in_e, D_hat = 1 - kappa^2 H_eo H_oe on even sites (dagger: the
- * adjoint, 1 - kappa^2 (H^+)_eo (H^+)_oe).  kappa_per_rhs: host double[n_rhs]. */
+ * adjoint, 1 - kappa^2 (H^+)_eo (H^+)_oe): the even/odd preconditioned
+ * operator of Sec. 3.1, the Schur complement of D on the even sites.
+ * kappa_per_rhs: host double[n_rhs].  in_e / out_e: device canonical even
+ * half fields, n_rhs stacked, must not overlap.  workspace: at least
+ * hrw_workspace_size(..., n_rhs, NULL) bytes (holds the packed fields and the
+ * odd intermediate H_oe in_e).  Enqueued on stream; EINVAL / ENOMEM on bad
+ * arguments, nothing enqueued. */
 int hrw_deo_apply(const hrw_gauge *g, const double *kappa_per_rhs, const double theta[4],
                   int dtype, int n_rhs, int dagger, const double *in_e, double *out_e,
                   void *workspace, size_t ws_bytes, void *stream);

@@ -154,13 +154,39 @@ int hrw_gauge_create(const int dims[4], int nc, int rep, const double *u_f, unsi
             for (int d = 0; d < 4; ++d)
                 if (storage_mask & (1u << d))
                     for (int q = 0; q < 2; ++q) h->fblocks[d][q] = ar.take(gauge_block_elems(g, nc) * dtype_cbytes(d));
+        unsigned long long *defect =
+            (storage_mask & HRW_STORE_SU3_TWO_ROWS) ? (unsigned long long *)ar.take(sizeof(unsigned long long)) : nullptr;
         hipError_t e = launch_gauge_pack(nc, rep, nr, g, u_f, h->blocks, (hipStream_t)stream);
         // the fundamental links in the same hopping layout (representation map = identity)
         if (e == hipSuccess && (storage_mask & HRW_STORE_FUND_HOP))
             e = launch_gauge_pack(nc, HRW_REP_FUND, nc, g, u_f, h->fblocks, (hipStream_t)stream);
+        // two-row links: the hops rebuild row 2 as conj(row 0 x row 1), exact only for special
+        // unitary links, so the field is checked once here (a reduction and a host sync)
+        unsigned long long bits = 0;
+        if (e == hipSuccess && defect) {
+            e = launch_su3_defect(8LL * g.half, u_f, defect, (hipStream_t)stream);  // 4 V links
+            if (e == hipSuccess) e = hipMemcpyAsync(&bits, defect, sizeof bits, hipMemcpyDeviceToHost, (hipStream_t)stream);
+            if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+        }
         if (e != hipSuccess) {
             delete h;
             return fail(HRW_EDEVICE, "gauge packing failed: %s", hipGetErrorString(e));
+        }
+        if (defect) {
+            double d;
+            memcpy(&d, &bits, sizeof d);
+            // FP64 storage: the rebuilt row must match to well below the 1e-13 operator tolerance;
+            // otherwise a few units of the most precise stored format
+            const double tol = (storage_mask & HRW_STORE_F64)   ? 1e-12
+                               : (storage_mask & HRW_STORE_F32) ? 4.0 * 0x1p-24
+                               : (storage_mask & HRW_STORE_F16) ? 4.0 * 0x1p-11
+                                                                : 4.0 * 0x1p-8;
+            if (!(d <= tol)) {
+                delete h;
+                return fail(HRW_EINVAL,
+                            "two-row storage needs special unitary links: max |u_2 - conj(u_0 x u_1)| = %.3e > %.1e",
+                            d, tol);
+            }
         }
         *out = h;
         return HRW_OK;

@@ -246,6 +246,7 @@ int gauge_storage_bytes(const Geom &g, int nc, int nr, unsigned mask, size_t *by
         for (int d = 0; d < 4; ++d)
             if (mask & (1u << d))
                 for (int q = 0; q < 2; ++q) ar.take(gauge_block_elems(g, nc) * dtype_cbytes(d));
+    if (mask & HRW_STORE_SU3_TWO_ROWS) ar.take(sizeof(unsigned long long));  // special-unitarity check
     *bytes = ar.off + 256;
     return HRW_OK;
 }

@@ -192,6 +192,10 @@ hipError_t launch_rep_map(int nc, int rep, long long n_links, const double *uf, 
 hipError_t launch_gauge_pack(int nc, int rep, int nr, const Geom &g, const double *uf,
                              void *const blocks[4][2], hipStream_t st);
 
+// largest |u_2 - conj(u_0 x u_1)| over the SU(3) links uf ([n][3][3] canonical FP64),
+// written to *out as the bit pattern of a double (device; cleared first)
+hipError_t launch_su3_defect(long long n_links, const double *uf, unsigned long long *out, hipStream_t st);
+
 // ------------------------------------------------------------------ vector kernels
 
 // all operate on n_rhs fields of `halves` consecutive packed halves each

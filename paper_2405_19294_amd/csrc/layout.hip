@@ -366,6 +366,46 @@ __global__ void __launch_bounds__(WG) gauge_pack_kernel(Geom g, const double *__
     }
 }
 
+// Largest deviation of an SU(3) link from special unitarity as the two-row hops
+// see it: max over links and entries of |u_2c - conj(u_0a u_1b - u_0b u_1a)|,
+// (a, b) = (c+1, c+2) mod 3.  For a unitary U this is |1 - det U| times the
+// modulus of a row entry, so it catches both non-unitary and U(3) links.  Each
+// workgroup folds its maximum into *out with an integer atomic max (the bit
+// patterns of non-negative doubles order like the numbers; NaN compares
+// larger than any finite value).
+__global__ void __launch_bounds__(WG) su3_defect_kernel(long long n_links, const double *__restrict__ uf,
+                                                        unsigned long long *out)
+{
+    const long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double m = 0;
+    if (l < n_links) {
+        C64 u[3][3];
+        load_link<3>(uf + l * 18, u);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int a = (c + 1) % 3, b = (c + 2) % 3;
+            const C64 x = csub(cmul(u[0][a], u[1][b]), cmul(u[0][b], u[1][a]));
+            const double dr = u[2][c].re - x.re, di = u[2][c].im + x.im;
+            const double d = sqrt(dr * dr + di * di);
+            m = (d > m || d != d) ? d : m;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_down(m, off, 64);
+        m = (o > m || o != o) ? o : m;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+
+hipError_t launch_su3_defect(long long n_links, const double *uf, unsigned long long *out, hipStream_t st)
+{
+    hipError_t e = launch_zero(out, sizeof *out, st);
+    if (e != hipSuccess || n_links == 0) return e;
+    const long long blocks = (n_links + WG - 1) / WG;
+    su3_defect_kernel<<<(unsigned)blocks, WG, 0, st>>>(n_links, uf, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_gauge_pack(int nc, int rep, int nr, const Geom &g, const double *uf,
                              void *const blocks[4][2], hipStream_t st)
 {

@@ -37,10 +37,44 @@ def fp64_close(out, ref):
     assert np.max(np.abs(out - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
-def bound_check(dims, ur_r, psi_r, kappa, out, ref, nr, unit_out):
-    """|out - ref| <= gamma_k (|psi| + kappa |H||psi|) + unit_out |ref| componentwise (a-priori bound of a
-    low-precision D_W evaluation on the rounded inputs; k = 2 N_R + 16)."""
-    bound = orc.gamma_k(2 * nr + 16, U32) * (np.abs(psi_r) + kappa * orc.hop_abs(dims, np.abs(ur_r), np.abs(psi_r)))
-    bound = bound + unit_out * np.abs(ref) + 1e-300
-    excess = np.abs(out - ref) / bound
-    assert np.max(excess) <= 1.0, np.max(excess)
+def hop_rounding_count(nr):
+    """Roundings an FP32 evaluation of D_W = 1 - kappa H applies to one real monomial of
+    a hop term, counted along the kernel's evaluation order: the spin projection (1
+    addition), the boundary phase on a wrap (the phase rounded to FP32, a product and
+    a sum: 3), the complex link row times the half-spinor as a chain of 2 N_R fused
+    multiply-adds (2 N_R), the sum over the 8 directions (7 additions; the first goes
+    into zero) and the epilogue psi - kappa acc (kappa rounded to FP32, a product and
+    a difference: 3).  The self term passes through one rounding."""
+    return 2 * nr + 14
+
+
+def lowprec_bound(dims, ur_r, psi_r, kappa, nr, theta=THETA_TW, dagger=False):
+    """Per real component, the a-priori bound of an FP32 evaluation of D_W (or D_W^+)
+    on the rounded inputs: gamma_m (|psi| + kappa |H||psi|) with |H||psi| the sum of the
+    absolute values of the real monomials (oracle.hop_abs_real) and m from
+    hop_rounding_count (Higham, Accuracy and Stability of Numerical Algorithms, Sec. 3.1,
+    3.6).  Returned as one complex array: real part for the real components, imaginary
+    part for the imaginary ones."""
+    hr = orc.hop_abs_real(dims, ur_r, psi_r, theta, dagger)
+    gm = orc.gamma_k(hop_rounding_count(nr), U32)
+    p = np.asarray(psi_r)
+    return gm * (np.abs(p.real) + kappa * hr.real) + 1j * gm * (np.abs(p.imag) + kappa * hr.imag)
+
+
+def check_real_bound(out, ref, bound, unit_out):
+    """|Re(out - ref)| <= Re bound + unit_out (|Re ref| + Re bound), the same for the
+    imaginary parts; unit_out bounds the final rounding to the output format (0 in FP32
+    arithmetic with FP32 output: the bound already covers it)."""
+    br = bound.real + unit_out * (np.abs(ref.real) + bound.real) + 1e-300
+    bi = bound.imag + unit_out * (np.abs(ref.imag) + bound.imag) + 1e-300
+    d = out - ref
+    excess = max(np.max(np.abs(d.real) / br), np.max(np.abs(d.imag) / bi))
+    assert excess <= 1.0, excess
+    return excess
+
+
+def bound_check(dims, ur_r, psi_r, kappa, out, ref, nr, unit_out, theta=THETA_TW, dagger=False):
+    """A low-precision D_W apply against the oracle's FP64 D_W on the same rounded inputs,
+    per real component within lowprec_bound, plus one rounding to the output format
+    for 16-bit storage (FP32 output: unit_out is the FP32 unit, a harmless extra)."""
+    return check_real_bound(out, ref, lowprec_bound(dims, ur_r, psi_r, kappa, nr, theta, dagger), unit_out)

@@ -121,13 +121,13 @@ def test_fused_rep_map_storage_flag(lib):
 
 
 def test_su3_two_row_storage_flag(lib):
-    """The two-row flag leaves the storage size unchanged (all rows stay stored) and is refused
-    for anything but SU(3) fundamental fields."""
+    """The two-row flag keeps all rows stored (plus one aligned 8-byte slot for the
+    special-unitarity check) and is refused for anything but SU(3) fundamental fields."""
     from paper_2405_19294_amd import hrw
     dims = (4, 4, 4, 4)
     assert hrw.STORE_SU3_TWO_ROWS == 1 << 5
     assert hrw.gauge_storage_size(dims, 3, "fund", ("f64", "f32"), two_rows=True) == \
-        hrw.gauge_storage_size(dims, 3, "fund", ("f64", "f32"))
+        hrw.gauge_storage_size(dims, 3, "fund", ("f64", "f32")) + 8
     for nc, rep in [(2, "fund"), (4, "fund"), (3, "sym"), (3, "adj")]:
         with pytest.raises(hrw.HrwError) as e:
             hrw.gauge_storage_size(dims, nc, rep, ("f64",), two_rows=True)

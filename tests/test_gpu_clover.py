@@ -7,8 +7,11 @@ Tolerances:
     psi_r in FP64 and the difference must sit inside gamma_k (|A_r||psi_r| + kappa |H||psi_r|) +
     u |ref| with k = 4 N_R + 18 (a hop of 2 N_R + 16 operations per component plus a block product
     of 2 N_R), u = 2^-24.
-  * FP32 D_hat_sw (four stages, one of them A^-1): normwise relative error <= 1e-5 against the FP64
-    oracle on unrounded inputs (about 100 u, the stages' componentwise bounds compounded).
+  * FP32 D_hat_sw = A_ee psi - kappa^2 H_eo A_oo^-1 H_oe psi, evaluated in four FP32 stages (plain
+    hop t1 = H_oe psi, stored; t2 = A_oo^-1 t1, stored; s = A_ee psi, stored; s - kappa^2 H_eo t2):
+    per real component against the FP64 value on the rounded input and links, with the FP64 blocks
+    of the oracle, within the stages' a-priori bounds propagated through the later stages
+    (dhat_sw_bound below).
 """
 
 import numpy as np
@@ -18,7 +21,7 @@ import fixtures as fx
 import oracle as orc
 from paper_2405_19294_amd import hrw
 
-from gpu_helpers import THETA_AP, THETA_TW, U32, fp64_close, rel, to_dev
+from gpu_helpers import THETA_AP, THETA_TW, U32, check_real_bound, fp64_close, rel, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -78,7 +81,57 @@ def test_clover_f32_within_bound(case):
     assert np.max(np.abs(out - ref) / bound) <= 1.0
     pe = orc.split_eo(dims, psi)[0]
     out = hrw.dsw_eo_apply(c, to_dev(pe), THETA_TW, "f32").cpu().numpy()
+    pe_r = orc.round_to("f32", pe)
+    ref, bound = dhat_sw_bound(dims, ur_r, orc.clover(dims, ur, KAPPA, CSW), pe_r, nr)
+    check_real_bound(out, ref, bound, 0.0)
     assert rel(out, orc.dsw_eo(dims, ur, KAPPA, CSW, pe, THETA_TW)) <= 1e-5
+
+
+def _absmul(m, x):
+    """Per real component of m x (m [n][k][k], x [n][k], complex): the sum of the absolute
+    values of its real monomials, coded as one complex array (real part for the real
+    components, imaginary part for the imaginary ones)."""
+    mr, mi, xr, xi = np.abs(m.real), np.abs(m.imag), np.abs(x.real), np.abs(x.imag)
+    mul = lambda a, b: np.einsum("sij,sj->si", a, b)
+    return mul(mr, xr) + mul(mi, xi) + 1j * (mul(mi, xr) + mul(mr, xi))
+
+
+def _hop_half_abs(dims, ur, half, out_parity):
+    """oracle.hop_abs_real of an even/odd block: the input half embedded in the full lattice."""
+    z = np.zeros_like(half)
+    full = orc.merge_eo(dims, half, z) if out_parity == 1 else orc.merge_eo(dims, z, half)
+    return orc.split_eo(dims, orc.hop_abs_real(dims, ur, full, THETA_TW))[out_parity]
+
+
+def dhat_sw_bound(dims, ur_r, a64, pe_r, nr):
+    """FP64 reference of D_hat_sw on the rounded input and links, and the per-real-component
+    bound of the FP32 evaluation in the kernel's four stages (Higham, Accuracy and Stability
+    of Numerical Algorithms, Sec. 3.1, 3.6), each stage's own rounding bound gamma_m times the
+    absolute monomial sums of its computed inputs, plus the earlier stages' bounds carried
+    through it:
+      t1 = H_oe psi: the hop (projection 1, phase 3, link row 2 N_R, 7 additions) and the FP32
+           store: m = 2 N_R + 12;
+      t2 = A_oo^-1 t1, s = A_ee psi: the block entries rounded to FP32 (1), a 2 N_R complex
+           product chain (4 N_R) and the store (1): m = 4 N_R + 2;
+      out = s - kappa^2 H_eo t2: the hop and the epilogue (kappa^2 rounded, product,
+           difference): m = 2 N_R + 14."""
+    h, k = pe_r.shape[0], 4 * nr
+    par = orc.parity_of_sites(dims)
+    ae, ainv = a64[par == 0], np.linalg.inv(a64[par == 1])
+    kk = KAPPA * KAPPA
+    g = lambda m: orc.gamma_k(m, U32)
+    cabs = lambda z: np.abs(z.real) + 1j * np.abs(z.imag)
+    flat = lambda z: z.reshape(h, k)
+    t1 = orc.hop_eo(dims, ur_r, pe_r, 1, THETA_TW)
+    e1 = g(2 * nr + 12) * _hop_half_abs(dims, ur_r, pe_r, 1)
+    t2 = np.einsum("sij,sj->si", ainv, flat(t1)).reshape(t1.shape)
+    e2 = (_absmul(ainv, flat(e1)) + g(4 * nr + 2) * _absmul(ainv, flat(cabs(t1) + e1))).reshape(t1.shape)
+    sv = np.einsum("sij,sj->si", ae, flat(pe_r)).reshape(pe_r.shape)
+    e3 = g(4 * nr + 2) * _absmul(ae, flat(pe_r)).reshape(pe_r.shape)
+    ref = sv - kk * orc.hop_eo(dims, ur_r, t2, 0, THETA_TW)
+    e4 = (e3 + kk * _hop_half_abs(dims, ur_r, e2, 0)
+          + g(2 * nr + 14) * (cabs(sv) + e3 + kk * _hop_half_abs(dims, ur_r, cabs(t2) + e2, 0)))
+    return ref, e4
 
 
 def test_clover_multi_rhs_and_limits():

@@ -53,7 +53,7 @@ def test_c2_operators_full_size(c2_field):
         fp64_close(out, orc.deo(C2, ur, KAPPA, pe, THETA_AP, dagger=dagger))
     ur_r, psi_r = orc.round_to("f32", ur), orc.round_to("f32", psi)
     out32 = hrw.dw_apply(g, KAPPA, to_dev(psi), THETA_AP, "f32").cpu().numpy()
-    bound_check(C2, ur_r, psi_r, KAPPA, out32, orc.dw(C2, ur_r, KAPPA, psi_r, THETA_AP), 3, U32)
+    bound_check(C2, ur_r, psi_r, KAPPA, out32, orc.dw(C2, ur_r, KAPPA, psi_r, THETA_AP), 3, 0.0, THETA_AP)
 
 
 def test_c2_solve_residual_by_oracle(c2_field):

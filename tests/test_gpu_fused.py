@@ -6,7 +6,8 @@ Tolerances:
     the rows of U_R are built from U in FP64 and R(U^+) = R(U)^+ holds to the unitarity of U.
   * FP32 arithmetic on FP32 / BF16 / FP16 storage: the oracle applies FP64 D with U_R = R(U_r), the
     representation map of the rounded stored fundamental links U_r, to the rounded input.  Besides
-    the hop's own bound gamma_k (|psi| + kappa |H||psi|) (k = 2 N_R + 16, u = 2^-24) the kernel's
+    the hop's own bound, per real component gamma_m (|psi| + kappa |H||psi|) with m = 2 N_R + 14
+    and u = 2^-24 (gpu_helpers.lowprec_bound), the kernel's
     evaluation of each U_R entry from U_r adds at most 2 gamma_5 (every entry is a sum of at most
     four products of entries of modulus <= 1), which enters as kappa 2 gamma_5 |H|_1 |psi| with
     |H|_1 the hop with every link entry set to 1; plus one rounding of the stored output.
@@ -21,7 +22,8 @@ import fixtures as fx
 import oracle as orc
 from paper_2405_19294_amd import hrw
 
-from gpu_helpers import THETA_AP, THETA_TW, U32, U_BF16, U_F16, bound_check, fp64_close, rel, to_dev
+from gpu_helpers import (THETA_AP, THETA_TW, U32, U_BF16, U_F16, bound_check, check_real_bound, fp64_close,
+                         lowprec_bound, rel, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -86,11 +88,9 @@ def test_fused_low_precision_within_bound(case, dtype):
     ur_ref = orc.rep_map(nc, rep, uf_r)
     ref = orc.dw(dims, ur_ref, kappa, psi_r, THETA_TW)
     ones = np.ones_like(np.abs(ur_ref))
-    bound = (orc.gamma_k(2 * nr + 16, U32) * (np.abs(psi_r) + kappa * orc.hop_abs(dims, np.abs(ur_ref), np.abs(psi_r)))
-             + 2 * orc.gamma_k(5, U32) * kappa * orc.hop_abs(dims, ones, np.abs(psi_r))
-             + unit_out * np.abs(ref) + 1e-300)
-    excess = np.max(np.abs(out - ref) / bound)
-    assert excess <= 1.0, excess
+    rows = 2 * orc.gamma_k(5, U32) * kappa * orc.hop_abs(dims, ones, np.abs(psi_r))
+    check_real_bound(out, ref, lowprec_bound(dims, ur_ref, psi_r, kappa, nr) + rows * (1 + 1j),
+                     0.0 if dtype == "f32" else unit_out)
     assert rel(out, orc.dw(dims, ur, kappa, psi, THETA_TW)) < {"f32": 1e-6, "bf16": 2e-2, "f16": 3e-3}[dtype]
 
 

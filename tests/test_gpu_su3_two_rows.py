@@ -6,7 +6,8 @@ Tolerances:
     the rebuilt row conj(u_0 x u_1) equals the stored one to the unitarity of the FP64 links.
   * FP32 arithmetic on FP32 / BF16 / FP16 storage: the oracle applies FP64 D with the rounded stored
     links U_r (all three rows) to the rounded input.  Besides the hop's own bound
-    gamma_k (|psi| + kappa |H||psi|) (k = 2 N_R + 16, u = 2^-24), the rebuilt row differs from the
+    gamma_m (|psi| + kappa |H||psi|) per real component (m = 2 N_R + 14, u = 2^-24,
+    gpu_helpers.lowprec_bound), the rebuilt row differs from the
     rounded stored one: every entry is a difference of two products of rounded entries of modulus
     <= 1, so |row_2' - round(row_2)| <= 4 sqrt(2) u_s + sqrt(2) u_s + 2 gamma_2 <= 8 u_s + 8 u per
     entry (u_s the storage unit roundoff), which enters as kappa (8 u_s + 8 u) |H|_1 |psi| with |H|_1
@@ -20,7 +21,7 @@ import fixtures as fx
 import oracle as orc
 from paper_2405_19294_amd import hrw
 
-from gpu_helpers import THETA_AP, THETA_TW, U32, U_BF16, U_F16, fp64_close, rel, to_dev
+from gpu_helpers import THETA_AP, THETA_TW, U32, U_BF16, U_F16, check_real_bound, fp64_close, lowprec_bound, rel, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -73,11 +74,9 @@ def test_two_rows_low_precision_within_bound(case, dtype):
     out = hrw.dw_apply(g, kappa, to_dev(psi), THETA_TW, dtype).cpu().numpy()
     ref = orc.dw(dims, ur_r, kappa, psi_r, THETA_TW)
     ones = np.ones_like(np.abs(ur_r))
-    bound = (orc.gamma_k(2 * 3 + 16, U32) * (np.abs(psi_r) + kappa * orc.hop_abs(dims, np.abs(ur_r), np.abs(psi_r)))
-             + (8 * UNIT[dtype] + 8 * U32) * kappa * orc.hop_abs(dims, ones, np.abs(psi_r))
-             + UNIT[dtype] * np.abs(ref) + 1e-300)
-    excess = np.max(np.abs(out - ref) / bound)
-    assert excess <= 1.0, excess
+    row2 = (8 * UNIT[dtype] + 8 * U32) * kappa * orc.hop_abs(dims, ones, np.abs(psi_r))
+    check_real_bound(out, ref, lowprec_bound(dims, ur_r, psi_r, kappa, 3) + row2 * (1 + 1j),
+                     0.0 if dtype == "f32" else UNIT[dtype])
     assert rel(out, orc.dw(dims, ur, kappa, psi, THETA_TW)) < {"f32": 1e-6, "bf16": 2e-2, "f16": 3e-3}[dtype]
 
 
@@ -124,3 +123,22 @@ def test_two_rows_solves():
         assert rc == 0, res
         r = rel(orc.deo(dims, ur, kappa, y.cpu().numpy(), THETA_AP), b)
         assert r <= 1.01e-10 and abs(r - res[0]["true_rel_resid"]) <= 1e-3 * r + 1e-16
+
+
+def test_two_rows_refuse_links_that_are_not_special_unitary():
+    """Gauge creation with two-row storage measures max |u_2 - conj(u_0 x u_1)| and refuses a
+    field with a U(3) link (unitary, det = exp(3 i a) != 1) or a non-unitary field beyond the
+    tolerance of the stored formats; the same links without the flag are accepted."""
+    dims = (4, 4, 2, 4)
+    uf = fx.gauge_field(dims, 3, "haar", seed=27)
+    hrw.Gauge(dims, 3, "fund", to_dev(uf), dtypes=("f64",), two_rows=True).close()
+    u3 = uf.copy()
+    u3[5, 2] *= np.exp(0.15j)                 # one link leaves SU(3) for U(3)
+    stretched = uf * (1 + 1e-9)               # every link 1e-9 off unitarity
+    for bad, dtypes in ((u3, ("f64",)), (u3, ("f32",)), (stretched, ("f64", "f32"))):
+        with pytest.raises(hrw.HrwError) as e:
+            hrw.Gauge(dims, 3, "fund", to_dev(bad), dtypes=dtypes, two_rows=True)
+        assert e.value.code == hrw.EINVAL and "special unitary" in str(e.value)
+        hrw.Gauge(dims, 3, "fund", to_dev(bad), dtypes=dtypes).close()
+    # 1e-9 is within four FP32 units: accepted when only FP32 links are stored
+    hrw.Gauge(dims, 3, "fund", to_dev(stretched), dtypes=("f32",), two_rows=True).close()
