@@ -252,6 +252,30 @@ int hrw_deo_apply(const hrw_gauge *g, const double *kappa_per_rhs, const double 
                   int dtype, int n_rhs, int dagger, const double *in_e, double *out_e,
                   void *workspace, size_t ws_bytes, void *stream);
 
+/* Bytes of the static device scratch behind hrw_deo_apply_noalloc (320 MiB:
+ * D_hat of one FP64 source at 32^4 with N_R = 3, 302 MB, fits). */
+#define HRW_NOALLOC_SCRATCH_BYTES (320ull << 20)
+
+/* hrw_deo_apply without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same D_hat, computed by the same
+ * kernels bit for bit, with its temporaries (three packed half fields of
+ * dtype per source and the coefficients) in a file-scope device array of
+ * HRW_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends.  The call allocates nothing and calls no
+ * allocating routine.  It needs three buffers of n_rhs P bytes and 512
+ * bytes of coefficients, each rounded up to 256 bytes, P = (V/2 rounded up
+ * to 64 sites) x 4 N_R x (16, 8, 4, 4 bytes for F64, F32, BF16, F16); a call
+ * needing more than HRW_NOALLOC_SCRATCH_BYTES is HRW_ENOMEM, nothing enqueued.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (two streams, two host threads) race and corrupt each other's results;
+ * serialise them.  Nothing needs clearing between calls (every scratch entry
+ * a call reads it writes first).  Other arguments, errors and stream
+ * ordering as hrw_deo_apply. */
+int hrw_deo_apply_noalloc(const hrw_gauge *g, const double *kappa_per_rhs, const double theta[4],
+                          int dtype, int n_rhs, int dagger, const double *in_e, double *out_e,
+                          void *stream);
+
 /* Conjugate gradient (Sec. 3.3) for n_rhs independent systems sharing the
  * gauge field, each with its own kappa (host double[n_rhs]).  b and x are
  * device canonical fields: half-parity (even) for HRW_SYS_DDAG_D_EO, full

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <exception>
+#include <mutex>
 #include <new>
 
 #include "engine.h"
@@ -84,6 +85,36 @@ int guarded(F &&f)
     } catch (...) {
         return fail(HRW_EDEVICE, "internal error");
     }
+}
+
+// Device scratch of hrw_deo_apply_noalloc: a file-scope array, so that entry
+// point never allocates.  Each GPU the library runs on holds its own copy from
+// module load until the process ends.  Host code must not use the array's name
+// as a device address (it is a host-side stand-in); it uses the address
+// hipGetSymbolAddress returns for the current device instead.
+static __device__ __align__(256) unsigned char scratch[HRW_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES];
+
+// the current device's address of `scratch`, looked up on its first use on that device
+int scratch_address(void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(HRW_EDEVICE, "hipGetDevice failed: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(HRW_EDEVICE, "device %d outside 0..%d", dev, MAX_DEVICES - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(HRW_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return HRW_OK;
 }
 
 }  // namespace
@@ -280,6 +311,24 @@ int hrw_deo_apply(const hrw_gauge *g, const double *kappa_per_rhs, const double 
         if (!kappa_per_rhs || !workspace) return fail(HRW_EINVAL, "null kappa or workspace");
         return deo_apply(g, kappa_per_rhs, theta, dtype, n_rhs, dagger, in_e, out_e, workspace, ws_bytes,
                          (hipStream_t)stream);
+    });
+}
+
+int hrw_deo_apply_noalloc(const hrw_gauge *g, const double *kappa_per_rhs, const double theta[4], int dtype,
+                          int n_rhs, int dagger, const double *in_e, double *out_e, void *stream)
+{
+    return guarded([&] {
+        int rc;
+        if ((rc = check_apply(g, dtype, n_rhs, in_e, out_e))) return rc;
+        if (!kappa_per_rhs) return fail(HRW_EINVAL, "null kappa");
+        const size_t need = deo_compact_bytes(g, dtype, n_rhs);
+        if (need > HRW_NOALLOC_SCRATCH_BYTES)
+            return fail(HRW_ENOMEM, "needs %zu bytes of scratch, the static scratch holds %zu", need,
+                        (size_t)HRW_NOALLOC_SCRATCH_BYTES);
+        void *buf = nullptr;
+        if ((rc = scratch_address(&buf))) return rc;
+        return deo_apply_compact(g, kappa_per_rhs, theta, dtype, n_rhs, dagger, in_e, out_e, buf,
+                                 HRW_NOALLOC_SCRATCH_BYTES, (hipStream_t)stream);
     });
 }
 

@@ -142,6 +142,12 @@ int hop_eo_apply(const hrw_gauge *g, int out_parity, const double theta[4], int 
                  int dagger, const double *in, double *out, void *ws, size_t ws_bytes, hipStream_t st);
 int deo_apply(const hrw_gauge *g, const double *kappa, const double theta[4], int dt, int n_rhs,
               int dagger, const double *in, double *out, void *ws, size_t ws_bytes, hipStream_t st);
+// D_hat in a caller-provided buffer laid out by the compact plan (three half
+// fields of dtype dt per source and the coefficients); deo_compact_bytes is
+// what that plan needs from a 256-byte aligned base
+size_t deo_compact_bytes(const hrw_gauge *g, int dt, int n_rhs);
+int deo_apply_compact(const hrw_gauge *g, const double *kappa, const double theta[4], int dt, int n_rhs,
+                      int dagger, const double *in, double *out, void *buf, size_t buf_bytes, hipStream_t st);
 int cg_solve(const hrw_gauge *g, const hrw_solve_params *p, int n_rhs, const double *kappa,
              const double *b, double *x, hrw_solve_result *res, void *ws, size_t ws_bytes,
              hipStream_t st);

@@ -356,19 +356,19 @@ int hop_eo_apply(const hrw_gauge *g, int out_parity, const double theta[4], int 
     return HRW_OK;
 }
 
-int deo_apply(const hrw_gauge *g, const double *kappa, const double theta[4], int dt, int n_rhs,
-              int dagger, const double *in, double *out, void *ws, size_t ws_bytes, hipStream_t st)
+// D_hat on caller-provided device buffers: f0 (packed input), f1 (odd
+// intermediate), f2 (packed output), each n_rhs half fields of dtype dt, and
+// coef (MAX_RHS doubles).  Every entry these kernels read is written first in
+// the same call, so the buffers need no clearing between calls.
+static int deo_apply_on(const hrw_gauge *g, const double *kappa, const double theta[4], int dt, int n_rhs,
+                        int dagger, const double *in, double *out, void *f0, void *f1, void *f2, double *coef,
+                        hipStream_t st)
 {
-    Arena ar(ws, ws_bytes);
-    ApplyPlan pl;
-    plan_apply(ar, g->g, g->nr, n_rhs, pl);
-    int rc = check_ws(ar, ws_bytes);
-    if (rc) return rc;
     const size_t H = half_elems(g->g, g->nr);
-    HRW_HIP(launch_pack_spinor(dt, g->nr, g->g, false, 0, n_rhs, in, pl.f[0], nullptr, H, st));
+    HRW_HIP(launch_pack_spinor(dt, g->nr, g->g, false, 0, n_rhs, in, f0, nullptr, H, st));
     double k2[MAX_RHS];
     for (int j = 0; j < n_rhs; ++j) k2[j] = kappa[j] * kappa[j];
-    rc = set_device_doubles(pl.coef, k2, n_rhs, st);
+    int rc = set_device_doubles(coef, k2, n_rhs, st);
     if (rc) return rc;
     const Phases ph = make_phases(theta);
     HopCall c;
@@ -378,8 +378,8 @@ int deo_apply(const hrw_gauge *g, const double *kappa, const double theta[4], in
     c.rstride = H;
     c.parity = 1;
     c.epi = EPI_PLAIN;
-    c.in[0] = pl.f[0];
-    c.out[1] = pl.f[1];
+    c.in[0] = f0;
+    c.out[1] = f1;
     rc = run_hop(g, ph, c, st);
     if (rc) return rc;
     HopCall d;
@@ -389,14 +389,55 @@ int deo_apply(const hrw_gauge *g, const double *kappa, const double theta[4], in
     d.rstride = H;
     d.parity = 0;
     d.epi = EPI_AXPY;
-    d.in[1] = pl.f[1];
-    d.self[0] = pl.f[0];
-    d.out[0] = pl.f[2];
-    d.coef = pl.coef;
+    d.in[1] = f1;
+    d.self[0] = f0;
+    d.out[0] = f2;
+    d.coef = coef;
     rc = run_hop(g, ph, d, st);
     if (rc) return rc;
-    HRW_HIP(launch_unpack_spinor(dt, g->nr, g->g, false, 0, n_rhs, pl.f[2], nullptr, H, out, st));
+    HRW_HIP(launch_unpack_spinor(dt, g->nr, g->g, false, 0, n_rhs, f2, nullptr, H, out, st));
     return HRW_OK;
+}
+
+int deo_apply(const hrw_gauge *g, const double *kappa, const double theta[4], int dt, int n_rhs,
+              int dagger, const double *in, double *out, void *ws, size_t ws_bytes, hipStream_t st)
+{
+    Arena ar(ws, ws_bytes);
+    ApplyPlan pl;
+    plan_apply(ar, g->g, g->nr, n_rhs, pl);
+    int rc = check_ws(ar, ws_bytes);
+    if (rc) return rc;
+    return deo_apply_on(g, kappa, theta, dt, n_rhs, dagger, in, out, pl.f[0], pl.f[1], pl.f[2], pl.coef, st);
+}
+
+// the compact plan of the allocation-free D_hat: three half fields of dtype dt
+// per source and the coefficients, nothing else
+static void plan_deo_compact(Arena &ar, const Geom &g, int nr, int dt, int n_rhs, void *f[3], double **coef)
+{
+    const size_t bytes = half_elems(g, nr) * n_rhs * dtype_cbytes(dt);
+    for (int k = 0; k < 3; ++k) f[k] = ar.take(bytes);
+    *coef = (double *)ar.take(sizeof(double) * MAX_RHS);
+}
+
+size_t deo_compact_bytes(const hrw_gauge *g, int dt, int n_rhs)
+{
+    Arena ar(nullptr, 0);
+    void *f[3];
+    double *coef;
+    plan_deo_compact(ar, g->g, g->nr, dt, n_rhs, f, &coef);
+    return ar.off;
+}
+
+int deo_apply_compact(const hrw_gauge *g, const double *kappa, const double theta[4], int dt, int n_rhs,
+                      int dagger, const double *in, double *out, void *buf, size_t buf_bytes, hipStream_t st)
+{
+    Arena ar(buf, buf_bytes);
+    void *f[3];
+    double *coef;
+    plan_deo_compact(ar, g->g, g->nr, dt, n_rhs, f, &coef);
+    int rc = check_ws(ar, buf_bytes);
+    if (rc) return rc;
+    return deo_apply_on(g, kappa, theta, dt, n_rhs, dagger, in, out, f[0], f[1], f[2], coef, st);
 }
 
 // ------------------------------------------------------------------ CG

@@ -65,6 +65,7 @@ SIGNATURES = {
     "hrw_dw_apply": (I, [P, D, DP, I, I, I, P, P, P, SZ, P]),
     "hrw_hop_eo": (I, [P, I, DP, I, I, I, P, P, P, SZ, P]),
     "hrw_deo_apply": (I, [P, DP, DP, I, I, I, P, P, P, SZ, P]),
+    "hrw_deo_apply_noalloc": (I, [P, DP, DP, I, I, I, P, P, P]),
     "hrw_cg_solve": (I, [P, ctypes.POINTER(SolveParams), I, DP, P, P, ctypes.POINTER(SolveResult), P, SZ, P]),
     "hrw_bicgstab_solve": (I, [P, ctypes.POINTER(SolveParams), I, DP, P, P, ctypes.POINTER(SolveResult), P, SZ,
                                P]),
@@ -268,6 +269,18 @@ def deo_apply(g: Gauge, kappa, psi_e: torch.Tensor, theta=(0, 0, 0, 0), dtype="f
     _check(load().hrw_deo_apply(g.handle, _doubles(ks), _doubles(theta), DTYPES[dtype], n, int(bool(dagger)),
                                 _dev_field(psi_e, "psi"), _dev_field(out, "out"), ws.buf.data_ptr(), ws.nbytes,
                                 _stream(stream)))
+    return out
+
+
+def deo_apply_noalloc(g: Gauge, kappa, psi_e: torch.Tensor, out: torch.Tensor, theta=(0, 0, 0, 0), dtype="f64",
+                      dagger=False, stream=None) -> torch.Tensor:
+    """deo_apply with the library's static device scratch instead of a workspace: the call
+    allocates nothing (out is the caller's).  Calls that overlap on one GPU race."""
+    n = _n_rhs(psi_e, g.volume // 2 * 4 * g.nr)
+    ks = [kappa] * n if isinstance(kappa, (int, float)) else list(kappa)
+    _check(load().hrw_deo_apply_noalloc(g.handle, _doubles(ks), _doubles(theta), DTYPES[dtype], n,
+                                        int(bool(dagger)), _dev_field(psi_e, "psi"), _dev_field(out, "out"),
+                                        _stream(stream)))
     return out
 
 
