@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the four-representation operator table and the multi-source rows")
     ap.add_argument("--cpu-iters", type=int, default=0, help="oracle CG iterations in the CPU sample (0 = auto)")
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "ops", "bicgstab", "clover"])
     args = ap.parse_args()
@@ -195,6 +197,14 @@ def main():
                                       out["hbm_copy_reference"]["gbs"])
     out["bicgstab"] = bicgstab_rows(torch, hrw, dev, dims, nc, rep, uf_d, b_d, kappa, theta, out["value"],
                                     max(2, min(args.steps, 5)))
+    # after the timed steps: the operator table over the four representations and the
+    # multi-source workload's ratios (context; the timed region above is unchanged)
+    if not args.no_extras:
+        del x_d, ws
+        torch.cuda.empty_cache()
+        out["operators_4_reps"] = four_rep_table(torch, hrw, dev, kappa, theta, out["hbm_copy_reference"]["gbs"])
+        c4 = c4_rows(torch, hrw, dev, 1, extras=False)
+        out["c4_multi_source"] = {"fp64_cg": c4["fp64_cg"], "multi_source": c4["multi_source"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dims, uf, b, kappa, theta, r["iters"], args.cpu_iters)
     print(json.dumps(out), flush=True)
@@ -628,18 +638,17 @@ def workload_c3(args):
                   "reliable_every": 50, "reliable_delta": hrw.RELIABLE_DELTA, "tol": 1e-10}, roof, cases=cases)
 
 
-def workload_c4(args):
-    """SU(3) sym 32^4, 12 and 24 point-smeared sources: multi-source mixed CG vs plain FP64 CG."""
-    import torch
-
+def c4_rows(torch, hrw, dev, steps, extras=True):
+    """SU(3) sym 32^4, 12 and 24 point-smeared sources: multi-source mixed CG (FP32 inner,
+    FP64 reliable updates) against two FP64 CG baselines on the same system, one source at a
+    time and all 24 batched (links shared).  extras: also FP16 storage and BiCGstab rows."""
     import fixtures as fx
-    from paper_2405_19294_amd import hrw
-    dev = torch.device("cuda:0")
     dims, kappa, theta = (32, 32, 32, 32), 0.135, (np.pi, 0, 0, 0)
     t0 = time.time()
-    uf = torch.from_numpy(fx.gauge_field(dims, 3, "thermal", seed=6, eps=0.3)).to(dev)
+    uf_h = fx.gauge_field(dims, 3, "thermal", seed=6, eps=0.3)
+    uf = torch.from_numpy(uf_h).to(dev)
     g = hrw.Gauge(dims, 3, "sym", uf, dtypes=("f64", "f32"))
-    g_fused = hrw.Gauge(dims, 3, "sym", uf, dtypes=("f64",), fused=True)
+    g_fused = hrw.Gauge(dims, 3, "sym", uf, dtypes=("f64",), fused=True) if extras else None
     del uf
     nmax = 24
     srcs = torch.empty((nmax, fx.volume(dims) // 2, 4, g.nr), dtype=torch.complex128, device=dev)
@@ -649,16 +658,19 @@ def workload_c4(args):
     log(f"c4 inputs in {time.time() - t0:.1f}s")
     # plain FP64 CG, one source at a time (the reference rate)
     prm64 = hrw.solve_params(tol=1e-10, max_iter=20000, system="ddag_d_eo", inner_dtype="f64", theta=theta)
-    x64, res64, per64, _ = _solve_timed(hrw, torch, g, srcs[0:1].contiguous(), kappa, prm64, max(1, args.steps // 2), 1)
+    x64, res64, per64, _ = _solve_timed(hrw, torch, g, srcs[0:1].contiguous(), kappa, prm64, steps, 1)
     fp64_rate = 1.0 / per64
-    # the same FP64 CG batched over all sources (links shared): context only
+    # the same FP64 CG batched over all sources (links shared through LDS)
     _, res64b, per64b, _ = _solve_timed(hrw, torch, g, srcs, kappa, prm64, 1, 0)
-    # FP64 CG, one source at a time, with the representation map fused into the hop (the faster
-    # FP64 single-source path; the ratios below are also given against it)
-    _, res64f, per64f, _ = _solve_timed(hrw, torch, g_fused, srcs[0:1].contiguous(), kappa, prm64,
-                                        max(1, args.steps // 2), 1)
-    g_fused.close()
-    fp64_fused_rate = 1.0 / per64f
+    fp64_batched_rate = nmax / per64b
+    fp64 = {"solves_per_s": round(fp64_rate, 3), "iters": res64[0]["iters"],
+            "batched_24_rhs_solves_per_s": round(fp64_batched_rate, 3),
+            "batched_max_iters": max(q["iters"] for q in res64b)}
+    if extras:
+        # FP64 CG, one source at a time, with the representation map fused into the hop
+        _, res64f, per64f, _ = _solve_timed(hrw, torch, g_fused, srcs[0:1].contiguous(), kappa, prm64, steps, 1)
+        g_fused.close()
+        fp64["fused_rep_map_solves_per_s"] = round(1.0 / per64f, 3)
     out = {}
     roof = None
     for n in (12, 24):
@@ -666,44 +678,62 @@ def workload_c4(args):
                                reliable_every=50, reliable_delta=hrw.RELIABLE_DELTA["f32"], theta=theta)
         b = srcs[:n].contiguous()
         hrw.timing_enable(True)
-        x, res, per, lat = _solve_timed(hrw, torch, g, b, kappa, prm, max(1, args.steps // 2), 1)
+        x, res, per, lat = _solve_timed(hrw, torch, g, b, kappa, prm, steps, 1)
         r = _hop_roofline(hrw, f"hop_mrhs_kernel<N_R=6, float, {n} sources>")
         hrw.timing_enable(False)
         err0 = float((torch.linalg.vector_norm(x[0] - x64[0]) / torch.linalg.vector_norm(x64[0])).item())
         out[n] = {"rhs_solves_per_s": round(n / per, 3), "ms_per_batch": round(per * 1e3, 1),
                   "speedup_vs_fp64_cg": round(n / per / fp64_rate, 2),
-                  "speedup_vs_fp64_cg_fused_rep_map": round(n / per / fp64_fused_rate, 2),
+                  "speedup_vs_fp64_cg_batched": round(n / per / fp64_batched_rate, 2),
                   "max_iters": max(q["iters"] for q in res),
+                  "max_reliable_updates": max(q["reliable_updates"] for q in res),
                   "max_true_rel_resid": max(q["true_rel_resid"] for q in res),
                   "rel_error_vs_fp64_source0": err0, "hop_roofline": r}
+        if extras:
+            out[n]["speedup_vs_fp64_cg_fused_rep_map"] = round(n / per * 1.0 / fp64["fused_rep_map_solves_per_s"], 2)
         log(f"c4 n={n}: {out[n]}")
         roof = r
-    # the same 24 sources with FP16 storage of the inner fields (FP32 arithmetic)
-    prm16 = hrw.solve_params(tol=1e-10, max_iter=20000, system="ddag_d_eo", inner_dtype="f16",
-                             reliable_every=50, reliable_delta=hrw.RELIABLE_DELTA["f16"], theta=theta)
-    g16 = hrw.Gauge(dims, 3, "sym", torch.from_numpy(fx.gauge_field(dims, 3, "thermal", seed=6, eps=0.3)).to(dev),
-                    dtypes=("f64", "f16"))
-    x16, res16, per16, _ = _solve_timed(hrw, torch, g16, srcs, kappa, prm16, max(1, args.steps // 2), 1)
-    f16_row = {"rhs_solves_per_s": round(nmax / per16, 3), "ms_per_batch": round(per16 * 1e3, 1),
-               "speedup_vs_fp64_cg": round(nmax / per16 / fp64_rate, 2),
-               "max_iters": max(q["iters"] for q in res16),
-               "max_true_rel_resid": max(q["true_rel_resid"] for q in res16),
-               "rel_error_vs_fp64_source0": float((torch.linalg.vector_norm(x16[0] - x64[0]) /
-                                                   torch.linalg.vector_norm(x64[0])).item())}
-    log(f"c4 n=24 f16 storage: {f16_row}")
-    g16.close()
-    bicg = _c4_bicgstab(hrw, torch, g, srcs, kappa, theta, max(1, args.steps // 2))
-    return _line(out[24]["rhs_solves_per_s"], "rhs-solves/s", max(1, args.steps // 2), 1, out[24]["ms_per_batch"],
-                 "f32", {"workload": "su3_sym_32^4_multi_source_mixed_cg", "lattice": list(dims), "kappa": kappa,
-                         "sources": "point-smeared (Gaussian spatial profile, width 2), 12 and 24",
+    rows = {"fp64_cg": fp64, "multi_source": out, "roofline": roof}
+    if extras:
+        # the same 24 sources with FP16 storage of the inner fields (FP32 arithmetic)
+        prm16 = hrw.solve_params(tol=1e-10, max_iter=20000, system="ddag_d_eo", inner_dtype="f16",
+                                 reliable_every=50, reliable_delta=hrw.RELIABLE_DELTA["f16"], theta=theta)
+        g16 = hrw.Gauge(dims, 3, "sym", torch.from_numpy(uf_h).to(dev), dtypes=("f64", "f16"))
+        x16, res16, per16, _ = _solve_timed(hrw, torch, g16, srcs, kappa, prm16, steps, 1)
+        rows["multi_source_24_f16_storage"] = {
+            "rhs_solves_per_s": round(nmax / per16, 3), "ms_per_batch": round(per16 * 1e3, 1),
+            "speedup_vs_fp64_cg": round(nmax / per16 / fp64_rate, 2),
+            "speedup_vs_fp64_cg_batched": round(nmax / per16 / fp64_batched_rate, 2),
+            "max_iters": max(q["iters"] for q in res16),
+            "max_true_rel_resid": max(q["true_rel_resid"] for q in res16),
+            "rel_error_vs_fp64_source0": float((torch.linalg.vector_norm(x16[0] - x64[0]) /
+                                                torch.linalg.vector_norm(x64[0])).item())}
+        log(f"c4 n=24 f16 storage: {rows['multi_source_24_f16_storage']}")
+        g16.close()
+        rows["bicgstab_propagators"] = _c4_bicgstab(hrw, torch, g, srcs, kappa, theta, steps)
+    g.close()
+    del srcs
+    torch.cuda.empty_cache()
+    return rows
+
+
+def workload_c4(args):
+    """SU(3) sym 32^4, 12 and 24 point-smeared sources: multi-source mixed CG vs plain FP64 CG."""
+    import torch
+
+    from paper_2405_19294_amd import hrw
+    dev = torch.device("cuda:0")
+    steps = max(1, args.steps // 2)
+    rows = c4_rows(torch, hrw, dev, steps, extras=True)
+    out = rows["multi_source"]
+    return _line(out[24]["rhs_solves_per_s"], "rhs-solves/s", steps, 1, out[24]["ms_per_batch"],
+                 "f32", {"workload": "su3_sym_32^4_multi_source_mixed_cg", "lattice": [32, 32, 32, 32],
+                         "kappa": 0.135, "sources": "point-smeared (Gaussian spatial profile, width 2), 12 and 24",
                          "inner": "f32", "reliable_every": 50, "reliable_delta": hrw.RELIABLE_DELTA["f32"],
-                         "tol": 1e-10}, roof,
-                 fp64_cg={"solves_per_s": round(fp64_rate, 3), "iters": res64[0]["iters"],
-                          "fused_rep_map_solves_per_s": round(fp64_fused_rate, 3),
-                          "batched_24_rhs_solves_per_s": round(nmax / per64b, 3),
-                          "batched_max_iters": max(q["iters"] for q in res64b)},
-                 multi_source=out, multi_source_24_f16_storage=f16_row, bicgstab_propagators=bicg,
-                 hbm_copy_reference=copy_reference(torch, dev))
+                         "tol": 1e-10}, rows["roofline"],
+                 fp64_cg=rows["fp64_cg"], multi_source=out,
+                 multi_source_24_f16_storage=rows["multi_source_24_f16_storage"],
+                 bicgstab_propagators=rows["bicgstab_propagators"], hbm_copy_reference=copy_reference(torch, dev))
 
 
 def _c4_bicgstab(hrw, torch, g, srcs, kappa, theta, steps):
@@ -787,6 +817,28 @@ def workload_c5(args):
                  rate_sweep=sweep, highest_rate_with_bounded_p99=bounded)
 
 
+FOUR_REPS = [(3, "fund", (32, 32, 32, 32)), (2, "adj", (48, 24, 24, 24)), (4, "asym", (48, 24, 24, 24)),
+             (3, "sym", (32, 32, 32, 32))]
+
+
+def four_rep_table(torch, hrw, dev, kappa, theta, copy_gbs):
+    """D_W and D_hat single applies in FP64 and FP32 for the four representations at the
+    sizes of the solve workloads, with stored U_R (and, for SU(3) fund, two-row links),
+    on near-thermal links generated on the device."""
+    from paper_2405_19294_amd import serve
+    table = {}
+    for nc, rep, dims in FOUR_REPS:
+        uf = serve.near_thermal_links(torch, dev, dims, nc, eps=0.3, seed=2)
+        key = f"SU({nc}) {rep} {'x'.join(str(d) for d in dims[::-1])}"
+        table[key] = operator_table(torch, hrw, dev, dims, nc, rep, uf, kappa, theta, copy_gbs)
+        if rep == "fund":
+            table[key + " two-row"] = operator_table(torch, hrw, dev, dims, nc, rep, uf, kappa, theta, copy_gbs,
+                                                     two_rows=True)
+        del uf
+        torch.cuda.empty_cache()
+    return table
+
+
 def workload_ops(args):
     """Single D_W and D_hat applies in FP64 and FP32 for the four representations at the sizes of
     the solve workloads (SU(3) fund and sym 32^4, SU(2) adj and SU(4) asym 24^3x48)."""
@@ -854,42 +906,63 @@ def copy_reference(torch, dev, nbytes=1 << 30, reps=10):
 
 
 def cpu_baseline(dims, uf, b, kappa, theta, gpu_iters, cpu_iters):
-    """The CPU oracle (as it stands) on a bounded sample of the same solve.
+    """The CPU oracle (as it stands, built -O3 -march=native on this host) on a bounded
+    sample of the same solve, on all the host threads this process may use and on one.
 
-    Times a few iterations of the oracle's FP64 CG on the same even/odd system
-    and extrapolates to the iteration count of the full solve.
+    Times the b' and eta preparation and a few iterations of the oracle's FP64 CG on the
+    same even/odd system with every thread, and extrapolates to the iteration count of
+    the full solve.  The one-core figure scales that by the ratio of one D_hat apply
+    timed on one thread to the same apply on all of them (a CG iteration is two D_hat
+    applies plus site-wise vector work).
     """
+    import tempfile
+
     import oracle as orc
 
-    threads = orc.num_threads()
+    orc.load_native(tempfile.mkdtemp(prefix="oracle_native_"))
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except AttributeError:
+        threads = os.cpu_count() or 1
+    threads = int(os.environ.get("OMP_NUM_THREADS", threads))
+    orc.set_num_threads(threads)
     ur = orc.rep_map(3, "fund", uf)
     be, bo = orc.split_eo(dims, b)
     t0 = time.perf_counter()
     bpe = be + kappa * orc.hop_eo(dims, ur, bo, 0, theta)
     eta = orc.deo(dims, ur, kappa, bpe, theta, dagger=True)
     t_prep = time.perf_counter() - t0
-    n = cpu_iters or 0
-    if n <= 0:
-        # size the sample to roughly 15 s from the cost of one D_hat apply
-        t1 = time.perf_counter()
-        orc.deo(dims, ur, kappa, be, theta)
-        t_apply = time.perf_counter() - t1
-        n = int(max(1, min(20, 15.0 / max(2 * t_apply, 1e-3))))
+    t1 = time.perf_counter()
+    orc.deo(dims, ur, kappa, be, theta)
+    t_apply = time.perf_counter() - t1
+    n = cpu_iters or int(max(1, min(20, 10.0 / max(2 * t_apply, 1e-3))))
     t1 = time.perf_counter()
     orc.cg(dims, ur, kappa, eta, theta, orc.SYSTEM_EO, tol=1e-10, max_iter=n)
     t_cg = time.perf_counter() - t1
     per_iter = t_cg / n
     est_solve = t_prep + per_iter * gpu_iters
-    log(f"cpu oracle: {n} CG iterations in {t_cg:.1f}s on {threads} threads ({cpu_model()})")
+    orc.set_num_threads(1)
+    t1 = time.perf_counter()
+    orc.deo(dims, ur, kappa, be, theta)
+    t_apply1 = time.perf_counter() - t1
+    orc.set_num_threads(threads)
+    scale = t_apply1 / t_apply
+    log(f"cpu oracle (-O3 -march=native): {n} CG iterations in {t_cg:.1f}s on {threads} threads, "
+        f"D_hat {t_apply:.2f}s ({threads} threads) / {t_apply1:.2f}s (1 thread) ({cpu_model()})")
     return {
         "value": round(1.0 / est_solve, 6),
         "unit": "solves/s",
         "cores": threads,
         "kind": "oracle",
+        "build": "gcc -O3 -march=native -fopenmp",
         "sample": (f"{n} iterations of the oracle's FP64 CG on the same 32^4 even/odd system "
                    f"({per_iter:.2f} s/iteration incl. the final true-residual check) plus the "
                    f"b' and eta preparation ({t_prep:.2f} s), extrapolated to the GPU solve's "
-                   f"{gpu_iters} iterations; host CPU: {cpu_model()}"),
+                   f"{gpu_iters} iterations; {threads} threads; host CPU: {cpu_model()}"),
+        "one_core": {
+            "value": round(1.0 / (est_solve * scale), 6), "unit": "solves/s", "cores": 1,
+            "sample": (f"the all-thread estimate scaled by one D_hat apply on 1 thread ({t_apply1:.2f} s) "
+                       f"over the same apply on {threads} threads ({t_apply:.2f} s)")},
     }
 
 

@@ -33,23 +33,36 @@ FMT_IDS = {"f32": 0, "bf16": 1, "f16": 2}
 _lib = None
 
 
-def build(force: bool = True) -> str:
-    """Compile oracle.c into liboracle.so (gcc, -O2, OpenMP)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared",
+def build(force: bool = True, path: str = _LIB, opt=("-O2",)) -> str:
+    """Compile oracle.c into a shared library (gcc, OpenMP; -O2 for the tests)."""
+    if force or not os.path.exists(path):
+        tmp = path + ".tmp"
+        cmd = ["gcc", *opt, "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared",
                "-Wall", "-Wno-unknown-pragmas", "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, path)
+    return path
 
 
-def _load():
+def load_native(directory: str) -> str:
+    """Build the same source with -O3 -march=native for the machine this runs on, into
+    ``directory``, and use it for every later call (the timing of the oracle as a CPU
+    baseline; the tests keep the portable -O2 build)."""
+    global _lib
+    path = build(True, os.path.join(directory, "liboracle_native.so"), ("-O3", "-march=native"))
+    _lib = None
+    _load(path)
+    return path
+
+
+def _load(path: str | None = None):
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
-        lib = ctypes.CDLL(_LIB)
+        if path is None:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build()
+        lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         I = ctypes.c_int
         L = ctypes.c_long
@@ -76,6 +89,7 @@ def _load():
             "orc_round": (I, [I, L, P]),
             "orc_parity_count": (I, [P, I]),
             "orc_num_threads": (I, []),
+            "orc_set_num_threads": (None, [I]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -449,6 +463,11 @@ def round_to(fmt: str, a) -> np.ndarray:
 def num_threads() -> int:
     """Threads the oracle's OpenMP loops use."""
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for the oracle's later OpenMP loops."""
+    _load().orc_set_num_threads(int(n))
 
 
 # ---------------------------------------------------------------- rounding-error bound

@@ -1567,6 +1567,15 @@ int orc_round(int fmt, long n, double *a)
 }
 
 /* Threads the OpenMP loops above use. */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

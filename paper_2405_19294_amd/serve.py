@@ -86,6 +86,26 @@ def poisson_stream(n_requests=400, rate=20.0, seed=5, volumes=C5_VOLUMES, reps=C
 
 # ---------------------------------------------------------------- backends
 
+def near_thermal_links(torch, dev, dims, nc, eps, seed):
+    """Seeded near-thermal SU(nc) links U = exp(i eps H), H traceless GUE (density
+    exp(-Tr H^2 / 2)), generated on the device; canonical [V][4][nc][nc] complex128."""
+    v = int(np.prod(dims))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(seed))
+    n = 4 * v
+    a = torch.randn((n, nc, nc), generator=gen, device=dev, dtype=torch.float64)
+    b = torch.randn((n, nc, nc), generator=gen, device=dev, dtype=torch.float64)
+    h = torch.complex(a, b) / math.sqrt(2.0)
+    h = torch.triu(h, 1)
+    h = h + h.conj().transpose(1, 2)
+    d = torch.randn((n, nc), generator=gen, device=dev, dtype=torch.float64)
+    h = h + torch.diag_embed(d.to(torch.complex128))
+    tr = torch.diagonal(h, dim1=1, dim2=2).sum(-1) / nc
+    h = h - tr[:, None, None] * torch.eye(nc, dtype=torch.complex128, device=dev)
+    u = torch.linalg.matrix_exp(1j * eps * h)
+    return u.reshape(v, 4, nc, nc).contiguous()
+
+
 class GpuBackend:
     """libhrw sessions on torch-owned device memory, one HIP stream per session."""
 
@@ -107,23 +127,8 @@ class GpuBackend:
 
     # inputs are generated on the device from seeded torch generators
     def _links(self, dims, nc):
-        torch = self.torch
-        v = int(np.prod(dims))
-        gen = torch.Generator(device=self.dev)
-        gen.manual_seed(self.gauge_seed * 1000 + nc * 100 + sum(dims))
-        n = 4 * v
-        # traceless GUE H (density exp(-Tr H^2 / 2)), U = exp(i eps H)
-        a = torch.randn((n, nc, nc), generator=gen, device=self.dev, dtype=torch.float64)
-        b = torch.randn((n, nc, nc), generator=gen, device=self.dev, dtype=torch.float64)
-        h = torch.complex(a, b) / math.sqrt(2.0)
-        h = torch.triu(h, 1)
-        h = h + h.conj().transpose(1, 2)
-        d = torch.randn((n, nc), generator=gen, device=self.dev, dtype=torch.float64)
-        h = h + torch.diag_embed(d.to(torch.complex128))
-        tr = torch.diagonal(h, dim1=1, dim2=2).sum(-1) / nc
-        h = h - tr[:, None, None] * torch.eye(nc, dtype=torch.complex128, device=self.dev)
-        u = torch.linalg.matrix_exp(1j * self.eps * h)
-        return u.reshape(v, 4, nc, nc).contiguous()
+        return near_thermal_links(self.torch, self.dev, dims, nc, self.eps,
+                                  self.gauge_seed * 1000 + nc * 100 + sum(dims))
 
     def gauge(self, key):
         with self.lock:
