@@ -57,9 +57,18 @@
  *
  * Environment (read at each hopping-kernel launch):
  *   HRW_TUNE=0       use the occupancy model for the multi-source kernel's
- *                    launch shape instead of timing the candidates on the
- *                    first plain-epilogue launch of each (sources, extents);
+ *                    launch shape instead of timing the candidates (16 or 32
+ *                    sites per workgroup x threads x walk chunk) on the first
+ *                    plain-epilogue launch of each (sources, extents);
  *                    results are bitwise the same either way;
+ *   HRW_TUNE_CACHE   file of tuned launch shapes (JSON, keyed by architecture,
+ *                    N_R, row split, storage type, sources and
+ *                    ceil(log2(sites per parity))), read before tuning and
+ *                    updated after; default $HOME/.cache/hrw/tune.json, an
+ *                    empty value keeps the shapes in memory only;
+ *   HRW_MRHS_SITES=16|32  pin the multi-source workgroup to that many sites
+ *                    (occupancy-model threads, no tuning; bitwise the same
+ *                    results);
  *   HRW_MRHS_MFMA=1  run FP32 N_R = 6 launches with >= 6 sources on the
  *                    matrix-core multi-source kernel (results differ from the
  *                    default vector kernel only by FP32 rounding; slower on

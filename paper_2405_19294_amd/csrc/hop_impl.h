@@ -28,9 +28,14 @@
 
 #include <stdlib.h>
 
+#include <stdio.h>
+#include <sys/stat.h>
+#include <unistd.h>
+
 #include <array>
 #include <map>
 #include <mutex>
+#include <string>
 #include <utility>
 
 #include "kernels.h"
@@ -180,7 +185,7 @@ struct Su3Links {
     }
 };
 
-template <class S>
+template <class S, int NS = MR_SITES>
 struct LdsLinks {
     static constexpr bool ROWWISE = true;  // one row at a time: fewer live registers
     static constexpr bool FUSED = false;
@@ -188,12 +193,12 @@ struct LdsLinks {
     static constexpr int NF = 1;
     static constexpr int REPID = 0;
     static constexpr bool RECON = false;
-    const cpx<S> *l;  // [comp][MR_SITES]
+    const cpx<S> *l;  // [comp][NS sites]
     int s;
     __device__ __forceinline__ void load(int comp, typename acc_of<S>::type &re,
                                          typename acc_of<S>::type &im) const
     {
-        load_c(l + comp * MR_SITES + s, re, im);
+        load_c(l + comp * NS + s, re, im);
     }
 };
 
@@ -663,40 +668,46 @@ __global__ void __launch_bounds__(WG) hop_su3_kernel(const HopArgs<S> a)
     }
 }
 
-// Multi-source kernel: a workgroup owns MR_SITES sites and every source.  It
-// copies the sites' links (all 8 directions) into LDS once, then its threads
-// run the per-site hop reading links from LDS: each link crosses HBM once per
-// launch however many sources there are.  The workgroup has as many threads as
-// (source, site, row group) items, up to MR_MAX_THREADS per round (see
-// mr_threads), so a round is never partly idle.  Thread t keeps its site and
-// row group in every round; only the source advances.
+// Multi-source kernel: a workgroup owns MRS sites (16 or 32: one or two
+// partial-sum groups) and every source.  It copies the sites' links (all 8
+// directions) into LDS once, then its threads run the per-site hop reading
+// links from LDS: each link crosses HBM once per launch however many sources
+// there are.  The workgroup has as many threads as (source, site, row group)
+// items, up to MR_MAX_THREADS per round (a whole number of MRS x G items, see
+// mr_threads and MrTuner), so a round is never partly idle.  Thread t keeps
+// its site and row group in every round; only the source advances.  The site
+// count changes neither the per-site arithmetic nor the 16-site partial sums,
+// so results are bitwise the same for either.
 // Waves per SIMD the instance is compiled for: 32-bit N_R <= 6 fits three
 // (168 VGPRs), except the fused CG update at N_R = 6, whose epilogue operands
 // (self, r, x, p for 4 N_R components) need more registers: at three waves it
-// spilled 28-164 bytes per lane, so it is compiled for two.
-template <class S, int NR, int EPI> struct MRW { static constexpr int value = NR < 6 || (NR == 6 && EPI != EPI_CG) ? 3 : 2; };
-template <int NR, int EPI> struct MRW<double, NR, EPI> { static constexpr int value = 2; };
+// spilled 28-164 bytes per lane, so it is compiled for two; so are the
+// 32-site N_R = 6 workgroups, whose 74 KB of links allow two per CU anyway.
+template <class S, int NR, int EPI, int MRS>
+struct MRW { static constexpr int value = NR < 6 || (NR == 6 && EPI != EPI_CG && MRS == 16) ? 3 : 2; };
+template <int NR, int EPI, int MRS> struct MRW<double, NR, EPI, MRS> { static constexpr int value = 2; };
 
-template <int NR, int RS, class S, bool DAG, int EPI>
-__global__ void __launch_bounds__(MR_MAX_THREADS) __attribute__((amdgpu_waves_per_eu(MRW<S, NR, EPI>::value)))
+template <int NR, int RS, class S, bool DAG, int EPI, int MRS = MR_SITES>
+__global__ void __launch_bounds__(MR_MAX_THREADS) __attribute__((amdgpu_waves_per_eu(MRW<S, NR, EPI, MRS>::value)))
 hop_mrhs_kernel(const HopArgs<S> a)
 {
+    static_assert(MRS % PG_SITES == 0, "whole partial-sum groups per workgroup");
     constexpr int G = NR / RS;
     constexpr int GC = 8 * NR * NR;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<S> *lk = (cpx<S> *)smem_raw;
     __shared__ double sh[MR_MAX_THREADS / 64];
-    const int nt = blockDim.x;  // a multiple of 64 and of PG_SITES * G
+    const int nt = blockDim.x;  // a multiple of 64 and of MRS * G
     int parity = a.parity, bx = blockIdx.x;
     if (parity < 0) {
         parity = bx >= a.grid_half;
         if (parity) bx -= a.grid_half;
     }
     bx = tile_remap(xcd_remap(bx, a.grid_half), a.grid_half, a.tile_ts, a.tile_c);
-    const int i0 = bx * MR_SITES;
+    const int i0 = bx * MRS;
     const cpx<S> *__restrict__ gauge = a.gauge[parity];
-    for (int e = threadIdx.x; e < GC * MR_SITES; e += nt) {
-        const int comp = e / MR_SITES, s = e - comp * MR_SITES;
+    for (int e = threadIdx.x; e < GC * MRS; e += nt) {
+        const int comp = e / MRS, s = e - comp * MRS;
         const int i = i0 + s;
         cpx<S> v;
         if (i < a.g.half) {
@@ -713,19 +724,20 @@ hop_mrhs_kernel(const HopArgs<S> a)
     __syncthreads();
     const int t = threadIdx.x;
     const int rg = t % G;
-    const int s = (t / G) % MR_SITES;
+    const int s = (t / G) % MRS;
     const int i = i0 + s;
-    LdsLinks<S> links{lk, s};
-    const int items = MR_SITES * G * a.n_rhs;
+    LdsLinks<S, MRS> links{lk, s};
+    const int items = MRS * G * a.n_rhs;
     for (int e0 = 0; e0 < items; e0 += nt) {
-        const int rhs = (e0 + t) / (MR_SITES * G);
+        const int rhs = (e0 + t) / (MRS * G);
         const bool live = rhs < a.n_rhs && (!a.run || a.run[rhs]);
         double nrm = 0;
         if (i < a.g.half && live) nrm = site_hop<NR, RS, S, DAG, EPI>(a, parity, i, rg * RS, rhs, links);
         if (EPI != EPI_PLAIN && a.partial) {
             const double tt = group_sum<G>(nrm, sh);
-            if ((t & (PG_SITES * G - 1)) == 0 && live)
-                a.partial[(size_t)rhs * a.pstride + (a.parity < 0 ? parity * a.ngroups : 0) + bx] = tt;
+            const int grp = bx * (MRS / PG_SITES) + s / PG_SITES;
+            if ((t & (PG_SITES * G - 1)) == 0 && live && grp < a.ngroups)
+                a.partial[(size_t)rhs * a.pstride + (a.parity < 0 ? parity * a.ngroups : 0) + grp] = tt;
         }
     }
 }
@@ -747,13 +759,16 @@ inline void hop_tiling(const Geom &g, int sites_per_wg, int *ts, int *c, int cma
     *c = best;
 }
 
+// enum hrw_dtype of a storage type (0 FP64, 1 FP32, 2 BF16, 3 FP16)
 template <class S> constexpr int dtype_id() { return 1; }
 template <> constexpr int dtype_id<double>() { return 0; }
+template <> constexpr int dtype_id<bf16_t>() { return 2; }
+template <> constexpr int dtype_id<f16_t>() { return 3; }
 
 // Workgroup size of one multi-source kernel instance for n_rhs sources, from
 // the runtime's occupancy figure for each candidate size (queried once per
 // instance and size; lds is fixed per instance).
-template <int NR, int RS, class S, bool D, int E>
+template <int NR, int RS, class S, bool D, int E, int MRS>
 int mr_block(int n_rhs, size_t lds)
 {
     static int occ[MR_MAX_THREADS / 64 + 1] = {};
@@ -763,37 +778,179 @@ int mr_block(int n_rhs, size_t lds)
         int &o = occ[t / 64];
         if (!o) {
             int nb = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, hop_mrhs_kernel<NR, RS, S, D, E>, t, lds) !=
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, hop_mrhs_kernel<NR, RS, S, D, E, MRS>, t, lds) !=
                     hipSuccess || nb < 1)
                 nb = 1;
             o = nb;
         }
         return o;
     };
-    return mr_threads(NR / RS, n_rhs, blocks_per_cu);
+    return mr_threads(NR / RS, n_rhs, blocks_per_cu, MRS);
 }
+
+template <int NR, class S>
+constexpr size_t mr_lds(int sites) { return sizeof(cpx<S>) * 8 * NR * NR * (size_t)sites; }
+
+// Whether the 32-site workgroup is built for an instance: two partial-sum
+// groups of G row threads must fit a round (32 G <= 128) and its links the LDS.
+template <int NR, int RS, class S>
+constexpr bool mr_has32() { return 32 * (NR / RS) <= WG / 2 && mr_lds<NR, S>(32) <= 160 * 1024; }
 
 // ------------------------------------------------------------ launch-shape tuning
 //
-// Launch shape of the multi-source kernel: threads per workgroup and the
-// spatial chunk of the time-tiled walk.  Neither changes any result (the
-// partial sums are per 16-site group, the per-source arithmetic is fixed), so
-// the shape is picked by timing.  On the first plain-epilogue launch of each
-// (instance family, sources, half volume) the candidates — every admissible
-// workgroup size x chunk 16 or 4 — run twice each on the caller's stream and
-// the fastest is kept for every epilogue of that key for the life of the
-// process.  Until a key is tuned (or with HRW_TUNE=0, or while the stream is
-// being captured into a graph) the occupancy model (mr_block) and chunk 16
-// are used.
+// Launch shape of the multi-source kernel: sites per workgroup (16 or 32),
+// threads per workgroup and the spatial chunk of the time-tiled walk.  None
+// changes any result (the partial sums are per 16-site group, the per-source
+// arithmetic is fixed), so the shape is picked by timing.  On the first
+// plain-epilogue launch of each (instance family, sources, lattice extents)
+// every candidate runs twice on the caller's stream and the fastest is kept
+// for every epilogue of that key for the life of the process, and written to
+// a cache file (JSON, keyed by architecture, N_R, row split, storage type,
+// sources and volume class = ceil(log2(sites per parity))) that later
+// processes read before tuning.  The file is $HRW_TUNE_CACHE, else
+// $HOME/.cache/hrw/tune.json; HRW_TUNE_CACHE set to an empty string keeps
+// the choices in memory only.  Until a key is tuned (or with HRW_TUNE=0, or
+// while the stream is being captured into a graph) the occupancy model
+// (mr_block, 16 sites) and chunk 16 are used.
 struct MrShape {
     int threads;
-    int cmax;  // chunk limit handed to hop_tiling (the chunk itself follows the launch's geometry)
+    int cmax;   // chunk limit handed to hop_tiling (the chunk itself follows the launch's geometry)
+    int sites;  // sites per workgroup: 16 or 32
 };
 
 inline bool mr_tuning_enabled()
 {
     const char *e = getenv("HRW_TUNE");
     return !(e && e[0] == '0');
+}
+
+// The persistent part of the tuner: one JSON file shared by every instance
+// family, an object whose entries are  "key": {"threads": T, "cmax": C,
+// "sites": S, "us": U}  (written one per line).
+struct TuneCache {
+    std::mutex mu;
+    bool loaded = false;
+    std::map<std::string, std::pair<MrShape, double>> entries;
+
+    static std::string path()
+    {
+        const char *e = getenv("HRW_TUNE_CACHE");
+        if (e) return std::string(e);
+        const char *h = getenv("HOME");
+        if (!h || !h[0]) return std::string();
+        return std::string(h) + "/.cache/hrw/tune.json";
+    }
+
+    // entries of an object of objects  {"key": {"threads": T, "cmax": C, "sites": S, "us": U}, ...}
+    // in any JSON layout; entries with unusable values are skipped
+    void read_file(const std::string &p, std::map<std::string, std::pair<MrShape, double>> &into)
+    {
+        FILE *f = fopen(p.c_str(), "r");
+        if (!f) return;
+        std::string text;
+        char buf[4096];
+        size_t n;
+        while ((n = fread(buf, 1, sizeof buf, f)) > 0 && text.size() < (1u << 22)) text.append(buf, n);
+        fclose(f);
+        auto field = [](const std::string &obj, const char *name, double *v) {
+            const size_t k = obj.find(std::string("\"") + name + "\"");
+            if (k == std::string::npos) return false;
+            const size_t c = obj.find(':', k);
+            return c != std::string::npos && sscanf(obj.c_str() + c + 1, "%lf", v) == 1;
+        };
+        size_t pos = 0;
+        const size_t open = text.find('{');
+        if (open == std::string::npos) return;
+        pos = open + 1;
+        while (true) {
+            const size_t q0 = text.find('"', pos);
+            if (q0 == std::string::npos) break;
+            const size_t q1 = text.find('"', q0 + 1);
+            if (q1 == std::string::npos) break;
+            const size_t b0 = text.find('{', q1);
+            const size_t b1 = b0 == std::string::npos ? b0 : text.find('}', b0);
+            if (b1 == std::string::npos) break;
+            const std::string key = text.substr(q0 + 1, q1 - q0 - 1), obj = text.substr(b0, b1 - b0 + 1);
+            double t = 0, c = 0, s = 0, us = 0;
+            if (field(obj, "threads", &t) && field(obj, "cmax", &c) && field(obj, "sites", &s)) {
+                field(obj, "us", &us);
+                const MrShape sh{(int)t, (int)c, (int)s};
+                if (sh.threads > 0 && sh.threads <= MR_MAX_THREADS && sh.threads % 64 == 0 &&
+                    (sh.sites == 16 || sh.sites == 32) && (sh.cmax == 16 || sh.cmax == 4))
+                    into[key] = {sh, us};
+            }
+            pos = b1 + 1;
+        }
+    }
+
+    bool lookup(const std::string &key, MrShape *out)
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        if (!loaded) {
+            loaded = true;
+            const std::string p = path();
+            if (!p.empty()) read_file(p, entries);
+        }
+        auto it = entries.find(key);
+        if (it == entries.end()) return false;
+        *out = it->second.first;
+        return true;
+    }
+
+    // merge with what other processes wrote meanwhile, then replace the file atomically
+    void store(const std::string &key, MrShape sh, double us)
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        entries[key] = {sh, us};
+        const std::string p = path();
+        if (p.empty()) return;
+        const size_t slash = p.find_last_of('/');
+        if (slash != std::string::npos && slash > 0) {
+            const std::string dir = p.substr(0, slash);
+            const std::string parent = dir.substr(0, dir.find_last_of('/'));
+            if (!parent.empty()) mkdir(parent.c_str(), 0755);
+            mkdir(dir.c_str(), 0755);
+        }
+        std::map<std::string, std::pair<MrShape, double>> merged;
+        read_file(p, merged);
+        for (auto &kv : entries) merged[kv.first] = kv.second;
+        const std::string tmp = p + ".tmp" + std::to_string((long)getpid());
+        FILE *f = fopen(tmp.c_str(), "w");
+        if (!f) return;
+        fprintf(f, "{\n");
+        size_t n = 0;
+        for (auto &kv : merged) {
+            const MrShape &m = kv.second.first;
+            fprintf(f, "  \"%s\": {\"threads\": %d, \"cmax\": %d, \"sites\": %d, \"us\": %.1f}%s\n", kv.first.c_str(),
+                    m.threads, m.cmax, m.sites, kv.second.second, ++n < merged.size() ? "," : "");
+        }
+        fprintf(f, "}\n");
+        const bool ok = fclose(f) == 0;
+        if (!ok || rename(tmp.c_str(), p.c_str()) != 0) remove(tmp.c_str());
+    }
+};
+
+inline TuneCache &tune_cache()
+{
+    static TuneCache c;
+    return c;
+}
+
+inline std::string device_arch()
+{
+    static std::string arch;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            arch = prop.gcnArchName;
+            const size_t c = arch.find(':');
+            if (c != std::string::npos) arch = arch.substr(0, c);
+        }
+        if (arch.empty()) arch = "unknown";
+    });
+    return arch;
 }
 
 template <int NR, int RS, class S>
@@ -804,19 +961,41 @@ struct MrTuner {
 
     static Key key(const HopArgs<S> &b) { return Key{b.n_rhs, b.g.d[0], b.g.d[1], b.g.d[2], b.g.d[3]}; }
 
+    static std::string cache_key(const HopArgs<S> &b)
+    {
+        int vc = 0;
+        while ((1LL << vc) < (long long)b.g.half) ++vc;
+        static const char *names[] = {"f64", "f32", "bf16", "f16"};
+        char buf[160];
+        snprintf(buf, sizeof buf, "%s/nr%d/rs%d/%s/n%d/v%d", device_arch().c_str(), NR, RS, names[dtype_id<S>()],
+                 b.n_rhs, vc);
+        return buf;
+    }
+
     bool lookup(const HopArgs<S> &b, MrShape *out)
     {
+        {
+            std::lock_guard<std::mutex> lock(mu);
+            auto it = best.find(key(b));
+            if (it != best.end()) {
+                *out = it->second;
+                return true;
+            }
+        }
+        MrShape sh;
+        if (!tune_cache().lookup(cache_key(b), &sh)) return false;
+        if (sh.sites == 32 && !mr_has32<NR, RS, S>()) return false;
+        if (sh.threads % mr_unit(NR / RS, sh.sites)) return false;  // not a shape of this instance
         std::lock_guard<std::mutex> lock(mu);
-        auto it = best.find(key(b));
-        if (it == best.end()) return false;
-        *out = it->second;
+        best[key(b)] = sh;
+        *out = sh;
         return true;
     }
 
     // time every candidate with the plain epilogue (out = H in: re-running it is
     // harmless); returns the fastest, or false if timing was not possible
     template <bool D>
-    bool tune(const HopArgs<S> &b0, size_t lds, dim3 grid, hipStream_t st, MrShape *out)
+    bool tune(const HopArgs<S> &b0, hipStream_t st, MrShape *out)
     {
         std::lock_guard<std::mutex> lock(mu);
         auto it = best.find(key(b0));
@@ -825,7 +1004,6 @@ struct MrTuner {
             return true;
         }
         constexpr int G = NR / RS;
-        const int unit = PG_SITES * G > 64 ? PG_SITES * G : 64;
         hipEvent_t ev[2];
         if (hipEventCreate(&ev[0]) != hipSuccess) return false;
         if (hipEventCreate(&ev[1]) != hipSuccess) {
@@ -833,29 +1011,41 @@ struct MrTuner {
             return false;
         }
         float best_ms = 0;
-        MrShape pick{0, 0};
+        MrShape pick{0, 0, 0};
         bool ok = true;
-        int ts16 = 0, c16 = 0;
-        hop_tiling(b0.g, MR_SITES, &ts16, &c16, 16);
-        for (int cmax : {16, 4}) {
+        for (int sites : {16, 32}) {
+            if (sites == 32 && !mr_has32<NR, RS, S>()) continue;
+            const int unit = mr_unit(G, sites);
+            const size_t lds = mr_lds<NR, S>(sites);
             HopArgs<S> b = b0;
-            hop_tiling(b.g, MR_SITES, &b.tile_ts, &b.tile_c, cmax);
-            if (cmax == 4 && b.tile_c == c16) continue;  // no distinct chunk
-            for (int t = MR_MAX_THREADS; t >= unit && ok; t -= 64) {
-                if (t % unit) continue;
-                float ms = 0;
-                for (int rep = 0; rep < 2 && ok; ++rep) {
-                    ok = hipEventRecord(ev[0], st) == hipSuccess;
-                    hop_mrhs_kernel<NR, RS, S, D, EPI_PLAIN><<<grid, dim3(t), lds, st>>>(b);
-                    ok = ok && hipGetLastError() == hipSuccess && hipEventRecord(ev[1], st) == hipSuccess &&
-                         hipEventSynchronize(ev[1]) == hipSuccess;
-                    float e = 0;
-                    ok = ok && hipEventElapsedTime(&e, ev[0], ev[1]) == hipSuccess;
-                    if (ok && (rep == 0 || e < ms)) ms = e;
-                }
-                if (ok && (pick.threads == 0 || ms < best_ms)) {
-                    best_ms = ms;
-                    pick = MrShape{t, cmax};
+            b.grid_half = (b0.ngroups + sites / PG_SITES - 1) / (sites / PG_SITES);
+            const dim3 grid(b0.parity < 0 ? 2 * b.grid_half : b.grid_half, 1);
+            int ts16 = 0, c16 = 0;
+            hop_tiling(b0.g, sites, &ts16, &c16, 16);
+            for (int cmax : {16, 4}) {
+                hop_tiling(b.g, sites, &b.tile_ts, &b.tile_c, cmax);
+                if (cmax == 4 && b.tile_c == c16) continue;  // no distinct chunk
+                for (int t = MR_MAX_THREADS; t >= unit && ok; t -= 64) {
+                    if (t % unit) continue;
+                    float ms = 0;
+                    for (int rep = 0; rep < 2 && ok; ++rep) {
+                        ok = hipEventRecord(ev[0], st) == hipSuccess;
+                        if (sites == 32) {
+                            if constexpr (mr_has32<NR, RS, S>())
+                                hop_mrhs_kernel<NR, RS, S, D, EPI_PLAIN, 32><<<grid, dim3(t), lds, st>>>(b);
+                        } else {
+                            hop_mrhs_kernel<NR, RS, S, D, EPI_PLAIN, 16><<<grid, dim3(t), lds, st>>>(b);
+                        }
+                        ok = ok && hipGetLastError() == hipSuccess && hipEventRecord(ev[1], st) == hipSuccess &&
+                             hipEventSynchronize(ev[1]) == hipSuccess;
+                        float e = 0;
+                        ok = ok && hipEventElapsedTime(&e, ev[0], ev[1]) == hipSuccess;
+                        if (ok && (rep == 0 || e < ms)) ms = e;
+                    }
+                    if (ok && (pick.threads == 0 || ms < best_ms)) {
+                        best_ms = ms;
+                        pick = MrShape{t, cmax, sites};
+                    }
                 }
             }
         }
@@ -863,6 +1053,7 @@ struct MrTuner {
         (void)hipEventDestroy(ev[1]);
         if (!ok || pick.threads == 0) return false;
         best[key(b0)] = pick;
+        tune_cache().store(cache_key(b0), pick, best_ms * 1e3);
         *out = pick;
         return true;
     }
@@ -875,35 +1066,60 @@ MrTuner<NR, RS, S> &mr_tuner()
     return t;
 }
 
+// HRW_MRHS_SITES=16 or 32 pins the sites per workgroup (threads from the
+// occupancy model, chunk 16; no tuning): for tests and experiments
+inline int mr_forced_sites()
+{
+    const char *e = getenv("HRW_MRHS_SITES");
+    if (!e) return 0;
+    const int v = atoi(e);
+    return v == 16 || v == 32 ? v : 0;
+}
+
 // shape for this launch (see MrTuner); tunes on a plain-epilogue launch
 template <int NR, int RS, class S, bool D, int E>
-MrShape mr_shape(const HopArgs<S> &b, size_t lds, dim3 grid, hipStream_t st)
+MrShape mr_shape(const HopArgs<S> &b, hipStream_t st)
 {
     MrShape sh;
+    const int forced = mr_forced_sites();
+    if (forced == 32 && mr_has32<NR, RS, S>())
+        return MrShape{mr_block<NR, RS, S, D, E, 32>(b.n_rhs, mr_lds<NR, S>(32)), 16, 32};
+    if (forced == 16) return MrShape{mr_block<NR, RS, S, D, E, 16>(b.n_rhs, mr_lds<NR, S>(16)), 16, 16};
     auto &tuner = mr_tuner<NR, RS, S>();
     if (tuner.lookup(b, &sh)) return sh;
     if (E == EPI_PLAIN && mr_tuning_enabled()) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone &&
-            tuner.template tune<D>(b, lds, grid, st, &sh))
+            tuner.template tune<D>(b, st, &sh))
             return sh;
     }
-    return MrShape{mr_block<NR, RS, S, D, E>(b.n_rhs, lds), 16};
+    return MrShape{mr_block<NR, RS, S, D, E, 16>(b.n_rhs, mr_lds<NR, S>(16)), 16, 16};
+}
+
+template <int NR, int RS, class S, bool D, int E>
+void launch_mrhs(const HopArgs<S> &b, hipStream_t st)
+{
+    const MrShape sh = mr_shape<NR, RS, S, D, E>(b, st);
+    HopArgs<S> bt = b;
+    bt.grid_half = (b.ngroups + sh.sites / PG_SITES - 1) / (sh.sites / PG_SITES);
+    hop_tiling(bt.g, sh.sites, &bt.tile_ts, &bt.tile_c, sh.cmax);
+    const dim3 grid(b.parity < 0 ? 2 * bt.grid_half : bt.grid_half, 1);
+    if constexpr (mr_has32<NR, RS, S>()) {
+        if (sh.sites == 32) {
+            hop_mrhs_kernel<NR, RS, S, D, E, 32><<<grid, dim3(sh.threads), mr_lds<NR, S>(32), st>>>(bt);
+            return;
+        }
+    }
+    hop_mrhs_kernel<NR, RS, S, D, E, 16><<<grid, dim3(sh.threads), mr_lds<NR, S>(16), st>>>(bt);
 }
 
 template <int NR, int RS, class S, bool MRK>
-void launch_hop_rs(bool dagger, int epi, dim3 grid, size_t lds, const HopArgs<S> &b, hipStream_t st)
+void launch_hop_rs(bool dagger, int epi, dim3 grid, const HopArgs<S> &b, hipStream_t st)
 {
 #define HRW_LAUNCH(D, E)                                                                           \
     do {                                                                                           \
-        if (MRK) {                                                                                 \
-            const MrShape sh = mr_shape<NR, RS, S, D, E>(b, lds, grid, st);                        \
-            HopArgs<S> bt = b;                                                                     \
-            hop_tiling(bt.g, MR_SITES, &bt.tile_ts, &bt.tile_c, sh.cmax);                          \
-            hop_mrhs_kernel<NR, RS, S, D, E><<<grid, dim3(sh.threads), lds, st>>>(bt);             \
-        } else {                                                                                   \
-            hop_kernel<NR, RS, S, D, E><<<grid, WG, 0, st>>>(b);                                   \
-        }                                                                                          \
+        if (MRK) launch_mrhs<NR, RS, S, D, E>(b, st);                                              \
+        else hop_kernel<NR, RS, S, D, E><<<grid, WG, 0, st>>>(b);                                  \
     } while (0)
     if (epi == EPI_PLAIN) {
         if (dagger) HRW_LAUNCH(true, EPI_PLAIN);
@@ -918,20 +1134,27 @@ void launch_hop_rs(bool dagger, int epi, dim3 grid, size_t lds, const HopArgs<S>
 }
 
 template <int NR, int RS, class S>
-hipError_t allow_lds(size_t lds)
+hipError_t allow_lds()
 {
     // the multi-source instances may need more than the default 64 KB of LDS
     static bool done = false;
-    if (done || lds <= 65536) return hipSuccess;
+    if (done) return hipSuccess;
     hipError_t e = hipSuccess;
-    auto set = [&](const void *f) {
-        if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    auto set = [&](const void *f, size_t lds) {
+        if (e == hipSuccess && lds > 65536)
+            e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     };
-    set((const void *)hop_mrhs_kernel<NR, RS, S, true, EPI_PLAIN>);
-    set((const void *)hop_mrhs_kernel<NR, RS, S, false, EPI_PLAIN>);
-    set((const void *)hop_mrhs_kernel<NR, RS, S, true, EPI_AXPY>);
-    set((const void *)hop_mrhs_kernel<NR, RS, S, false, EPI_AXPY>);
-    set((const void *)hop_mrhs_kernel<NR, RS, S, true, EPI_CG>);
+#define HRW_ALLOW(M)                                                                                 \
+    set((const void *)hop_mrhs_kernel<NR, RS, S, true, EPI_PLAIN, M>, mr_lds<NR, S>(M));               \
+    set((const void *)hop_mrhs_kernel<NR, RS, S, false, EPI_PLAIN, M>, mr_lds<NR, S>(M));              \
+    set((const void *)hop_mrhs_kernel<NR, RS, S, true, EPI_AXPY, M>, mr_lds<NR, S>(M));                \
+    set((const void *)hop_mrhs_kernel<NR, RS, S, false, EPI_AXPY, M>, mr_lds<NR, S>(M));               \
+    set((const void *)hop_mrhs_kernel<NR, RS, S, true, EPI_CG, M>, mr_lds<NR, S>(M));
+    HRW_ALLOW(16)
+    if constexpr (mr_has32<NR, RS, S>()) {
+        HRW_ALLOW(32)
+    }
+#undef HRW_ALLOW
     done = e == hipSuccess;
     return e;
 }
@@ -948,20 +1171,16 @@ hipError_t launch_hop_impl(int nr, bool dagger, int epi, const HopArgs<S> &a, hi
         constexpr int G = NR / RS;
         b.ngroups = hop_groups(a.g);
         if (hop_uses_mrhs(NR, dtype_id<S>(), a.n_rhs)) {
-            const int gh = b.ngroups;  // one workgroup per 16-site group
-            b.grid_half = gh;
-            hop_tiling(a.g, MR_SITES, &b.tile_ts, &b.tile_c);
-            const size_t lds = sizeof(cpx<S>) * 8 * NR * NR * MR_SITES;
-            err = allow_lds<NR, RS, S>(lds);
+            // grid, tiling and LDS follow the launch shape (launch_mrhs)
+            err = allow_lds<NR, RS, S>();
             if (err != hipSuccess) return;
-            dim3 grid(a.parity < 0 ? 2 * gh : gh, 1);
-            launch_hop_rs<NR, RS, S, true>(dagger, epi, grid, lds, b, st);
+            launch_hop_rs<NR, RS, S, true>(dagger, epi, dim3(1), b, st);
         } else {
             const int gh = hop_grid(a.g, G);
             b.grid_half = gh;
             hop_tiling(a.g, WG / G, &b.tile_ts, &b.tile_c);
             dim3 grid(a.parity < 0 ? 2 * gh : gh, a.n_rhs);
-            launch_hop_rs<NR, RS, S, false>(dagger, epi, grid, 0, b, st);
+            launch_hop_rs<NR, RS, S, false>(dagger, epi, grid, b, st);
         }
     });
     if (!ok) return hipErrorInvalidValue;

@@ -125,16 +125,21 @@ constexpr int PG_SITES = 16;  // sites per FP64 partial-sum group of the hopping
 constexpr int MR_SITES = 16;  // sites per workgroup of the multi-source hopping kernel
 constexpr int MR_MAX_THREADS = 256;  // largest multi-source workgroup
 
-// Threads of a multi-source workgroup for n_rhs sources.  The MR_SITES x g x
-// n_rhs (source, site, row group) items run in rounds of `threads` (a whole
-// number of wavefronts and of 16-site partial-sum groups); the choice
-// maximises blocks_per_cu(threads) x items per round, i.e. the busy lanes a CU
-// holds on average.  Ties go to the larger workgroup.
+// Smallest thread count of a multi-source workgroup with `sites` sites and g
+// row threads per site: a whole number of wavefronts and of (site, row group)
+// sets, so that every round of items keeps the same site per thread.
+inline int mr_unit(int g, int sites) { return sites * g > 64 ? sites * g : 64; }
+
+// Threads of a multi-source workgroup for n_rhs sources.  The sites x g x
+// n_rhs (source, site, row group) items run in rounds of `threads` (a
+// multiple of mr_unit); the choice maximises blocks_per_cu(threads) x items
+// per round, i.e. the busy lanes a CU holds on average.  Ties go to the
+// larger workgroup.
 template <class F>
-inline int mr_threads(int g, int n_rhs, F blocks_per_cu)
+inline int mr_threads(int g, int n_rhs, F blocks_per_cu, int sites = MR_SITES)
 {
-    const long items = (long)MR_SITES * g * n_rhs;
-    const int unit = PG_SITES * g > 64 ? PG_SITES * g : 64;
+    const long items = (long)sites * g * n_rhs;
+    const int unit = mr_unit(g, sites);
     int best = MR_MAX_THREADS;
     double best_score = -1;
     for (int t = MR_MAX_THREADS; t >= unit; t -= 64) {

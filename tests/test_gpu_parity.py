@@ -132,11 +132,14 @@ MULTI_SOURCE_CASES = [(3, "fund", "f64", 40), (3, "fund", "f32", 40), (3, "sym",
                       (3, "adj", "f64", 5), (3, "adj", "f32", 7), (2, "fund", "bf16", 9), (4, "asym", "f16", 6), (4, "asym", "f32", 2)]
 
 
+@pytest.mark.parametrize("sites", [16, 32])
 @pytest.mark.parametrize("nc,rep,dtype,n", MULTI_SOURCE_CASES)
 @pytest.mark.parametrize("dims", [(2, 2, 2, 6), (4, 2, 4, 4)])
-def test_multi_source_kernel_equals_single(nc, rep, dtype, n, dims):
+def test_multi_source_kernel_equals_single(nc, rep, dtype, n, dims, sites, monkeypatch):
     """Every source of a batched D_W and D_hat apply equals its single-source apply bit for bit
-    (the 24-site half lattice leaves a partly filled 16-site group); FP64 also matches the oracle."""
+    (the 24-site half lattice leaves a partly filled 16-site group), with 16 and 32 sites per
+    multi-source workgroup; FP64 also matches the oracle."""
+    monkeypatch.setenv("HRW_MRHS_SITES", str(sites))
     uf, ur, g = setup(dims, nc, rep, "haar", seed=31, dtypes=(dtype,))
     psi = fx.gaussian_spinor(dims, g.nr, seed=32, n_rhs=n)
     many = hrw.dw_apply(g, 0.12, to_dev(psi), THETA_TW, dtype).cpu().numpy()
