@@ -9,6 +9,7 @@
 #include <math.h>
 
 #include "kernels.h"
+#include "cg_reduce.h"
 
 namespace hrw {
 
@@ -187,6 +188,37 @@ hipError_t launch_xpay(const cpx<S> *r, cpx<S> *p, const double *beta, const int
                        size_t rstride, int n_rhs, hipStream_t st)
 {
     xpay_kernel<S><<<dim3(vec_grid(elems), n_rhs), WG, 0, st>>>(r, p, beta, active, elems, rstride);
+    return hipGetLastError();
+}
+
+template <class S>
+__global__ void __launch_bounds__(WG) cg_xp_kernel(const cpx<S> *__restrict__ r, cpx<S> *__restrict__ p,
+                                                    cpx<S> *__restrict__ x, const double *alpha, const double *beta,
+                                                    const int *advanced, size_t n, size_t rstride)
+{
+    typedef typename acc_of<S>::type A;
+    const int rhs = blockIdx.y;
+    if (!advanced[rhs]) return;
+    const A al = (A)alpha[rhs], bt = (A)beta[rhs];
+    const size_t ro = (size_t)rhs * rstride;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+        A rr, ri, pr, pi, xr, xi;
+        load_c_nt(r + ro + t, rr, ri);
+        load_c(p + ro + t, pr, pi);
+        load_c_nt(x + ro + t, xr, xi);
+        xr += al * pr;
+        xi += al * pi;
+        store_c_nt(x + ro + t, xr, xi);
+        store_c(p + ro + t, rr + bt * pr, ri + bt * pi);
+    }
+}
+
+template <class S>
+hipError_t launch_cg_xp(const cpx<S> *r, cpx<S> *p, cpx<S> *x, const double *alpha, const double *beta,
+                        const int *advanced, size_t elems, size_t rstride, int n_rhs, hipStream_t st)
+{
+    cg_xp_kernel<S><<<dim3(vec_grid(elems), n_rhs), WG, 0, st>>>(r, p, x, alpha, beta, advanced, elems, rstride);
     return hipGetLastError();
 }
 
@@ -419,24 +451,7 @@ __global__ void __launch_bounds__(WG) cg_alpha_kernel(CgState *cs, const double 
 {
     __shared__ double sh[WG / 64];
     const int rhs = blockIdx.x;
-    const double pap = sum_parts(partial + (size_t)rhs * pstride, nparts, sh);
-    if (threadIdx.x == 0) {
-        CgState c = cs[rhs];
-        c.pap = pap;
-        if (c.active) {
-            if (!(pap > 0) || isinf(pap)) {
-                c.status = CG_BREAKDOWN;
-                c.active = 0;
-                c.alpha = 0;
-            } else {
-                c.alpha = c.rr / pap;
-            }
-        } else {
-            c.alpha = 0;
-        }
-        cs[rhs] = c;
-        alpha_out[rhs] = c.alpha;
-    }
+    cg_alpha_step(cs, partial + (size_t)rhs * pstride, nparts, alpha_out, rhs, sh);
 }
 
 hipError_t launch_cg_alpha(CgState *cs, const double *partial, int pstride, int nparts, int n_rhs,
@@ -508,6 +523,8 @@ template hipError_t launch_copy<f16_t>(const cpx<f16_t> *, cpx<f16_t> *, size_t,
                                         hipStream_t);                                                  \
     template hipError_t launch_residual<S>(const cpx<S> *, const cpx<S> *, cpx<S> *, size_t, size_t, int, \
                                            double *, int, int, hipStream_t);                           \
+    template hipError_t launch_cg_xp<S>(const cpx<S> *, cpx<S> *, cpx<S> *, const double *, const double *, \
+                                        const int *, size_t, size_t, int, hipStream_t);                       \
     template hipError_t launch_xpay<S>(const cpx<S> *, cpx<S> *, const double *, const int *, size_t,   \
                                        size_t, int, hipStream_t);
 HRW_INST(double)

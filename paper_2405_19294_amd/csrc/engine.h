@@ -115,6 +115,11 @@ struct HopCall {
     const int *run = nullptr;  // per rhs: skip sources whose system is not iterating
     double *partial = nullptr;
     int pstride = 0;
+    // the CG alpha step on the side of a plain-epilogue launch (see HopArgs)
+    CgState *red_cs = nullptr;
+    const double *red_partial = nullptr;
+    double *red_alpha = nullptr;
+    int red_pstride = 0, red_nparts = 0, red_n = 0;
 };
 int run_hop(const hrw_gauge *g, const Phases &ph, const HopCall &c, hipStream_t st);
 

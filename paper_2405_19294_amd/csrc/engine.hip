@@ -124,7 +124,7 @@ double hop_bytes(const Geom &g, int nr, int dt, int parity, int epi, int n_rhs, 
     double per = sp;  // neighbour spinors (each input spinor once)
     if (epi == EPI_PLAIN) per += sp;            // out
     else if (epi == EPI_AXPY) per += 2 * sp;    // self + out
-    else per += 6 * sp;                         // self, r, x, p read; r, x written
+    else per += 3 * sp;                         // self and r read; r written
     // the multi-source kernel reads each link once for all sources
     const double link_reads = !fused_nc && hop_uses_mrhs(nr, dt, n_rhs) ? 1.0 : (double)n_rhs;
     return (per * n_rhs + links * link_reads) * sites;
@@ -169,6 +169,12 @@ int run_hop(const hrw_gauge *g, const Phases &ph, const HopCall &c, hipStream_t 
         a.run = c.run;
         a.partial = c.partial;
         a.pstride = c.pstride;
+        a.red_cs = c.red_cs;
+        a.red_partial = c.red_partial;
+        a.red_alpha = c.red_alpha;
+        a.red_pstride = c.red_pstride;
+        a.red_nparts = c.red_nparts;
+        a.red_n = c.red_n;
         err = fused_nc   ? launch_hop_fused<S>(g->nc, g->rep, c.dagger, c.epi, a, st)
               : two_rows ? launch_hop_su3<S>(c.dagger, c.epi, a, st)
                          : launch_hop<S>(g->nr, c.dagger, c.epi, a, st);
@@ -616,6 +622,7 @@ static int cg_iteration(CgRun &R, int max_iter, ReliableSchedule sched, int *hos
     c.rstride = P.RS;
     c.run = P.active;  // systems that are not iterating skip every hop of the iteration
     int rc;
+    // q = A p: D p (its |.|^2 partials give <p, A p>), then D^+ of it with the CG update of r
     if (R.full()) {
         HopCall a = c;
         a.parity = -1;
@@ -629,6 +636,22 @@ static int cg_iteration(CgRun &R, int max_iter, ReliableSchedule sched, int *hos
             a.out[k] = P.s.h(k);
         }
         if ((rc = run_hop(R.g, R.ph, a, R.st))) return rc;
+        HRW_HIP(launch_cg_alpha(P.cs, P.pa, P.pstride, R.nparts_hop(), R.n_rhs, P.alpha, R.st));
+        HopCall b = c;
+        b.parity = -1;
+        b.dagger = true;
+        b.epi = EPI_CG;
+        b.coef = P.coef_k;
+        for (int k = 0; k < 2; ++k) {
+            b.in[k] = P.s.h(k);
+            b.self[k] = P.s.h(k);
+            b.r[k] = P.r.h(k);
+        }
+        b.alpha = P.alpha;
+        b.active = P.active;
+        b.partial = P.pb;
+        b.pstride = P.pstride;
+        if ((rc = run_hop(R.g, R.ph, b, R.st))) return rc;
     } else {
         HopCall a = c;
         a.parity = 1;
@@ -646,59 +669,46 @@ static int cg_iteration(CgRun &R, int max_iter, ReliableSchedule sched, int *hos
         b.partial = P.pa;
         b.pstride = P.pstride;
         if ((rc = run_hop(R.g, R.ph, b, R.st))) return rc;
-    }
-    HRW_HIP(launch_cg_alpha(P.cs, P.pa, P.pstride, R.nparts_hop(), R.n_rhs, P.alpha, R.st));
-    if (R.full()) {
-        HopCall a = c;
-        a.parity = -1;
-        a.dagger = true;
-        a.epi = EPI_CG;
-        a.coef = P.coef_k;
-        for (int k = 0; k < 2; ++k) {
-            a.in[k] = P.s.h(k);
-            a.self[k] = P.s.h(k);
-            a.r[k] = P.r.h(k);
-            a.x[k] = P.x.h(k);
-            a.p[k] = P.p.h(k);
-        }
-        a.alpha = P.alpha;
-        a.active = P.active;
-        a.partial = P.pb;
-        a.pstride = P.pstride;
-        if ((rc = run_hop(R.g, R.ph, a, R.st))) return rc;
-    } else {
-        HopCall a = c;
-        a.parity = 1;
-        a.dagger = true;
-        a.epi = EPI_PLAIN;
-        a.in[0] = P.s.h(0);
-        a.out[1] = P.u.h(1);
-        if ((rc = run_hop(R.g, R.ph, a, R.st))) return rc;
-        HopCall b = c;
-        b.parity = 0;
-        b.dagger = true;
-        b.epi = EPI_CG;
-        b.coef = P.coef_k2;
-        b.in[1] = P.u.h(1);
-        b.self[0] = P.s.h(0);
-        b.r[0] = P.r.h(0);
-        b.x[0] = P.x.h(0);
-        b.p[0] = P.p.h(0);
-        b.alpha = P.alpha;
-        b.active = P.active;
-        b.partial = P.pb;
-        b.pstride = P.pstride;
-        if ((rc = run_hop(R.g, R.ph, b, R.st))) return rc;
+        // the first hop of D_hat^+ carries the alpha step (the second stage of the
+        // <p, A p> reduction): no launch of its own, and alpha is set before the
+        // CG hop that needs it
+        HopCall d = c;
+        d.parity = 1;
+        d.dagger = true;
+        d.epi = EPI_PLAIN;
+        d.in[0] = P.s.h(0);
+        d.out[1] = P.u.h(1);
+        d.red_cs = P.cs;
+        d.red_partial = P.pa;
+        d.red_alpha = P.alpha;
+        d.red_pstride = P.pstride;
+        d.red_nparts = R.nparts_hop();
+        d.red_n = R.n_rhs;
+        if ((rc = run_hop(R.g, R.ph, d, R.st))) return rc;
+        HopCall e = c;
+        e.parity = 0;
+        e.dagger = true;
+        e.epi = EPI_CG;
+        e.coef = P.coef_k2;
+        e.in[1] = P.u.h(1);
+        e.self[0] = P.s.h(0);
+        e.r[0] = P.r.h(0);
+        e.alpha = P.alpha;
+        e.active = P.active;
+        e.partial = P.pb;
+        e.pstride = P.pstride;
+        if ((rc = run_hop(R.g, R.ph, e, R.st))) return rc;
     }
     int *advanced = P.active + 2 * MAX_RHS;
     HRW_HIP(launch_cg_beta(P.cs, P.pb, P.pstride, R.nparts_hop(), R.n_rhs, max_iter, sched, P.beta, P.active,
                            advanced, host_active, R.st));
+    // x += alpha p and p = r + beta p in one pass for the systems that took this step
     int err = HRW_OK;
     dispatch_dtype(dt, [&](auto sv) {
         typedef decltype(sv) S;
-        if (launch_xpay<S>((const cpx<S> *)P.r.h(0), (cpx<S> *)P.p.h(0), P.beta, advanced, R.elems(), P.RS,
-                           R.n_rhs, R.st) != hipSuccess)
-            err = fail(HRW_EDEVICE, "xpay launch failed");
+        if (launch_cg_xp<S>((const cpx<S> *)P.r.h(0), (cpx<S> *)P.p.h(0), (cpx<S> *)P.x.h(0), P.alpha, P.beta,
+                            advanced, R.elems(), P.RS, R.n_rhs, R.st) != hipSuccess)
+            err = fail(HRW_EDEVICE, "x/p update launch failed");
     });
     return err;
 }

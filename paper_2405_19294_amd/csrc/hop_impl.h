@@ -38,6 +38,7 @@
 #include <string>
 #include <utility>
 
+#include "cg_reduce.h"
 #include "kernels.h"
 
 namespace hrw {
@@ -548,10 +549,8 @@ __device__ __forceinline__ double site_hop(const HopArgs<S> &a, int parity, int 
                     store_c_nt(out + o, vr, vi);
                     nrm += (double)vr * (double)vr + (double)vi * (double)vi;
                 }
-        } else {  // EPI_CG
+        } else {  // EPI_CG: r -= alpha q (x += alpha p follows in launch_cg_xp)
             cpx<S> *r = a.r[parity] + roff;
-            cpx<S> *xx = a.x[parity] + roff;
-            const cpx<S> *p = a.p[parity] + roff;
             const bool act = a.active[rhs] != 0;
             const A al = (A)a.alpha[rhs];
 #pragma unroll
@@ -559,19 +558,14 @@ __device__ __forceinline__ double site_hop(const HopArgs<S> &a, int parity, int 
 #pragma unroll
                 for (int c = 0; c < RS; ++c) {
                     const size_t o = lay(i, sp * NR + r0 + c, NC);
-                    A sr, si, rr_, ri, xr, xi, pr_, pi_;
+                    A sr, si, rr_, ri;
                     load_c_nt(self + o, sr, si);
                     load_c_nt(r + o, rr_, ri);
                     if (act) {
                         const A qr = sr - cf * ar[sp][c], qi = si - cf * ai[sp][c];
-                        load_c_nt(xx + o, xr, xi);
-                        load_c_nt(p + o, pr_, pi_);
                         rr_ -= al * qr;
                         ri -= al * qi;
-                        xr += al * pr_;
-                        xi += al * pi_;
                         store_c_nt(r + o, rr_, ri);
-                        store_c_nt(xx + o, xr, xi);
                     }
                     nrm += (double)rr_ * (double)rr_ + (double)ri * (double)ri;
                 }
@@ -592,6 +586,7 @@ __global__ void __launch_bounds__(WG) hop_kernel(const HopArgs<S> a)
     }
     bx = tile_remap(xcd_remap(bx, a.grid_half), a.grid_half, a.tile_ts, a.tile_c);
     const int rhs = blockIdx.y;
+    if (EPI == EPI_PLAIN) hop_alpha_on_the_side(a, sh);
     if (a.run && !a.run[rhs]) return;  // whole workgroup: one source
     const int gid = bx * WG + threadIdx.x;
     const int i = gid / G;
@@ -623,6 +618,7 @@ __global__ void __launch_bounds__(WG) hop_fused_kernel(const HopArgs<S> a)
     }
     bx = tile_remap(xcd_remap(bx, a.grid_half), a.grid_half, a.tile_ts, a.tile_c);
     const int rhs = blockIdx.y;
+    if (EPI == EPI_PLAIN) hop_alpha_on_the_side(a, sh);
     if (a.run && !a.run[rhs]) return;
     const int gid = bx * WG + threadIdx.x;
     const int i = gid / G;
@@ -653,6 +649,7 @@ __global__ void __launch_bounds__(WG) hop_su3_kernel(const HopArgs<S> a)
     }
     bx = tile_remap(xcd_remap(bx, a.grid_half), a.grid_half, a.tile_ts, a.tile_c);
     const int rhs = blockIdx.y;
+    if (EPI == EPI_PLAIN) hop_alpha_on_the_side(a, sh);
     if (a.run && !a.run[rhs]) return;
     const int i = bx * WG + threadIdx.x;
     double nrm = 0;
@@ -704,6 +701,7 @@ hop_mrhs_kernel(const HopArgs<S> a)
         if (parity) bx -= a.grid_half;
     }
     bx = tile_remap(xcd_remap(bx, a.grid_half), a.grid_half, a.tile_ts, a.tile_c);
+    if (EPI == EPI_PLAIN) hop_alpha_on_the_side(a, sh);
     const int i0 = bx * MRS;
     const cpx<S> *__restrict__ gauge = a.gauge[parity];
     for (int e = threadIdx.x; e < GC * MRS; e += nt) {

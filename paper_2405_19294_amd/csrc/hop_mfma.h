@@ -221,6 +221,7 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) ho
     constexpr int NT = MF_NT, K = M::K, NC = M::NC, GC = M::GC;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<float> *lk = (cpx<float> *)smem_raw;
+    __shared__ double sh[4];
     const int nt = blockDim.x;  // whole wavefronts
     int parity = a.parity, bx = blockIdx.x;
     if (parity < 0) {
@@ -228,6 +229,7 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) ho
         if (parity) bx -= a.grid_half;
     }
     bx = tile_remap(xcd_remap(bx, a.grid_half), a.grid_half, a.tile_ts, a.tile_c);
+    if (EPI == EPI_PLAIN) hop_alpha_on_the_side(a, sh);
     const int i0 = bx * MR_SITES;
     const cpx<float> *__restrict__ gauge = a.gauge[parity];
     for (int e = threadIdx.x; e < GC * MR_SITES; e += nt) {
@@ -301,18 +303,10 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) ho
                                 float rr_, ri;
                                 load_c_nt(r + o, rr_, ri);
                                 if (a.active[s]) {
-                                    cpx<float> *xx = a.x[parity] + roff;
-                                    const cpx<float> *p = a.p[parity] + roff;
                                     const float al = (float)a.alpha[s];
-                                    float xr, xi, pr_, pi_;
-                                    load_c_nt(xx + o, xr, xi);
-                                    load_c_nt(p + o, pr_, pi_);
                                     rr_ -= al * vr;
                                     ri -= al * vi;
-                                    xr += al * pr_;
-                                    xi += al * pi_;
                                     store_c_nt(r + o, rr_, ri);
-                                    store_c_nt(xx + o, xr, xi);
                                 }
                                 nrm += (double)rr_ * (double)rr_ + (double)ri * (double)ri;
                             }

@@ -48,8 +48,10 @@ inline size_t dtype_cbytes(int dt)  // bytes of one complex number
 enum Epilogue {
     EPI_PLAIN = 0,  // out = H in
     EPI_AXPY = 1,   // out = self - c H in              (+ optional |out|^2 partials)
-    EPI_CG = 2      // q = self - c H in; r -= alpha q; x += alpha p; |r|^2 partials
+    EPI_CG = 2      // q = self - c H in; r -= alpha q; |r|^2 partials (x moves in launch_cg_xp)
 };
+
+struct CgState;
 
 // Pointers are per parity: index 0 / 1 = the half field of that parity.
 template <class S>
@@ -78,6 +80,14 @@ struct HopArgs {
     int tile_ts;                 // workgroups per time slice (0 = no tiling)
     int tile_c;                  // workgroups per spatial chunk of the walk
     int ngroups;                 // 16-site partial-sum groups per parity
+    // the CG alpha step run on the side of a plain-epilogue launch (null: none):
+    // red_n systems, their partials of <p, A p> and state, alpha written per system
+    CgState *red_cs;
+    const double *red_partial;
+    double *red_alpha;
+    int red_pstride;
+    int red_nparts;
+    int red_n;
 };
 
 // Launch the hopping kernel.  kc_bytes receives the algorithmic bytes.
@@ -225,6 +235,11 @@ hipError_t launch_residual(const cpx<S> *b, const cpx<S> *q, cpx<S> *r, size_t e
 template <class S>
 hipError_t launch_xpay(const cpx<S> *r, cpx<S> *p, const double *beta, const int *active,
                        size_t elems, size_t rstride, int n_rhs, hipStream_t st);
+// the end of a CG iteration for the rhs with advanced[rhs] != 0:
+// x += alpha p, then p = r + beta p (one pass over x, p and r)
+template <class S>
+hipError_t launch_cg_xp(const cpx<S> *r, cpx<S> *p, cpx<S> *x, const double *alpha, const double *beta,
+                        const int *advanced, size_t elems, size_t rstride, int n_rhs, hipStream_t st);
 // y += a x  with a per rhs (device), x and y possibly of different dtypes
 hipError_t launch_axpy_mixed(int dt_x, const void *x, int dt_y, void *y, const double *a,
                              size_t elems, size_t rstride_x, size_t rstride_y, int n_rhs,
