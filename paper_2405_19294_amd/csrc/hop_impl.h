@@ -366,12 +366,22 @@ __device__ __forceinline__ void su3_third_row(A (&ur)[RS][NR], A (&ui)[RS][NR])
     }
 }
 
+// The input spinors a workgroup stages in LDS: the half-sites lo .. lo + n - 1
+// of the input half field (its own sites and one x3 line before and after),
+// component-major ([comp][n]).  A neighbour inside that range is read from LDS,
+// any other from global memory.  l == nullptr: nothing staged.
+template <class S>
+struct Stage {
+    const cpx<S> *l;
+    int lo, n;
+};
+
 // one direction (forward or backward) of one mu, for colour rows r0 .. r0+RS-1
 template <int MU, int DIR, bool DAG, int NR, int RS, class S, class LS>
 __device__ __forceinline__ void hop_dir(const HopArgs<S> &a, const cpx<S> *__restrict__ in,
                                         const LS &links, int r0, const int (&x)[4],
                                         typename acc_of<S>::type (&ar)[4][RS],
-                                        typename acc_of<S>::type (&ai)[4][RS])
+                                        typename acc_of<S>::type (&ai)[4][RS], const Stage<S> &stg)
 {
     typedef typename acc_of<S>::type A;
     constexpr int NC = 4 * NR;
@@ -390,10 +400,18 @@ __device__ __forceinline__ void hop_dir(const HopArgs<S> &a, const cpx<S> *__res
     }
     const int j = eo_index(a.g, y);
     A pr[4][NR], pi[4][NR];
+    const int k = j - stg.lo;
+    if (stg.l && (unsigned)k < (unsigned)stg.n) {
 #pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
+        for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-        for (int c = 0; c < NR; ++c) load_c(in + lay(j, sp * NR + c, NC), pr[sp][c], pi[sp][c]);
+            for (int c = 0; c < NR; ++c) load_c(stg.l + (sp * NR + c) * stg.n + k, pr[sp][c], pi[sp][c]);
+    } else {
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int c = 0; c < NR; ++c) load_c(in + lay(j, sp * NR + c, NC), pr[sp][c], pi[sp][c]);
+    }
     constexpr int DD = MU + 4 * DIR;
     // links from HBM: every row's loads are issued together with the spinor's,
     // before any arithmetic waits on them (unused when links come from LDS)
@@ -505,7 +523,7 @@ __device__ __forceinline__ double group_sum(double v, double *sh)
 // then the epilogue; returns this thread's |.|^2 contribution
 template <int NR, int RS, class S, bool DAG, int EPI, class LS>
 __device__ __forceinline__ double site_hop(const HopArgs<S> &a, int parity, int i, int r0, int rhs,
-                                           const LS &links)
+                                           const LS &links, const Stage<S> &stg = Stage<S>{nullptr, 0, 0})
 {
     typedef typename acc_of<S>::type A;
     constexpr int NC = 4 * NR;
@@ -519,14 +537,14 @@ __device__ __forceinline__ double site_hop(const HopArgs<S> &a, int parity, int 
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
         for (int c = 0; c < RS; ++c) ar[sp][c] = ai[sp][c] = 0;
-    hop_dir<0, 0, DAG, NR, RS>(a, in, links, r0, x, ar, ai);
-    hop_dir<0, 1, DAG, NR, RS>(a, in, links, r0, x, ar, ai);
-    hop_dir<1, 0, DAG, NR, RS>(a, in, links, r0, x, ar, ai);
-    hop_dir<1, 1, DAG, NR, RS>(a, in, links, r0, x, ar, ai);
-    hop_dir<2, 0, DAG, NR, RS>(a, in, links, r0, x, ar, ai);
-    hop_dir<2, 1, DAG, NR, RS>(a, in, links, r0, x, ar, ai);
-    hop_dir<3, 0, DAG, NR, RS>(a, in, links, r0, x, ar, ai);
-    hop_dir<3, 1, DAG, NR, RS>(a, in, links, r0, x, ar, ai);
+    hop_dir<0, 0, DAG, NR, RS>(a, in, links, r0, x, ar, ai, stg);
+    hop_dir<0, 1, DAG, NR, RS>(a, in, links, r0, x, ar, ai, stg);
+    hop_dir<1, 0, DAG, NR, RS>(a, in, links, r0, x, ar, ai, stg);
+    hop_dir<1, 1, DAG, NR, RS>(a, in, links, r0, x, ar, ai, stg);
+    hop_dir<2, 0, DAG, NR, RS>(a, in, links, r0, x, ar, ai, stg);
+    hop_dir<2, 1, DAG, NR, RS>(a, in, links, r0, x, ar, ai, stg);
+    hop_dir<3, 0, DAG, NR, RS>(a, in, links, r0, x, ar, ai, stg);
+    hop_dir<3, 1, DAG, NR, RS>(a, in, links, r0, x, ar, ai, stg);
     if (EPI == EPI_PLAIN) {
         cpx<S> *out = a.out[parity] + roff;
 #pragma unroll
@@ -574,6 +592,30 @@ __device__ __forceinline__ double site_hop(const HopArgs<S> &a, int parity, int 
     return nrm;
 }
 
+// Stage the input spinors of a one-thread-per-site workgroup (sites i0 ..
+// i0 + WG - 1) in LDS: the half-sites from one x3 line (a.g.n3h sites) before
+// i0 to one line after the workgroup's last site, clipped to the half field.
+// They hold every x3 neighbour of the workgroup's sites and, away from the
+// periodic wrap in x2, every x2 neighbour (one line apart), so six of a
+// site's eight neighbour reads usually come from LDS.  Called by every thread
+// (it synchronises the workgroup); a.stage == 0 stages nothing.
+template <int NR, class S>
+__device__ __forceinline__ Stage<S> stage_input(const HopArgs<S> &a, const cpx<S> *__restrict__ in, int i0,
+                                                cpx<S> *lds)
+{
+    constexpr int NC = 4 * NR;
+    if (!a.stage) return Stage<S>{nullptr, 0, 0};
+    const int lo = max(i0 - a.g.n3h, 0);
+    const int hi = min(i0 + WG + a.g.n3h, a.g.half);
+    const int n = hi - lo;
+    for (int e = threadIdx.x; e < NC * n; e += WG) {
+        const int comp = e / n, k = e - comp * n;
+        lds[e] = in[lay(lo + k, comp, NC)];
+    }
+    __syncthreads();
+    return Stage<S>{lds, lo, n};
+}
+
 template <int NR, int RS, class S, bool DAG, int EPI>
 __global__ void __launch_bounds__(WG) hop_kernel(const HopArgs<S> a)
 {
@@ -592,9 +634,14 @@ __global__ void __launch_bounds__(WG) hop_kernel(const HopArgs<S> a)
     const int i = gid / G;
     const int r0 = (gid - i * G) * RS;
     double nrm = 0;
+    Stage<S> stg{nullptr, 0, 0};
+    if constexpr (G == 1) {
+        extern __shared__ __align__(16) unsigned char stage_raw[];
+        stg = stage_input<NR>(a, a.in[1 - parity] + (size_t)rhs * a.rstride, bx * WG, (cpx<S> *)stage_raw);
+    }
     if (i < a.g.half) {
         GlobalLinks<S, NR> links{a.gauge[parity], i};
-        nrm = site_hop<NR, RS, S, DAG, EPI>(a, parity, i, r0, rhs, links);
+        nrm = site_hop<NR, RS, S, DAG, EPI>(a, parity, i, r0, rhs, links, stg);
     }
     if (EPI != EPI_PLAIN && a.partial) {
         const double t = group_sum<G>(nrm, sh);
@@ -624,9 +671,14 @@ __global__ void __launch_bounds__(WG) hop_fused_kernel(const HopArgs<S> a)
     const int i = gid / G;
     const int r0 = (gid - i * G) * RS;
     double nrm = 0;
+    Stage<S> stg{nullptr, 0, 0};
+    if constexpr (G == 1) {
+        extern __shared__ __align__(16) unsigned char stage_raw[];
+        stg = stage_input<NR>(a, a.in[1 - parity] + (size_t)rhs * a.rstride, bx * WG, (cpx<S> *)stage_raw);
+    }
     if (i < a.g.half) {
         RepLinks<S, N, REP> links{a.gauge[parity], i};
-        nrm = site_hop<NR, RS, S, DAG, EPI>(a, parity, i, r0, rhs, links);
+        nrm = site_hop<NR, RS, S, DAG, EPI>(a, parity, i, r0, rhs, links, stg);
     }
     if (EPI != EPI_PLAIN && a.partial) {
         const double t = group_sum<G>(nrm, sh);
@@ -653,9 +705,11 @@ __global__ void __launch_bounds__(WG) hop_su3_kernel(const HopArgs<S> a)
     if (a.run && !a.run[rhs]) return;
     const int i = bx * WG + threadIdx.x;
     double nrm = 0;
+    extern __shared__ __align__(16) unsigned char stage_raw[];
+    const Stage<S> stg = stage_input<3>(a, a.in[1 - parity] + (size_t)rhs * a.rstride, bx * WG, (cpx<S> *)stage_raw);
     if (i < a.g.half) {
         Su3Links<S> links{a.gauge[parity], i};
-        nrm = site_hop<3, 3, S, DAG, EPI>(a, parity, i, 0, rhs, links);
+        nrm = site_hop<3, 3, S, DAG, EPI>(a, parity, i, 0, rhs, links, stg);
     }
     if (EPI != EPI_PLAIN && a.partial) {
         const double t = group_sum<1>(nrm, sh);
@@ -1111,13 +1165,40 @@ void launch_mrhs(const HopArgs<S> &b, hipStream_t st)
     hop_mrhs_kernel<NR, RS, S, D, E, 16><<<grid, dim3(sh.threads), mr_lds<NR, S>(16), st>>>(bt);
 }
 
+// Input staging of the one-thread-per-site kernels (stage_input), where it
+// was measured to pay: 32-bit and 16-bit storage with N_R <= 4 (D_hat at 32^4
+// SU(3) fund FP32 203 vs 211 us, two-row 180 vs 188 us, SU(2) adj 24^3x48
+// 150 vs 155 us).  FP64 and N_R = 6 hops run without it (the 55 KB of staged
+// FP64 spinors leave two workgroups per CU: two-row FP64 D_hat 306 vs 280 us;
+// FP32 N_R = 6 590 vs 569 us).  HRW_HOP_STAGE=0 turns it off, =1 on for every
+// one-thread-per-site instance.  Only where the staged range fits the default
+// 64 KB of LDS.  Returns the dynamic LDS bytes of the launch and sets b.stage.
+inline int hop_stage_mode()
+{
+    const char *e = getenv("HRW_HOP_STAGE");
+    if (!e || !e[0]) return -1;  // default rule
+    return e[0] == '0' ? 0 : 1;
+}
+
+template <int NR, class S, int G>
+size_t plan_stage(HopArgs<S> &b)
+{
+    b.stage = 0;
+    const int mode = hop_stage_mode();
+    if (G != 1 || mode == 0 || (mode < 0 && (dtype_id<S>() == 0 || NR > 4))) return 0;
+    const size_t bytes = (size_t)(WG + 2 * b.g.n3h) * 4 * NR * sizeof(cpx<S>);
+    if (bytes > 65536) return 0;
+    b.stage = 1;
+    return bytes;
+}
+
 template <int NR, int RS, class S, bool MRK>
-void launch_hop_rs(bool dagger, int epi, dim3 grid, const HopArgs<S> &b, hipStream_t st)
+void launch_hop_rs(bool dagger, int epi, dim3 grid, size_t lds, const HopArgs<S> &b, hipStream_t st)
 {
 #define HRW_LAUNCH(D, E)                                                                           \
     do {                                                                                           \
         if (MRK) launch_mrhs<NR, RS, S, D, E>(b, st);                                              \
-        else hop_kernel<NR, RS, S, D, E><<<grid, WG, 0, st>>>(b);                                  \
+        else hop_kernel<NR, RS, S, D, E><<<grid, WG, lds, st>>>(b);                                \
     } while (0)
     if (epi == EPI_PLAIN) {
         if (dagger) HRW_LAUNCH(true, EPI_PLAIN);
@@ -1172,13 +1253,14 @@ hipError_t launch_hop_impl(int nr, bool dagger, int epi, const HopArgs<S> &a, hi
             // grid, tiling and LDS follow the launch shape (launch_mrhs)
             err = allow_lds<NR, RS, S>();
             if (err != hipSuccess) return;
-            launch_hop_rs<NR, RS, S, true>(dagger, epi, dim3(1), b, st);
+            launch_hop_rs<NR, RS, S, true>(dagger, epi, dim3(1), 0, b, st);
         } else {
             const int gh = hop_grid(a.g, G);
             b.grid_half = gh;
             hop_tiling(a.g, WG / G, &b.tile_ts, &b.tile_c);
             dim3 grid(a.parity < 0 ? 2 * gh : gh, a.n_rhs);
-            launch_hop_rs<NR, RS, S, false>(dagger, epi, grid, b, st);
+            const size_t lds = plan_stage<NR, S, G>(b);
+            launch_hop_rs<NR, RS, S, false>(dagger, epi, grid, lds, b, st);
         }
     });
     if (!ok) return hipErrorInvalidValue;
@@ -1205,14 +1287,15 @@ hipError_t launch_hop_fused_impl(int nc, int rep, bool dagger, int epi, const Ho
         b.grid_half = gh;
         hop_tiling(a.g, WG / G, &b.tile_ts, &b.tile_c);
         dim3 grid(a.parity < 0 ? 2 * gh : gh, a.n_rhs);
+        const size_t lds = plan_stage<NR, S, G>(b);
         if (epi == EPI_PLAIN) {
-            if (dagger) hop_fused_kernel<N, REP, NR, RS, S, true, EPI_PLAIN><<<grid, WG, 0, st>>>(b);
-            else hop_fused_kernel<N, REP, NR, RS, S, false, EPI_PLAIN><<<grid, WG, 0, st>>>(b);
+            if (dagger) hop_fused_kernel<N, REP, NR, RS, S, true, EPI_PLAIN><<<grid, WG, lds, st>>>(b);
+            else hop_fused_kernel<N, REP, NR, RS, S, false, EPI_PLAIN><<<grid, WG, lds, st>>>(b);
         } else if (epi == EPI_AXPY) {
-            if (dagger) hop_fused_kernel<N, REP, NR, RS, S, true, EPI_AXPY><<<grid, WG, 0, st>>>(b);
-            else hop_fused_kernel<N, REP, NR, RS, S, false, EPI_AXPY><<<grid, WG, 0, st>>>(b);
+            if (dagger) hop_fused_kernel<N, REP, NR, RS, S, true, EPI_AXPY><<<grid, WG, lds, st>>>(b);
+            else hop_fused_kernel<N, REP, NR, RS, S, false, EPI_AXPY><<<grid, WG, lds, st>>>(b);
         } else {
-            hop_fused_kernel<N, REP, NR, RS, S, true, EPI_CG><<<grid, WG, 0, st>>>(b);
+            hop_fused_kernel<N, REP, NR, RS, S, true, EPI_CG><<<grid, WG, lds, st>>>(b);
         }
         ok = true;
     };
@@ -1237,14 +1320,15 @@ hipError_t launch_hop_su3_impl(bool dagger, int epi, const HopArgs<S> &a, hipStr
     b.grid_half = gh;
     hop_tiling(a.g, WG, &b.tile_ts, &b.tile_c);
     dim3 grid(a.parity < 0 ? 2 * gh : gh, a.n_rhs);
+    const size_t lds = plan_stage<3, S, 1>(b);
     if (epi == EPI_PLAIN) {
-        if (dagger) hop_su3_kernel<S, true, EPI_PLAIN><<<grid, WG, 0, st>>>(b);
-        else hop_su3_kernel<S, false, EPI_PLAIN><<<grid, WG, 0, st>>>(b);
+        if (dagger) hop_su3_kernel<S, true, EPI_PLAIN><<<grid, WG, lds, st>>>(b);
+        else hop_su3_kernel<S, false, EPI_PLAIN><<<grid, WG, lds, st>>>(b);
     } else if (epi == EPI_AXPY) {
-        if (dagger) hop_su3_kernel<S, true, EPI_AXPY><<<grid, WG, 0, st>>>(b);
-        else hop_su3_kernel<S, false, EPI_AXPY><<<grid, WG, 0, st>>>(b);
+        if (dagger) hop_su3_kernel<S, true, EPI_AXPY><<<grid, WG, lds, st>>>(b);
+        else hop_su3_kernel<S, false, EPI_AXPY><<<grid, WG, lds, st>>>(b);
     } else {
-        hop_su3_kernel<S, true, EPI_CG><<<grid, WG, 0, st>>>(b);
+        hop_su3_kernel<S, true, EPI_CG><<<grid, WG, lds, st>>>(b);
     }
     return hipGetLastError();
 }

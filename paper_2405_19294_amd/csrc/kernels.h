@@ -88,6 +88,7 @@ struct HopArgs {
     int red_pstride;
     int red_nparts;
     int red_n;
+    int stage;                   // one-thread-per-site kernels: stage the input in LDS (see stage_input)
 };
 
 // Launch the hopping kernel.  kc_bytes receives the algorithmic bytes.

@@ -360,3 +360,48 @@ def test_reliable_delta_trigger():
     x, res, rc = hrw.cg_solve(g, to_dev(b), 0.135, prm)
     assert rc == 0 and res[0]["reliable_updates"] >= 5  # ten decades, one update per decade
     assert _oracle_resid(dims, ur, 0.135, x.cpu().numpy(), b, "ddag_d_eo") <= 1.01e-10
+
+
+# ------------------------------------------------------------------ input staging in LDS
+
+STAGE_CASES = [((2, 2, 2, 6), 2, "fund"), ((4, 2, 4, 4), 3, "fund"), ((4, 6, 2, 4), 2, "adj"),
+               ((8, 4, 4, 8), 3, "fund"), ((2, 4, 4, 6), 4, "asym"), ((4, 4, 8, 16), 3, "fund")]
+
+
+@pytest.mark.parametrize("case", STAGE_CASES, ids=ids)
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
+def test_staged_input_equals_unstaged(case, dtype, monkeypatch):
+    """The single-source hops read the x3 and x2 neighbours (and, on small lattices, any other
+    neighbour inside the staged range) from the input staged in LDS: D_W, D_W^+ and D_hat equal
+    the unstaged kernels bit for bit, on ragged and several-tile lattices; FP64 also against the
+    oracle."""
+    dims, nc, rep = case
+    uf, ur, g = setup(dims, nc, rep, "haar", seed=51, dtypes=(dtype,))
+    psi = fx.gaussian_spinor(dims, g.nr, seed=52, n_rhs=2)
+    pe = orc.split_eo(dims, psi)[0]
+    got = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("HRW_HOP_STAGE", mode)
+        got[mode] = [hrw.dw_apply(g, 0.12, to_dev(psi[0]), THETA_TW, dtype, d).cpu().numpy() for d in (False, True)]
+        got[mode].append(hrw.deo_apply(g, [0.12, 0.13], to_dev(pe), THETA_TW, dtype).cpu().numpy())
+    for a, b in zip(got["1"], got["0"]):
+        assert np.array_equal(a, b)
+    if dtype == "f64":
+        fp64_close(got["1"][0], orc.dw(dims, ur, 0.12, psi[0], THETA_TW))
+        fp64_close(got["1"][2][1], orc.deo(dims, ur, 0.13, pe[1], THETA_TW))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_staged_input_two_row_and_fused_fields(dtype, monkeypatch):
+    dims = (4, 4, 4, 8)
+    for nc, rep, kw in ((3, "fund", {"two_rows": True}), (2, "adj", {"fused": True}), (3, "sym", {"fused": True})):
+        uf = fx.gauge_field(dims, nc, "thermal", seed=53)
+        g = hrw.Gauge(dims, nc, rep, to_dev(uf), dtypes=(dtype,), **kw)
+        pe = orc.split_eo(dims, fx.gaussian_spinor(dims, g.nr, seed=54))[0]
+        outs = []
+        for mode in ("1", "0"):
+            monkeypatch.setenv("HRW_HOP_STAGE", mode)
+            outs.append([hrw.deo_apply(g, 0.13, to_dev(pe), THETA_TW, dtype, d).cpu().numpy() for d in (False, True)])
+        for a, b in zip(*outs):
+            assert np.array_equal(a, b), (nc, rep)
+        g.close()
