@@ -66,11 +66,10 @@
  *                    ceil(log2(sites per parity))), read before tuning and
  *                    updated after; default $HOME/.cache/hrw/tune.json, an
  *                    empty value keeps the shapes in memory only;
- *   HRW_HOP_STAGE=0|1  input staging in LDS of the single-source hops (the
- *                    x3 and x2 neighbours read from a staged range): off, or on
- *                    for every one-thread-per-site instance; unset, on for
- *                    32-bit and 16-bit storage with N_R <= 4; results are
- *                    bitwise the same either way;
+ *   HRW_HOP_STAGE=1  single-source hops with 32-bit or 16-bit storage and
+ *                    N_R <= 4 stage their input in LDS and read the x3 and x2
+ *                    neighbours from there (slower on MI355X, hence off by
+ *                    default); results are bitwise the same either way;
  *   HRW_MRHS_SITES=16|32  pin the multi-source workgroup to that many sites
  *                    (occupancy-model threads, no tuning; bitwise the same
  *                    results);

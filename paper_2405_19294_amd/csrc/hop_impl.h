@@ -377,7 +377,7 @@ struct Stage {
 };
 
 // one direction (forward or backward) of one mu, for colour rows r0 .. r0+RS-1
-template <int MU, int DIR, bool DAG, int NR, int RS, class S, class LS>
+template <int MU, int DIR, bool DAG, int NR, int RS, class S, class LS, bool STG>
 __device__ __forceinline__ void hop_dir(const HopArgs<S> &a, const cpx<S> *__restrict__ in,
                                         const LS &links, int r0, const int (&x)[4],
                                         typename acc_of<S>::type (&ar)[4][RS],
@@ -400,13 +400,20 @@ __device__ __forceinline__ void hop_dir(const HopArgs<S> &a, const cpx<S> *__res
     }
     const int j = eo_index(a.g, y);
     A pr[4][NR], pi[4][NR];
-    const int k = j - stg.lo;
-    if (stg.l && (unsigned)k < (unsigned)stg.n) {
+    // the staged path is a separate instance: its range check and second load
+    // path cost the unstaged FP64 hop 7% even when nothing was staged
+    bool staged = false;
+    if constexpr (STG) {
+        const int k = j - stg.lo;
+        staged = (unsigned)k < (unsigned)stg.n;
+        if (staged) {
 #pragma unroll
-        for (int sp = 0; sp < 4; ++sp)
+            for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-            for (int c = 0; c < NR; ++c) load_c(stg.l + (sp * NR + c) * stg.n + k, pr[sp][c], pi[sp][c]);
-    } else {
+                for (int c = 0; c < NR; ++c) load_c(stg.l + (sp * NR + c) * stg.n + k, pr[sp][c], pi[sp][c]);
+        }
+    }
+    if (!staged) {
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -521,7 +528,7 @@ __device__ __forceinline__ double group_sum(double v, double *sh)
 
 // the per-site body shared by both kernels: hop of site i for one source,
 // then the epilogue; returns this thread's |.|^2 contribution
-template <int NR, int RS, class S, bool DAG, int EPI, class LS>
+template <int NR, int RS, class S, bool DAG, int EPI, class LS, bool STG = false>
 __device__ __forceinline__ double site_hop(const HopArgs<S> &a, int parity, int i, int r0, int rhs,
                                            const LS &links, const Stage<S> &stg = Stage<S>{nullptr, 0, 0})
 {
@@ -537,14 +544,14 @@ __device__ __forceinline__ double site_hop(const HopArgs<S> &a, int parity, int 
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
         for (int c = 0; c < RS; ++c) ar[sp][c] = ai[sp][c] = 0;
-    hop_dir<0, 0, DAG, NR, RS>(a, in, links, r0, x, ar, ai, stg);
-    hop_dir<0, 1, DAG, NR, RS>(a, in, links, r0, x, ar, ai, stg);
-    hop_dir<1, 0, DAG, NR, RS>(a, in, links, r0, x, ar, ai, stg);
-    hop_dir<1, 1, DAG, NR, RS>(a, in, links, r0, x, ar, ai, stg);
-    hop_dir<2, 0, DAG, NR, RS>(a, in, links, r0, x, ar, ai, stg);
-    hop_dir<2, 1, DAG, NR, RS>(a, in, links, r0, x, ar, ai, stg);
-    hop_dir<3, 0, DAG, NR, RS>(a, in, links, r0, x, ar, ai, stg);
-    hop_dir<3, 1, DAG, NR, RS>(a, in, links, r0, x, ar, ai, stg);
+    hop_dir<0, 0, DAG, NR, RS, S, LS, STG>(a, in, links, r0, x, ar, ai, stg);
+    hop_dir<0, 1, DAG, NR, RS, S, LS, STG>(a, in, links, r0, x, ar, ai, stg);
+    hop_dir<1, 0, DAG, NR, RS, S, LS, STG>(a, in, links, r0, x, ar, ai, stg);
+    hop_dir<1, 1, DAG, NR, RS, S, LS, STG>(a, in, links, r0, x, ar, ai, stg);
+    hop_dir<2, 0, DAG, NR, RS, S, LS, STG>(a, in, links, r0, x, ar, ai, stg);
+    hop_dir<2, 1, DAG, NR, RS, S, LS, STG>(a, in, links, r0, x, ar, ai, stg);
+    hop_dir<3, 0, DAG, NR, RS, S, LS, STG>(a, in, links, r0, x, ar, ai, stg);
+    hop_dir<3, 1, DAG, NR, RS, S, LS, STG>(a, in, links, r0, x, ar, ai, stg);
     if (EPI == EPI_PLAIN) {
         cpx<S> *out = a.out[parity] + roff;
 #pragma unroll
@@ -616,7 +623,7 @@ __device__ __forceinline__ Stage<S> stage_input(const HopArgs<S> &a, const cpx<S
     return Stage<S>{lds, lo, n};
 }
 
-template <int NR, int RS, class S, bool DAG, int EPI>
+template <int NR, int RS, class S, bool DAG, int EPI, bool STG = false>
 __global__ void __launch_bounds__(WG) hop_kernel(const HopArgs<S> a)
 {
     constexpr int G = NR / RS;  // threads per site, each owning RS colour rows
@@ -635,13 +642,13 @@ __global__ void __launch_bounds__(WG) hop_kernel(const HopArgs<S> a)
     const int r0 = (gid - i * G) * RS;
     double nrm = 0;
     Stage<S> stg{nullptr, 0, 0};
-    if constexpr (G == 1) {
+    if constexpr (STG && G == 1) {
         extern __shared__ __align__(16) unsigned char stage_raw[];
         stg = stage_input<NR>(a, a.in[1 - parity] + (size_t)rhs * a.rstride, bx * WG, (cpx<S> *)stage_raw);
     }
     if (i < a.g.half) {
         GlobalLinks<S, NR> links{a.gauge[parity], i};
-        nrm = site_hop<NR, RS, S, DAG, EPI>(a, parity, i, r0, rhs, links, stg);
+        nrm = site_hop<NR, RS, S, DAG, EPI, GlobalLinks<S, NR>, STG && G == 1>(a, parity, i, r0, rhs, links, stg);
     }
     if (EPI != EPI_PLAIN && a.partial) {
         const double t = group_sum<G>(nrm, sh);
@@ -653,7 +660,7 @@ __global__ void __launch_bounds__(WG) hop_kernel(const HopArgs<S> a)
 
 // The single-source kernel with the representation map fused in (RepLinks):
 // a.gauge[q] holds the fundamental hopping blocks of output parity q.
-template <int N, int REP, int NR, int RS, class S, bool DAG, int EPI>
+template <int N, int REP, int NR, int RS, class S, bool DAG, int EPI, bool STG = false>
 __global__ void __launch_bounds__(WG) hop_fused_kernel(const HopArgs<S> a)
 {
     constexpr int G = NR / RS;
@@ -672,13 +679,13 @@ __global__ void __launch_bounds__(WG) hop_fused_kernel(const HopArgs<S> a)
     const int r0 = (gid - i * G) * RS;
     double nrm = 0;
     Stage<S> stg{nullptr, 0, 0};
-    if constexpr (G == 1) {
+    if constexpr (STG && G == 1) {
         extern __shared__ __align__(16) unsigned char stage_raw[];
         stg = stage_input<NR>(a, a.in[1 - parity] + (size_t)rhs * a.rstride, bx * WG, (cpx<S> *)stage_raw);
     }
     if (i < a.g.half) {
         RepLinks<S, N, REP> links{a.gauge[parity], i};
-        nrm = site_hop<NR, RS, S, DAG, EPI>(a, parity, i, r0, rhs, links, stg);
+        nrm = site_hop<NR, RS, S, DAG, EPI, RepLinks<S, N, REP>, STG && G == 1>(a, parity, i, r0, rhs, links, stg);
     }
     if (EPI != EPI_PLAIN && a.partial) {
         const double t = group_sum<G>(nrm, sh);
@@ -690,7 +697,7 @@ __global__ void __launch_bounds__(WG) hop_fused_kernel(const HopArgs<S> a)
 
 // The single-source kernel for SU(3) fundamental links read as two rows per
 // link (Su3Links); one thread per site, as hop_kernel at N_R = 3.
-template <class S, bool DAG, int EPI>
+template <class S, bool DAG, int EPI, bool STG = false>
 __global__ void __launch_bounds__(WG) hop_su3_kernel(const HopArgs<S> a)
 {
     __shared__ double sh[WG / 64];
@@ -705,11 +712,14 @@ __global__ void __launch_bounds__(WG) hop_su3_kernel(const HopArgs<S> a)
     if (a.run && !a.run[rhs]) return;
     const int i = bx * WG + threadIdx.x;
     double nrm = 0;
-    extern __shared__ __align__(16) unsigned char stage_raw[];
-    const Stage<S> stg = stage_input<3>(a, a.in[1 - parity] + (size_t)rhs * a.rstride, bx * WG, (cpx<S> *)stage_raw);
+    Stage<S> stg{nullptr, 0, 0};
+    if constexpr (STG) {
+        extern __shared__ __align__(16) unsigned char stage_raw[];
+        stg = stage_input<3>(a, a.in[1 - parity] + (size_t)rhs * a.rstride, bx * WG, (cpx<S> *)stage_raw);
+    }
     if (i < a.g.half) {
         Su3Links<S> links{a.gauge[parity], i};
-        nrm = site_hop<3, 3, S, DAG, EPI>(a, parity, i, 0, rhs, links, stg);
+        nrm = site_hop<3, 3, S, DAG, EPI, Su3Links<S>, STG>(a, parity, i, 0, rhs, links, stg);
     }
     if (EPI != EPI_PLAIN && a.partial) {
         const double t = group_sum<1>(nrm, sh);
@@ -1165,27 +1175,32 @@ void launch_mrhs(const HopArgs<S> &b, hipStream_t st)
     hop_mrhs_kernel<NR, RS, S, D, E, 16><<<grid, dim3(sh.threads), mr_lds<NR, S>(16), st>>>(bt);
 }
 
-// Input staging of the one-thread-per-site kernels (stage_input), where it
-// was measured to pay: 32-bit and 16-bit storage with N_R <= 4 (D_hat at 32^4
-// SU(3) fund FP32 203 vs 211 us, two-row 180 vs 188 us, SU(2) adj 24^3x48
-// 150 vs 155 us).  FP64 and N_R = 6 hops run without it (the 55 KB of staged
-// FP64 spinors leave two workgroups per CU: two-row FP64 D_hat 306 vs 280 us;
-// FP32 N_R = 6 590 vs 569 us).  HRW_HOP_STAGE=0 turns it off, =1 on for every
-// one-thread-per-site instance.  Only where the staged range fits the default
-// 64 KB of LDS.  Returns the dynamic LDS bytes of the launch and sets b.stage.
-inline int hop_stage_mode()
+// Input staging of the one-thread-per-site kernels (stage_input): opt-in
+// (HRW_HOP_STAGE=1), built for 32-bit and 16-bit storage with N_R <= 4, and
+// used only where the staged range fits the default 64 KB of LDS.  Measured
+// on MI355X it does not pay: D_hat at 32^4 SU(3) fund FP32 204 us staged
+// against 180 us unstaged, two-row 180 against 151 us, SU(2) adj 24^3x48
+// 150 against 129 us (the neighbour reads it replaces mostly hit L2 already,
+// and the copy into LDS, its barrier and the lower occupancy cost more); an
+// FP64 variant (two workgroups per CU with 55 KB of staged spinors) was
+// slower still, and compiling the range check into the unstaged FP64 hop
+// alone cost it 7%, so the staged kernels are separate instances.  Returns
+// the dynamic LDS bytes of the launch and sets b.stage.
+inline bool hop_stage_enabled()
 {
     const char *e = getenv("HRW_HOP_STAGE");
-    if (!e || !e[0]) return -1;  // default rule
-    return e[0] == '0' ? 0 : 1;
+    return e && e[0] == '1';
 }
+
+// whether the staged instances of an (N_R, storage, threads per site) family are built
+template <int NR, class S, int G>
+constexpr bool stage_built() { return G == 1 && dtype_id<S>() != 0 && NR <= 4; }
 
 template <int NR, class S, int G>
 size_t plan_stage(HopArgs<S> &b)
 {
     b.stage = 0;
-    const int mode = hop_stage_mode();
-    if (G != 1 || mode == 0 || (mode < 0 && (dtype_id<S>() == 0 || NR > 4))) return 0;
+    if (!stage_built<NR, S, G>() || !hop_stage_enabled()) return 0;
     const size_t bytes = (size_t)(WG + 2 * b.g.n3h) * 4 * NR * sizeof(cpx<S>);
     if (bytes > 65536) return 0;
     b.stage = 1;
@@ -1198,7 +1213,8 @@ void launch_hop_rs(bool dagger, int epi, dim3 grid, size_t lds, const HopArgs<S>
 #define HRW_LAUNCH(D, E)                                                                           \
     do {                                                                                           \
         if (MRK) launch_mrhs<NR, RS, S, D, E>(b, st);                                              \
-        else hop_kernel<NR, RS, S, D, E><<<grid, WG, lds, st>>>(b);                                \
+        else if (b.stage) hop_kernel<NR, RS, S, D, E, stage_built<NR, S, NR / RS>()><<<grid, WG, lds, st>>>(b); \
+        else hop_kernel<NR, RS, S, D, E><<<grid, WG, 0, st>>>(b);                                  \
     } while (0)
     if (epi == EPI_PLAIN) {
         if (dagger) HRW_LAUNCH(true, EPI_PLAIN);
@@ -1288,15 +1304,22 @@ hipError_t launch_hop_fused_impl(int nc, int rep, bool dagger, int epi, const Ho
         hop_tiling(a.g, WG / G, &b.tile_ts, &b.tile_c);
         dim3 grid(a.parity < 0 ? 2 * gh : gh, a.n_rhs);
         const size_t lds = plan_stage<NR, S, G>(b);
+        constexpr bool SB = stage_built<NR, S, G>();
+#define HRW_FUSED(D, E)                                                                            \
+        do {                                                                                       \
+            if (b.stage) hop_fused_kernel<N, REP, NR, RS, S, D, E, SB><<<grid, WG, lds, st>>>(b);  \
+            else hop_fused_kernel<N, REP, NR, RS, S, D, E><<<grid, WG, 0, st>>>(b);                \
+        } while (0)
         if (epi == EPI_PLAIN) {
-            if (dagger) hop_fused_kernel<N, REP, NR, RS, S, true, EPI_PLAIN><<<grid, WG, lds, st>>>(b);
-            else hop_fused_kernel<N, REP, NR, RS, S, false, EPI_PLAIN><<<grid, WG, lds, st>>>(b);
+            if (dagger) HRW_FUSED(true, EPI_PLAIN);
+            else HRW_FUSED(false, EPI_PLAIN);
         } else if (epi == EPI_AXPY) {
-            if (dagger) hop_fused_kernel<N, REP, NR, RS, S, true, EPI_AXPY><<<grid, WG, lds, st>>>(b);
-            else hop_fused_kernel<N, REP, NR, RS, S, false, EPI_AXPY><<<grid, WG, lds, st>>>(b);
+            if (dagger) HRW_FUSED(true, EPI_AXPY);
+            else HRW_FUSED(false, EPI_AXPY);
         } else {
-            hop_fused_kernel<N, REP, NR, RS, S, true, EPI_CG><<<grid, WG, lds, st>>>(b);
+            HRW_FUSED(true, EPI_CG);
         }
+#undef HRW_FUSED
         ok = true;
     };
     if (nc == 2 && rep == 1) go(std::integral_constant<int, 2>{}, std::integral_constant<int, 1>{});
@@ -1321,15 +1344,22 @@ hipError_t launch_hop_su3_impl(bool dagger, int epi, const HopArgs<S> &a, hipStr
     hop_tiling(a.g, WG, &b.tile_ts, &b.tile_c);
     dim3 grid(a.parity < 0 ? 2 * gh : gh, a.n_rhs);
     const size_t lds = plan_stage<3, S, 1>(b);
+    constexpr bool SB = stage_built<3, S, 1>();
+#define HRW_SU3(D, E)                                                                              \
+    do {                                                                                           \
+        if (b.stage) hop_su3_kernel<S, D, E, SB><<<grid, WG, lds, st>>>(b);                        \
+        else hop_su3_kernel<S, D, E><<<grid, WG, 0, st>>>(b);                                      \
+    } while (0)
     if (epi == EPI_PLAIN) {
-        if (dagger) hop_su3_kernel<S, true, EPI_PLAIN><<<grid, WG, lds, st>>>(b);
-        else hop_su3_kernel<S, false, EPI_PLAIN><<<grid, WG, lds, st>>>(b);
+        if (dagger) HRW_SU3(true, EPI_PLAIN);
+        else HRW_SU3(false, EPI_PLAIN);
     } else if (epi == EPI_AXPY) {
-        if (dagger) hop_su3_kernel<S, true, EPI_AXPY><<<grid, WG, lds, st>>>(b);
-        else hop_su3_kernel<S, false, EPI_AXPY><<<grid, WG, lds, st>>>(b);
+        if (dagger) HRW_SU3(true, EPI_AXPY);
+        else HRW_SU3(false, EPI_AXPY);
     } else {
-        hop_su3_kernel<S, true, EPI_CG><<<grid, WG, lds, st>>>(b);
+        HRW_SU3(true, EPI_CG);
     }
+#undef HRW_SU3
     return hipGetLastError();
 }
 

@@ -371,10 +371,11 @@ STAGE_CASES = [((2, 2, 2, 6), 2, "fund"), ((4, 2, 4, 4), 3, "fund"), ((4, 6, 2, 
 @pytest.mark.parametrize("case", STAGE_CASES, ids=ids)
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
 def test_staged_input_equals_unstaged(case, dtype, monkeypatch):
-    """The single-source hops read the x3 and x2 neighbours (and, on small lattices, any other
-    neighbour inside the staged range) from the input staged in LDS: D_W, D_W^+ and D_hat equal
-    the unstaged kernels bit for bit, on ragged and several-tile lattices; FP64 also against the
-    oracle."""
+    """With HRW_HOP_STAGE=1, 32-bit or 16-bit storage and N_R <= 4, the single-source hops read the
+    x3 and x2 neighbours (and, on small lattices, any other neighbour inside the staged range) from
+    the input staged in LDS: D_W, D_W^+ and D_hat equal the unstaged kernels bit for bit, on ragged
+    and several-tile lattices; the other instances are unaffected by the switch; FP64 also against
+    the oracle."""
     dims, nc, rep = case
     uf, ur, g = setup(dims, nc, rep, "haar", seed=51, dtypes=(dtype,))
     psi = fx.gaussian_spinor(dims, g.nr, seed=52, n_rhs=2)
