@@ -461,12 +461,18 @@ hipError_t launch_cg_alpha(CgState *cs, const double *partial, int pstride, int 
     return hipGetLastError();
 }
 
-__global__ void __launch_bounds__(WG) cg_beta_kernel(CgState *cs, const double *partial, int pstride,
-                                                      int nparts, int max_iter, ReliableSchedule sched,
-                                                      double *beta_out, int *active_out, int *advanced_out,
-                                                      volatile int *host_active)
+// The beta step sits on the critical path of every CG iteration (the x / p
+// update waits for it), so its partial sums are read by 1024 threads (four
+// rounds of eight loads each at 32^4 instead of sixteen; 10.6 -> ~4 us); the
+// summation order is fixed by that workgroup size.
+constexpr int BETA_THREADS = 1024;
+
+__global__ void __launch_bounds__(BETA_THREADS) cg_beta_kernel(CgState *cs, const double *partial, int pstride,
+                                                               int nparts, int max_iter, ReliableSchedule sched,
+                                                               double *beta_out, int *active_out, int *advanced_out,
+                                                               volatile int *host_active)
 {
-    __shared__ double sh[WG / 64];
+    __shared__ double sh[BETA_THREADS / 64];
     const int rhs = blockIdx.x;
     const double rr_new = sum_parts(partial + (size_t)rhs * pstride, nparts, sh);
     if (threadIdx.x == 0) {
@@ -508,7 +514,7 @@ hipError_t launch_cg_beta(CgState *cs, const double *partial, int pstride, int n
                           int max_iter, ReliableSchedule sched, double *beta_out, int *active_out,
                           int *advanced_out, int *host_active, hipStream_t st)
 {
-    cg_beta_kernel<<<n_rhs, WG, 0, st>>>(cs, partial, pstride, nparts, max_iter, sched, beta_out, active_out,
+    cg_beta_kernel<<<n_rhs, BETA_THREADS, 0, st>>>(cs, partial, pstride, nparts, max_iter, sched, beta_out, active_out,
                                          advanced_out, host_active);
     return hipGetLastError();
 }

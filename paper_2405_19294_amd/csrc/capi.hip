@@ -187,16 +187,15 @@ int hrw_gauge_create(const int dims[4], int nc, int rep, const double *u_f, unsi
                     for (int q = 0; q < 2; ++q) h->fblocks[d][q] = ar.take(gauge_block_elems(g, nc) * dtype_cbytes(d));
         unsigned long long *defect =
             (storage_mask & HRW_STORE_SU3_TWO_ROWS) ? (unsigned long long *)ar.take(sizeof(unsigned long long)) : nullptr;
-        hipError_t e = launch_gauge_pack(nc, rep, nr, g, u_f, h->blocks, (hipStream_t)stream);
+        // two-row links: the hops rebuild row 2 as conj(row 0 x row 1), exact only for special
+        // unitary links, so the packing kernel also measures the links' defect (one host sync)
+        hipError_t e = launch_gauge_pack(nc, rep, nr, g, u_f, h->blocks, (hipStream_t)stream, defect);
         // the fundamental links in the same hopping layout (representation map = identity)
         if (e == hipSuccess && (storage_mask & HRW_STORE_FUND_HOP))
             e = launch_gauge_pack(nc, HRW_REP_FUND, nc, g, u_f, h->fblocks, (hipStream_t)stream);
-        // two-row links: the hops rebuild row 2 as conj(row 0 x row 1), exact only for special
-        // unitary links, so the field is checked once here (a reduction and a host sync)
         unsigned long long bits = 0;
         if (e == hipSuccess && defect) {
-            e = launch_su3_defect(8LL * g.half, u_f, defect, (hipStream_t)stream);  // 4 V links
-            if (e == hipSuccess) e = hipMemcpyAsync(&bits, defect, sizeof bits, hipMemcpyDeviceToHost, (hipStream_t)stream);
+            e = hipMemcpyAsync(&bits, defect, sizeof bits, hipMemcpyDeviceToHost, (hipStream_t)stream);
             if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
         }
         if (e != hipSuccess) {

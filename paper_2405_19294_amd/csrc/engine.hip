@@ -932,8 +932,11 @@ int session_create(const hrw_gauge *g, const hrw_solve_params *prm, int n_slots,
     for (auto &e : s->ev)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
             return cleanup(fail(HRW_EDEVICE, "event creation failed"));
-    // all fields start at zero: padding lanes stay finite, x starts at 0
-    if (launch_zero(ar.base, ar.off, st) != hipSuccess) return cleanup(fail(HRW_EDEVICE, "workspace clear failed"));
+    // padding lanes (a half lattice ending in a partial 64-site block) start at zero and so stay
+    // finite in the reductions that sweep whole blocks; every other entry is written before it
+    // is read (x and x64 are cleared when a system is loaded)
+    if (g->g.half % BLK && launch_zero(ar.base, ar.off, st) != hipSuccess)
+        return cleanup(fail(HRW_EDEVICE, "workspace clear failed"));
     free_slots_kernel<<<1, 64, 0, st>>>(P.cs, P.active, n_slots);
     if (hipGetLastError() != hipSuccess) return cleanup(fail(HRW_EDEVICE, "slot init failed"));
     for (int j = 0; j < n_slots; ++j) s->hf.host[j] = 0;

@@ -204,13 +204,11 @@ hipError_t launch_rep_map(int nc, int rep, long long n_links, const double *uf, 
                           hipStream_t st);
 
 // fused representation map + packing into the hopping blocks of every dtype in
-// mask; blocks[dt][q] = packed block for output parity q (or null).
+// mask; blocks[dt][q] = packed block for output parity q (or null).  defect
+// (SU(3) fundamental only, else null): receives max |u_2 - conj(u_0 x u_1)|
+// over the links, as the bit pattern of a double (cleared first).
 hipError_t launch_gauge_pack(int nc, int rep, int nr, const Geom &g, const double *uf,
-                             void *const blocks[4][2], hipStream_t st);
-
-// largest |u_2 - conj(u_0 x u_1)| over the SU(3) links uf ([n][3][3] canonical FP64),
-// written to *out as the bit pattern of a double (device; cleared first)
-hipError_t launch_su3_defect(long long n_links, const double *uf, unsigned long long *out, hipStream_t st);
+                             void *const blocks[4][2], hipStream_t st, unsigned long long *defect = nullptr);
 
 // ------------------------------------------------------------------ vector kernels
 

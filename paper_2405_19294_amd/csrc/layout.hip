@@ -326,16 +326,61 @@ __device__ inline void put_all(const GaugeBlocks &gb, int q, size_t off, C64 v)
     if (gb.p[3][q]) put_link<f16_t>(gb.p[3][q], off, v);
 }
 
+// Largest deviation of an SU(3) link from special unitarity as the two-row hops
+// see it: max over links and entries of |u_2c - conj(u_0a u_1b - u_0b u_1a)|,
+// (a, b) = (c+1, c+2) mod 3.  For a unitary U this is |1 - det U| times the
+// modulus of a row entry, so it catches both non-unitary and U(3) links.  Each
+// wavefront folds its maximum into *out with an integer atomic max (the bit
+// patterns of non-negative doubles order like the numbers; NaN compares
+// larger than any finite value).
+__device__ inline double su3_link_defect(const C64 (&u)[3][3])
+{
+    double m = 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int a = (c + 1) % 3, b = (c + 2) % 3;
+        const C64 x = csub(cmul(u[0][a], u[1][b]), cmul(u[0][b], u[1][a]));
+        const double dr = u[2][c].re - x.re, di = u[2][c].im + x.im;
+        const double d = sqrt(dr * dr + di * di);
+        m = (d > m || d != d) ? d : m;
+    }
+    return m;
+}
+
+// fold a thread's value into *out: wavefront max, then one atomic per wavefront
+// (every lane of the wavefront must call it)
+__device__ inline void fold_defect(double m, unsigned long long *out)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_down(m, off, 64);
+        m = (o > m || o != o) ? o : m;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+
 // one thread per (site, mu): U_R(x, mu) goes to the forward slot of x and, as
 // U_R^+, to the backward slot of x + mu
 template <int N, int REP>
 __global__ void __launch_bounds__(WG) gauge_pack_kernel(Geom g, const double *__restrict__ uf,
-                                                         GaugeBlocks gb)
+                                                         GaugeBlocks gb, unsigned long long *defect)
 {
     constexpr int NR = REP == 0 ? N : REP == 1 ? N * N - 1 : REP == 2 ? N * (N + 1) / 2 : N * (N - 1) / 2;
     constexpr int GC = 8 * NR * NR;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long v = 2LL * g.half;
+    if constexpr (N == 3 && REP == 0) {
+        // special-unitarity check of the fundamental SU(3) links (two-row storage), on the
+        // links this kernel reads anyway; before the bounds return: every lane folds
+        if (defect) {
+            double m = 0;
+            if (t < 4 * v) {
+                C64 u[3][3];
+                load_link<3>(uf + t * 18, u);
+                m = su3_link_defect(u);
+            }
+            fold_defect(m, defect);
+        }
+    }
     if (t >= 4 * v) return;
     const long long s = t >> 2;
     const int mu = (int)(t & 3);
@@ -366,49 +411,14 @@ __global__ void __launch_bounds__(WG) gauge_pack_kernel(Geom g, const double *__
     }
 }
 
-// Largest deviation of an SU(3) link from special unitarity as the two-row hops
-// see it: max over links and entries of |u_2c - conj(u_0a u_1b - u_0b u_1a)|,
-// (a, b) = (c+1, c+2) mod 3.  For a unitary U this is |1 - det U| times the
-// modulus of a row entry, so it catches both non-unitary and U(3) links.  Each
-// workgroup folds its maximum into *out with an integer atomic max (the bit
-// patterns of non-negative doubles order like the numbers; NaN compares
-// larger than any finite value).
-__global__ void __launch_bounds__(WG) su3_defect_kernel(long long n_links, const double *__restrict__ uf,
-                                                        unsigned long long *out)
-{
-    const long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    double m = 0;
-    if (l < n_links) {
-        C64 u[3][3];
-        load_link<3>(uf + l * 18, u);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const int a = (c + 1) % 3, b = (c + 2) % 3;
-            const C64 x = csub(cmul(u[0][a], u[1][b]), cmul(u[0][b], u[1][a]));
-            const double dr = u[2][c].re - x.re, di = u[2][c].im + x.im;
-            const double d = sqrt(dr * dr + di * di);
-            m = (d > m || d != d) ? d : m;
-        }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        const double o = __shfl_down(m, off, 64);
-        m = (o > m || o != o) ? o : m;
-    }
-    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
-}
-
-hipError_t launch_su3_defect(long long n_links, const double *uf, unsigned long long *out, hipStream_t st)
-{
-    hipError_t e = launch_zero(out, sizeof *out, st);
-    if (e != hipSuccess || n_links == 0) return e;
-    const long long blocks = (n_links + WG - 1) / WG;
-    su3_defect_kernel<<<(unsigned)blocks, WG, 0, st>>>(n_links, uf, out);
-    return hipGetLastError();
-}
-
 hipError_t launch_gauge_pack(int nc, int rep, int nr, const Geom &g, const double *uf,
-                             void *const blocks[4][2], hipStream_t st)
+                             void *const blocks[4][2], hipStream_t st, unsigned long long *defect)
 {
+    if (defect && !(nc == 3 && rep == 0)) return hipErrorInvalidValue;
+    if (defect) {
+        hipError_t e = launch_zero(defect, sizeof *defect, st);
+        if (e != hipSuccess) return e;
+    }
     GaugeBlocks gb;
     for (int d = 0; d < 4; ++d)
         for (int q = 0; q < 2; ++q) gb.p[d][q] = blocks[d][q];
@@ -428,7 +438,7 @@ hipError_t launch_gauge_pack(int nc, int rep, int nr, const Geom &g, const doubl
         constexpr int NR = REP == 0 ? N : REP == 1 ? N * N - 1 : REP == 2 ? N * (N + 1) / 2 : N * (N - 1) / 2;
         // only representations with hopping kernels are ever packed (SU(4) adjoint
         // and symmetric, N_R = 15 and 10, are not)
-        if constexpr (NR <= 8) gauge_pack_kernel<N, REP><<<(unsigned)blocks_, WG, 0, st>>>(g, uf, gb);
+        if constexpr (NR <= 8) gauge_pack_kernel<N, REP><<<(unsigned)blocks_, WG, 0, st>>>(g, uf, gb, defect);
     });
     if (!nr_supported(nr)) return hipErrorInvalidValue;
     if (!ok) return hipErrorInvalidValue;
