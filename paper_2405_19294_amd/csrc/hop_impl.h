@@ -934,12 +934,12 @@ struct TuneCache {
             if (b1 == std::string::npos) break;
             const std::string key = text.substr(q0 + 1, q1 - q0 - 1), obj = text.substr(b0, b1 - b0 + 1);
             double t = 0, c = 0, s = 0, us = 0;
-            if (field(obj, "threads", &t) && field(obj, "cmax", &c) && field(obj, "sites", &s)) {
+            // range checks before any conversion: a value outside int's range would be undefined
+            if (field(obj, "threads", &t) && field(obj, "cmax", &c) && field(obj, "sites", &s) && t >= 64 &&
+                t <= MR_MAX_THREADS && (c == 16 || c == 4) && (s == 16 || s == 32)) {
                 field(obj, "us", &us);
                 const MrShape sh{(int)t, (int)c, (int)s};
-                if (sh.threads > 0 && sh.threads <= MR_MAX_THREADS && sh.threads % 64 == 0 &&
-                    (sh.sites == 16 || sh.sites == 32) && (sh.cmax == 16 || sh.cmax == 4))
-                    into[key] = {sh, us};
+                if (sh.threads == t && sh.threads % 64 == 0) into[key] = {sh, us};
             }
             pos = b1 + 1;
         }
