@@ -371,17 +371,25 @@ __global__ void __launch_bounds__(WG) bi_alpha_kernel(BiState *st, int *active, 
     __shared__ double sh[WG / 64];
     const int rhs = blockIdx.x;
     if (!active[rhs]) return;
-    const double den[2] = {part_sum(partial, pstride, nb, rhs, 0, sh), part_sum(partial, pstride, nb, rhs, 1, sh)};
+    const double d0 = part_sum(partial, pstride, nb, rhs, 0, sh);
+    const double d1 = part_sum(partial, pstride, nb, rhs, 1, sh);
     if (threadIdx.x == 0) {
-        BiState c = st[rhs];
+        // alpha = rho / <r0, v>, the arithmetic of cdiv on scalars (a local copy of the
+        // state with its arrays went to scratch)
+        BiState &c = st[rhs];
+        const double a0 = c.rho[0], a1 = c.rho[1];
+        const double d = d0 * d0 + d1 * d1;
+        const double q0 = (a0 * d0 + a1 * d1) / d, q1 = (a1 * d0 - a0 * d1) / d;
         c.fresh = 0;
-        if (!cdiv(c.rho, den, c.alpha)) {
+        if (d > 0 && isfinite(q0) && isfinite(q1)) {
+            c.alpha[0] = q0;
+            c.alpha[1] = q1;
+        } else {
             c.alpha[0] = c.alpha[1] = 0;
             c.status = CG_UPDATE_DUE;
             c.restart = 1;
             active[rhs] = 0;
         }
-        st[rhs] = c;
     }
 }
 

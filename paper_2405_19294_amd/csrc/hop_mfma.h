@@ -215,7 +215,7 @@ __device__ __forceinline__ double mfma_source_sum(double v)
 }
 
 template <int NR, bool DAG, int EPI>
-__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) hop_mfma_kernel(const HopArgs<float> a)
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1))) hop_mfma_kernel(const HopArgs<float> a)
 {
     typedef MfmaGeom<NR> M;
     constexpr int NT = MF_NT, K = M::K, NC = M::NC, GC = M::GC;
@@ -327,7 +327,8 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) ho
 // not the default: at SU(3) sym 32^4 with 24 sources it takes 232 us per
 // source against 112 us for the vector multi-source kernel (operand
 // preparation and reconstruction are ~6000 VALU instructions per wave against
-// 576 MFMAs, at ~250 VGPRs).
+// 576 MFMAs, at ~250 VGPRs; measured at two waves per SIMD with 36-44 bytes of
+// spill per lane; it is compiled for one wave per SIMD now, with no scratch).
 inline bool hop_uses_mfma(int nr, int dt, int n_rhs)
 {
     if (dt != 1 || nr != 6 || n_rhs < 6) return false;
