@@ -40,7 +40,12 @@
  *     [rhs][site][spin][colour];
  *   - gauge field [site][mu 4][row][col], U_mu(x) joins x to x+mu;
  *   - half-parity fields list that parity's sites in lexicographic order.
- * The library converts to its own device layout internally.
+ * Spin components are those of the chiral basis (g_5 = diag(1, 1, -1, -1)).
+ * The library converts to its own device layout internally, and to a spin
+ * basis in which g_0 is diagonal (per colour q_s = psi_s - psi_{s+2},
+ * q_{s+2} = psi_s + psi_{s+2}); results come back in the chiral basis, so the
+ * conversion adds one FP64 rounding each way and, for FP32/16-bit storage,
+ * the storage rounding applies to q.
  *
  * Ownership: every field, storage and workspace pointer is device memory owned
  * by the caller (the Python binding takes it from torch).  The library

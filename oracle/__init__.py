@@ -472,9 +472,12 @@ def set_num_threads(n: int) -> None:
 
 # ---------------------------------------------------------------- rounding-error bound
 
-def hop_abs(dims, u_r_abs, psi_abs) -> np.ndarray:
-    """|H| |psi|: the hop with every link, projector and spinor entry replaced by
-    its absolute value (boundary phases have modulus one and drop out).
+def hop_abs(dims, u_r_abs, psi_abs, gammas=None, dagger=False) -> np.ndarray:
+    """|H| |psi| (or |H^+| |psi|): the hop with every link, projector and spinor
+    entry replaced by its absolute value (boundary phases have modulus one and
+    drop out).  `gammas` (four 4x4 matrices) evaluates the projectors in another
+    spin basis (default: the chiral gamma matrices of gamma()); in the chiral
+    basis |1 - g| = |1 + g| entrywise, so H and H^+ give the same array.
 
     Used for the a-priori componentwise bound of a low-precision D_W
     evaluation, |D psi - fl(D psi)| <= gamma_k (|psi| + kappa |H| |psi|),
@@ -486,23 +489,26 @@ def hop_abs(dims, u_r_abs, psi_abs) -> np.ndarray:
     u = np.asarray(u_r_abs, dtype=np.float64).reshape(d + (4, nr, nr))
     p = np.asarray(psi_abs, dtype=np.float64).reshape(d + (4, nr))
     out = np.zeros_like(p)
+    sign = -1.0 if dagger else 1.0
     for mu in range(4):
-        g = np.abs(gamma(mu))
+        g = gamma(mu) if gammas is None else np.asarray(gammas[mu])
         pf = np.roll(p, -1, axis=mu)            # psi(x + mu)
         pb = np.roll(p, 1, axis=mu)             # psi(x - mu)
         ub = np.roll(u[..., mu, :, :], 1, axis=mu)  # U_mu(x - mu)
-        proj = np.eye(4) + g                    # |1 -+ g| entrywise
         tf = np.einsum("...ab,...sb->...sa", u[..., mu, :, :], pf)
         tb = np.einsum("...ba,...sb->...sa", ub, pb)
-        out += np.einsum("st,...tc->...sc", proj, tf + tb)
+        out += np.einsum("st,...tc->...sc", np.abs(np.eye(4) - sign * g), tf)
+        out += np.einsum("st,...tc->...sc", np.abs(np.eye(4) + sign * g), tb)
     return out.reshape(np.asarray(psi_abs).shape)
 
 
-def hop_abs_real(dims, u_r, psi, theta=None, dagger=False) -> np.ndarray:
+def hop_abs_real(dims, u_r, psi, theta=None, dagger=False, gammas=None) -> np.ndarray:
     """Per real component of H psi (or H^+ psi), the sum of the absolute values of
     its real monomials: every complex product expanded into real products, each
     taken with its absolute value (the real-arithmetic |H||psi| of a rounding-error
     analysis, Higham, Accuracy and Stability of Numerical Algorithms, Sec. 3.6).
+    `gammas` (four 4x4 matrices) evaluates the projectors in another spin basis
+    (default: the chiral gamma matrices of gamma()).
 
     Returned as one complex array: the real part bounds the real components, the
     imaginary part the imaginary components.  A computed evaluation whose every
@@ -520,7 +526,7 @@ def hop_abs_real(dims, u_r, psi, theta=None, dagger=False) -> np.ndarray:
     x = np.indices(d)
     sign = -1.0 if dagger else 1.0
     for mu in range(4):
-        g = gamma(mu)
+        g = gamma(mu) if gammas is None else np.asarray(gammas[mu])
         for fwd in (True, False):
             if fwd:
                 link = u[..., mu, :, :]

@@ -227,24 +227,23 @@ __global__ void __launch_bounds__(64) clover_build_kernel(Geom g, const cpx<doub
     }
 }
 
-// out = B in on the sites of one parity, B a packed block field (A or A^-1);
-// blockIdx.y = rhs, blockIdx.z = chirality, one thread per site
+// out = B in on the sites of one parity, B a packed block field (A or A^-1)
+// whose two blocks act on the chiral halves (spins 0, 1 and 2, 3) of the
+// chiral basis; blockIdx.y = rhs, one thread per site.  The fields are held in
+// the hopping kernels' storage basis (q_s = psi_s - psi_{s+2}, q_{s+2} =
+// psi_s + psi_{s+2}), so the thread forms the chiral halves u = (q_s +
+// q_{s+2}) / 2 and d = (q_{s+2} - q_s) / 2, multiplies u by the first block
+// and d by the second, and returns (B u - B d, B u + B d) in the same basis.
 template <class S, int NR>
-__global__ void __launch_bounds__(WG) clover_mul_kernel(const cpx<S> *__restrict__ bm, const cpx<S> *__restrict__ in,
-                                                        cpx<S> *__restrict__ out, int half, size_t rstride)
+__device__ __forceinline__ void block_mul(const cpx<S> *__restrict__ blk, int i, int chi,
+                                          const typename acc_of<S>::type (&vr)[2 * NR],
+                                          const typename acc_of<S>::type (&vi)[2 * NR],
+                                          typename acc_of<S>::type (&sr)[2 * NR],
+                                          typename acc_of<S>::type (&si)[2 * NR])
 {
     typedef typename acc_of<S>::type A;
     constexpr int M = 2 * NR;
     constexpr int BS = M * M / 2;
-    constexpr int NC = 4 * NR;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= half) return;
-    const int chi = blockIdx.z;
-    const size_t ro = (size_t)blockIdx.y * rstride;
-    const cpx<S> *blk = bm;
-    A vr[M], vi[M], sr[M], si[M];
-#pragma unroll
-    for (int c = 0; c < M; ++c) load_c(in + ro + lay(i, chi * M + c, NC), vr[c], vi[c]);
     // diagonal (real)
 #pragma unroll
     for (int r = 0; r < M; r += 2) {
@@ -271,14 +270,43 @@ __global__ void __launch_bounds__(WG) clover_mul_kernel(const cpx<S> *__restrict
             si[c] = fmac(mr, vi[r], si[c]);
             si[c] = fmac(-mi, vr[r], si[c]);
         }
+}
+
+template <class S, int NR>
+__global__ void __launch_bounds__(WG) clover_mul_kernel(const cpx<S> *__restrict__ bm, const cpx<S> *__restrict__ in,
+                                                        cpx<S> *__restrict__ out, int half, size_t rstride)
+{
+    typedef typename acc_of<S>::type A;
+    constexpr int M = 2 * NR;
+    constexpr int NC = 4 * NR;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= half) return;
+    const size_t ro = (size_t)blockIdx.y * rstride;
+    A ur[M], ui[M], dr[M], di[M];
 #pragma unroll
-    for (int r = 0; r < M; ++r) store_c(out + ro + lay(i, chi * M + r, NC), sr[r], si[r]);
+    for (int c = 0; c < M; ++c) {
+        A ar, ai, br, bi;
+        load_c(in + ro + lay(i, c, NC), ar, ai);
+        load_c(in + ro + lay(i, M + c, NC), br, bi);
+        ur[c] = (ar + br) * (A)0.5;
+        ui[c] = (ai + bi) * (A)0.5;
+        dr[c] = (br - ar) * (A)0.5;
+        di[c] = (bi - ai) * (A)0.5;
+    }
+    A pr[M], pi[M], mr[M], mi[M];
+    block_mul<S, NR>(bm, i, 0, ur, ui, pr, pi);
+    block_mul<S, NR>(bm, i, 1, dr, di, mr, mi);
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        store_c(out + ro + lay(i, c, NC), pr[c] - mr[c], pi[c] - mi[c]);
+        store_c(out + ro + lay(i, M + c, NC), pr[c] + mr[c], pi[c] + mi[c]);
+    }
 }
 
 hipError_t launch_clover_mul(int dt, int nr, const Geom &g, const void *bm, const void *in, void *out, int n_rhs,
                              size_t rstride, hipStream_t st)
 {
-    const dim3 grid((unsigned)((g.half + WG - 1) / WG), (unsigned)n_rhs, 2);
+    const dim3 grid((unsigned)((g.half + WG - 1) / WG), (unsigned)n_rhs, 1);
     bool ok = false;
     dispatch_nr(nr, [&](auto nrc) {
         constexpr int NR = decltype(nrc)::value;

@@ -3,27 +3,41 @@
 //
 // Per output site x and direction mu the thread
 //   1. loads the neighbour spinor psi(x +- mu) (4 N_R complex, coalesced
-//      across the wavefront by the site-blocked layout),
+//      across the wavefront by the site-blocked layout; 2 N_R along mu = 0,
+//      see the spin basis below),
 //   2. projects it to a half-spinor h = (1 -+ g_mu) psi, which has only two
-//      independent spin components in the chiral basis (the same half-spinor
-//      trick the paper uses to halve its messages, Sec. 2.2),
+//      independent spin components (the same half-spinor trick the paper
+//      uses to halve its messages, Sec. 2.2),
 //   3. applies the boundary phase when the hop wraps,
 //   4. multiplies both components by the N_R x N_R link (forward: U_mu(x),
 //      backward: the stored U_mu(x - mu)^+), streaming the link from HBM,
-//   5. reconstructs the lower two spin components and accumulates.
+//   5. reconstructs the other two spin components and accumulates.
 // The epilogue is fused: out = H in, out = self - c H in (with |out|^2
-// partials), or the CG update r -= alpha (self - c H in), x += alpha p with
-// |r|^2 partials.  Partials are reduced per workgroup in a fixed order, so
+// partials), or the CG update r -= alpha (self - c H in) with |r|^2
+// partials.  Partials are reduced per workgroup in a fixed order, so
 // the result is bitwise reproducible.
 //
-// Spin projection in the chiral basis, with s = -1 for (1 - g_mu) and s = +1
-// for (1 + g_mu); psi = (p0, p1 | p2, p3) by spin, g = U h:
-//   mu = 0: h0 = p0 - s p2,    h1 = p1 - s p3;    out2 += -s g0,  out3 += -s g1
+// Spin basis.  Device fields hold q = T psi, psi in the chiral basis and T
+// acting on the spin pairs (s, s + 2) of each colour as
+//   q_s = psi_s - psi_{s+2},  q_{s+2} = psi_s + psi_{s+2}   (s = 0, 1),
+// the packing and unpacking kernels applying T and T^-1.  T is sqrt(2) times a
+// unitary map, so the operator on q is the unitary transform of D: g_1..g_3
+// keep their chiral form and g_0 becomes diag(1, 1, -1, -1).  The two
+// projections along mu = 0 then take one half of the spinor each: (1 - g_0) q
+// = 2 (0, 0, q2, q3) and (1 + g_0) q = 2 (q0, q1, 0, 0).  A hop along mu = 0
+// reads 2 N_R of the neighbour's 4 N_R components and adds to two output spin
+// components only; mu = 0 is the slowest lattice index, whose neighbours lie
+// a whole time slice away and are the most expensive reads of the hop.
+//
+// Spin projection with s = -1 for (1 - g_mu) and s = +1 for (1 + g_mu);
+// q = (p0, p1 | p2, p3) by spin, g = U h:
+//   mu = 0: s = -1: h0 = 2 p2, h1 = 2 p3; out2 += g0, out3 += g1
+//           s = +1: h0 = 2 p0, h1 = 2 p1; out0 += g0, out1 += g1
 //   mu = 1: h0 = p0 - s i p3,  h1 = p1 - s i p2;  out2 += s i g1, out3 += s i g0
 //   mu = 2: h0 = p0 - s p3,    h1 = p1 + s p2;    out2 += s g1,   out3 += -s g0
 //   mu = 3: h0 = p0 - s i p2,  h1 = p1 + s i p3;  out2 += s i g0, out3 += -s i g1
-// (out0 += g0, out1 += g1 always).  The forward hop of H uses s = -1 and the
-// backward hop s = +1; H^+ swaps them.
+// (for mu > 0 out0 += g0, out1 += g1 as well).  The forward hop of H uses
+// s = -1 and the backward hop s = +1; H^+ swaps them.
 #pragma once
 
 #include <stdlib.h>
@@ -55,6 +69,10 @@ __device__ inline double wave_block_sum(double v, double *sh)
     return r;
 }
 
+// first of the two spin components a mu = 0 hop with projector sign SG reads
+// and writes: (1 - g_0) keeps spins 2, 3 and (1 + g_0) spins 0, 1
+template <int SG> constexpr int t_half() { return SG < 0 ? 2 : 0; }
+
 template <int MU, int SG, class A, int NR>
 __device__ __forceinline__ void project(const A (&pr)[4][NR], const A (&pi)[4][NR], A (&hr)[2][NR],
                                         A (&hi)[2][NR])
@@ -62,9 +80,10 @@ __device__ __forceinline__ void project(const A (&pr)[4][NR], const A (&pi)[4][N
     const A s = (A)SG;
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
-        if (MU == 0) {
-            hr[0][c] = pr[0][c] - s * pr[2][c]; hi[0][c] = pi[0][c] - s * pi[2][c];
-            hr[1][c] = pr[1][c] - s * pr[3][c]; hi[1][c] = pi[1][c] - s * pi[3][c];
+        if (MU == 0) {  // only spins B, B + 1 were loaded (t_half)
+            constexpr int B = t_half<SG>();
+            hr[0][c] = 2 * pr[B][c]; hi[0][c] = 2 * pi[B][c];
+            hr[1][c] = 2 * pr[B + 1][c]; hi[1][c] = 2 * pi[B + 1][c];
         } else if (MU == 1) {  // - s i p3, - s i p2 :  i z = (-zi, zr)
             hr[0][c] = pr[0][c] + s * pi[3][c]; hi[0][c] = pi[0][c] - s * pr[3][c];
             hr[1][c] = pr[1][c] + s * pi[2][c]; hi[1][c] = pi[1][c] - s * pr[2][c];
@@ -85,12 +104,15 @@ __device__ __forceinline__ void reconstruct(const A (&gr)[2][NR], const A (&gi)[
     const A s = (A)SG;
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
+        if (MU == 0) {
+            constexpr int B = t_half<SG>();
+            ar[B][c] += gr[0][c]; ai[B][c] += gi[0][c];
+            ar[B + 1][c] += gr[1][c]; ai[B + 1][c] += gi[1][c];
+            continue;
+        }
         ar[0][c] += gr[0][c]; ai[0][c] += gi[0][c];
         ar[1][c] += gr[1][c]; ai[1][c] += gi[1][c];
-        if (MU == 0) {
-            ar[2][c] -= s * gr[0][c]; ai[2][c] -= s * gi[0][c];
-            ar[3][c] -= s * gr[1][c]; ai[3][c] -= s * gi[1][c];
-        } else if (MU == 1) {  // out2 += s i g1, out3 += s i g0
+        if (MU == 1) {  // out2 += s i g1, out3 += s i g0
             ar[2][c] -= s * gi[1][c]; ai[2][c] += s * gr[1][c];
             ar[3][c] -= s * gi[0][c]; ai[3][c] += s * gr[0][c];
         } else if (MU == 2) {  // out2 += s g1, out3 += -s g0
@@ -109,12 +131,19 @@ __device__ __forceinline__ void reconstruct_row(A g0r, A g0i, A g1r, A g1i, A &a
                                                 A &a2r, A &a2i, A &a3r, A &a3i)
 {
     const A s = (A)SG;
+    if (MU == 0) {
+        if (t_half<SG>() == 0) {
+            a0r += g0r; a0i += g0i;
+            a1r += g1r; a1i += g1i;
+        } else {
+            a2r += g0r; a2i += g0i;
+            a3r += g1r; a3i += g1i;
+        }
+        return;
+    }
     a0r += g0r; a0i += g0i;
     a1r += g1r; a1i += g1i;
-    if (MU == 0) {
-        a2r -= s * g0r; a2i -= s * g0i;
-        a3r -= s * g1r; a3i -= s * g1i;
-    } else if (MU == 1) {
+    if (MU == 1) {
         a2r -= s * g1i; a2i += s * g1r;
         a3r -= s * g0i; a3i += s * g0r;
     } else if (MU == 2) {
@@ -402,20 +431,22 @@ __device__ __forceinline__ void hop_dir(const HopArgs<S> &a, const cpx<S> *__res
     A pr[4][NR], pi[4][NR];
     // the staged path is a separate instance: its range check and second load
     // path cost the unstaged FP64 hop 7% even when nothing was staged
+    // spins this hop reads: all four, or along mu = 0 the half its projector keeps
+    constexpr int S0 = MU == 0 ? t_half<SG>() : 0, S1 = MU == 0 ? S0 + 2 : 4;
     bool staged = false;
     if constexpr (STG) {
         const int k = j - stg.lo;
         staged = (unsigned)k < (unsigned)stg.n;
         if (staged) {
 #pragma unroll
-            for (int sp = 0; sp < 4; ++sp)
+            for (int sp = S0; sp < S1; ++sp)
 #pragma unroll
                 for (int c = 0; c < NR; ++c) load_c(stg.l + (sp * NR + c) * stg.n + k, pr[sp][c], pi[sp][c]);
         }
     }
     if (!staged) {
 #pragma unroll
-        for (int sp = 0; sp < 4; ++sp)
+        for (int sp = S0; sp < S1; ++sp)
 #pragma unroll
             for (int c = 0; c < NR; ++c) load_c(in + lay(j, sp * NR + c, NC), pr[sp][c], pi[sp][c]);
     }

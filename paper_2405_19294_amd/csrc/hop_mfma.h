@@ -25,13 +25,15 @@
 // Lane (site b, source s, half h) accumulates the output spin components h
 // and 2 + h of its source in real-embedded form (rows: Re of the N_R colours,
 // then Im).  Projection and reconstruction, with sg = the projector sign of
-// the hop direction and e_h = +1 for h = 0, -1 for h = 1 (chiral basis):
-//   mu = 0: h_h = p_h - sg p_{h+2};         lower_h += -sg g_h
+// the hop direction and e_h = +1 for h = 0, -1 for h = 1, in the storage
+// basis of the vector kernel (g_0 diagonal there):
+//   mu = 0: sg = -1: h_h = 2 p_{h+2}; lower_h += g_h
+//           sg = +1: h_h = 2 p_h;     upper_h += g_h
 //   mu = 1: h_h = p_h - sg i p_{3-h};       lower_h +=  sg i g_{1-h}
 //   mu = 2: h_h = p_h - e_h sg p_{3-h};     lower_h +=  e_h sg g_{1-h}
 //   mu = 3: h_h = p_h - e_h sg i p_{2+h};   lower_h +=  e_h sg i g_h
-// (upper_h += g_h always), the same table as the vector kernel's, split by
-// half-spinor component.
+// (for mu > 0 upper_h += g_h as well), the same table as the vector
+// kernel's, split by half-spinor component.
 #pragma once
 
 #include <stdlib.h>
@@ -82,9 +84,9 @@ __device__ __forceinline__ void mfma_dir(const HopArgs<float> &a, const cpx<floa
         if (wrap) y[MU] = a.g.d[MU] - 1;
     }
     const int j = eo_index(a.g, y);
-    // spin components entering the lane's half-spinor component
-    const int sa = h;
-    const int sb = MU == 0 ? h + 2 : (MU == 3 ? h + 2 : 3 - h);
+    // spin components entering the lane's half-spinor component (one along mu = 0)
+    const int sa = MU == 0 ? t_half<SG>() + h : h;
+    const int sb = MU == 3 ? h + 2 : 3 - h;
     // A operand.  The 2 N_R real-embedded rows are ordered so that lanes q = 0, 1
     // hold the Re rows and q = 2, 3 the Im rows: lane row i of tile m is
     // Re row 2m + i (i < 2) or Im row 2m + i - 2 (i >= 2), i.e. the lane reads
@@ -121,7 +123,7 @@ __device__ __forceinline__ void mfma_dir(const HopArgs<float> &a, const cpx<floa
 #pragma unroll
             for (int c = 0; c < NR; ++c) {
                 load_c(pa + c * BLK, pr[0][c], pi[0][c]);
-                load_c(pb + c * BLK, pr[1][c], pi[1][c]);
+                if (MU != 0) load_c(pb + c * BLK, pr[1][c], pi[1][c]);
             }
         } else {
 #pragma unroll
@@ -133,7 +135,10 @@ __device__ __forceinline__ void mfma_dir(const HopArgs<float> &a, const cpx<floa
 #pragma unroll
         for (int c = 0; c < NR; ++c) {
             float hr, hi;
-            if (MU == 0 || MU == 2) {
+            if (MU == 0) {
+                hr = 2 * pr[0][c];
+                hi = 2 * pi[0][c];
+            } else if (MU == 2) {
                 hr = fmac(wr, pr[1][c], pr[0][c]);
                 hi = fmac(wr, pi[1][c], pi[0][c]);
             } else {  // i z = (-z_im, z_re)
@@ -176,6 +181,14 @@ __device__ __forceinline__ void mfma_dir(const HopArgs<float> &a, const cpx<floa
                 const int row = 2 * m + (i & 1);
                 if (row < NR) g[(i < 2 ? 0 : NR) + row] = d[m][t][i];
             }
+        if (MU == 0) {
+#pragma unroll
+            for (int rho = 0; rho < K; ++rho) {
+                if (t_half<SG>() == 0) up[t][rho] += g[rho];
+                else lo[t][rho] += g[rho];
+            }
+            continue;
+        }
 #pragma unroll
         for (int rho = 0; rho < K; ++rho) up[t][rho] += g[rho];
         if (MU == 1 || MU == 2) {

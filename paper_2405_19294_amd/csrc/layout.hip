@@ -39,17 +39,21 @@ __global__ void __launch_bounds__(WG) pack_spinor_kernel(Geom g, int nr, bool fu
         const int i = (int)(bk / nc) * BLK + lane;
         cpx<S> v;
         if (i < g.half) {
-            size_t sidx;
+            size_t sbase;  // the site's first canonical component
             if (full) {
                 int x[4];
                 eo_coords(g, q, i, x);
                 const size_t lex = (((size_t)x[0] * g.d[1] + x[1]) * g.d[2] + x[2]) * g.d[3] + x[3];
-                sidx = ((size_t)rhs * 2 * g.half + lex) * nc + k;
+                sbase = ((size_t)rhs * 2 * g.half + lex) * nc;
             } else {
-                sidx = ((size_t)rhs * g.half + i) * nc + k;
+                sbase = ((size_t)rhs * g.half + i) * nc;
             }
-            v.re = conv<S>::from_f64(src[2 * sidx]);
-            v.im = conv<S>::from_f64(src[2 * sidx + 1]);
+            // storage basis: q_s = psi_s - psi_{s+2}, q_{s+2} = psi_s + psi_{s+2}
+            const int sp = k / nr, c = k - sp * nr;
+            const size_t up = sbase + (size_t)(sp & 1) * nr + c, dn = up + 2 * nr;
+            const double sg = sp < 2 ? -1.0 : 1.0;
+            v.re = conv<S>::from_f64(src[2 * up] + sg * src[2 * dn]);
+            v.im = conv<S>::from_f64(src[2 * up + 1] + sg * src[2 * dn + 1]);
         } else {
             v.re = conv<S>::from_f64(0.0);
             v.im = conv<S>::from_f64(0.0);
@@ -91,10 +95,15 @@ __global__ void __launch_bounds__(WG) unpack_spinor_kernel(Geom g, int nr, bool 
             i = (int)site;
         }
         const cpx<S> *src = (q == 0 ? src0 : src1) + (size_t)rhs * rstride;
-        A re, im;
-        load_c(src + lay(i, k, nc), re, im);
-        dst[2 * t] = (double)re;
-        dst[2 * t + 1] = (double)im;
+        // chiral basis: psi_s = (q_s + q_{s+2}) / 2, psi_{s+2} = (q_{s+2} - q_s) / 2, in FP64
+        const int sp = k / nr, c = k - sp * nr;
+        const int ka = (sp & 1) * nr + c, kb = ka + 2 * nr;
+        A ar, ai, br, bi;
+        load_c(src + lay(i, ka, nc), ar, ai);
+        load_c(src + lay(i, kb, nc), br, bi);
+        const double sg = sp < 2 ? 1.0 : -1.0;
+        dst[2 * t] = ((double)br + sg * (double)ar) * 0.5;
+        dst[2 * t + 1] = ((double)bi + sg * (double)ai) * 0.5;
     }
 }
 

@@ -64,11 +64,18 @@ static __device__ inline double q_part_sum(const double *partial, int pstride, i
     return q_wg_sum(strided_sum(partial + (size_t)rhs * pstride + (size_t)k * nb, threadIdx.x, nb, blockDim.x), sh);
 }
 
-// g5 = diag(1, 1, -1, -1) in spin: the sign of packed element e (site blocks of BLK, component-major)
-static __device__ inline double g5_sign(size_t e, int ncomp, int nr)
+// The packed fields are in the hopping kernels' storage basis (q_s = psi_s -
+// psi_{s+2}, q_{s+2} = psi_s + psi_{s+2}, T = sqrt(2) x unitary), in which g5 =
+// diag(1, 1, -1, -1) of the chiral basis becomes the exchange of the spin
+// pairs (s, s + 2): [a, b] = sum conj(a_s) b_{s+2} + conj(a_{s+2}) b_s.  The
+// form and the norms both scale by 2 against the chiral basis, so every
+// coefficient of the process is the chiral one.  The loops below run over the
+// upper spin pairs (s = 0, 1): index u of the n / 2 of them gives the element
+// e of spin s and its partner e + 2 N_R BLK of spin s + 2.
+static __device__ inline size_t q_upper(size_t u, int nr)
 {
-    const int comp = (int)((e / BLK) % (size_t)ncomp);
-    return comp < 2 * nr ? 1.0 : -1.0;
+    const size_t half_blk = (size_t)2 * nr * BLK;
+    return (u / half_blk) * 2 * half_blk + u % half_blk;
 }
 
 #define Q_LOOP(n)                                                                                  \
@@ -83,12 +90,13 @@ __global__ void __launch_bounds__(WG) q_jdot_kernel(const cpx<double> *__restric
     __shared__ double sh[WG / 64];
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
-    const size_t o = (size_t)rhs * rs;
+    const size_t o = (size_t)rhs * rs, pair = (size_t)2 * nr * BLK;
     double s = 0;
-    Q_LOOP(n)
+    Q_LOOP(n / 2)
     {
-        const cpx<double> a = v[o + e], b = w[o + e];
-        s += g5_sign(e, 4 * nr, nr) * (a.re * b.re + a.im * b.im);
+        const size_t eu = o + q_upper(e, nr), ed = eu + pair;
+        const cpx<double> au = v[eu], ad = v[ed], bu = w[eu], bd = w[ed];
+        s += (au.re * bd.re + au.im * bd.im) + (ad.re * bu.re + ad.im * bu.im);
     }
     const double t = q_wg_sum(s, sh);
     if (threadIdx.x == 0) partial[(size_t)rhs * pstride + blockIdx.x] = t;
@@ -118,15 +126,21 @@ __global__ void __launch_bounds__(WG) q_lanczos_kernel(cpx<double> *__restrict__
     if (!active[rhs]) return;
     const size_t o = (size_t)rhs * rs;
     const double al = st[rhs].alpha, be = st[rhs].beta;
+    const size_t pair = (size_t)2 * nr * BLK;
     double nn = 0, jj = 0;
-    Q_LOOP(n)
+    Q_LOOP(n / 2)
     {
-        const cpx<double> a = w[o + e], b = v[o + e], c = vp[o + e];
-        const double re = a.re - al * b.re - be * c.re, im = a.im - al * b.im - be * c.im;
-        w[o + e] = {re, im};
-        const double m = re * re + im * im;
-        nn += m;
-        jj += g5_sign(e, 4 * nr, nr) * m;
+        double re[2], im[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const size_t x = o + q_upper(e, nr) + h * pair;
+            const cpx<double> a = w[x], b = v[x], c = vp[x];
+            re[h] = a.re - al * b.re - be * c.re;
+            im[h] = a.im - al * b.im - be * c.im;
+            w[x] = {re[h], im[h]};
+            nn += re[h] * re[h] + im[h] * im[h];
+        }
+        jj += 2 * (re[0] * re[1] + im[0] * im[1]);
     }
     const double t1 = q_wg_sum(nn, sh), t2 = q_wg_sum(jj, sh);
     if (threadIdx.x == 0) {
@@ -223,15 +237,21 @@ __global__ void __launch_bounds__(WG) q_resid_kernel(const cpx<double> *__restri
     const int rhs = blockIdx.y;
     if (!due[rhs]) return;
     const size_t o = (size_t)rhs * rs;
+    const size_t pair = (size_t)2 * nr * BLK;
     double nn = 0, jj = 0;
-    Q_LOOP(n)
+    Q_LOOP(n / 2)
     {
-        const cpx<double> a = b[o + e], c = q[o + e];
-        const double re = a.re - c.re, im = a.im - c.im;
-        r[o + e] = {re, im};
-        const double m = re * re + im * im;
-        nn += m;
-        jj += g5_sign(e, 4 * nr, nr) * m;
+        double re[2], im[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const size_t x = o + q_upper(e, nr) + h * pair;
+            const cpx<double> a = b[x], c = q[x];
+            re[h] = a.re - c.re;
+            im[h] = a.im - c.im;
+            r[x] = {re[h], im[h]};
+            nn += re[h] * re[h] + im[h] * im[h];
+        }
+        jj += 2 * (re[0] * re[1] + im[0] * im[1]);
     }
     const double t1 = q_wg_sum(nn, sh), t2 = q_wg_sum(jj, sh);
     if (threadIdx.x == 0) {

@@ -1,4 +1,9 @@
-"""Shared setup for the GPU parity tests (inputs from fixtures, references from oracle)."""
+"""Shared setup for the GPU parity tests (inputs from fixtures, references from oracle).
+
+The low-precision bounds are checked in the library's storage spin basis (spin_basis): the
+library rounds the storage-basis components of its input, evaluates the operator there and
+returns the chiral components of its stored output, which a test recovers exactly.
+"""
 
 import numpy as np
 import torch
@@ -6,6 +11,7 @@ import torch
 import fixtures as fx
 import oracle as orc
 from paper_2405_19294_amd import hrw
+from spin_basis import storage_gammas, stored, to_chiral, to_storage
 
 THETA_AP = (np.pi, 0.0, 0.0, 0.0)
 THETA_TW = (np.pi, 0.7, -0.4, 1.3)
@@ -48,17 +54,25 @@ def hop_rounding_count(nr):
     return 2 * nr + 14
 
 
-def lowprec_bound(dims, ur_r, psi_r, kappa, nr, theta=THETA_TW, dagger=False):
-    """Per real component, the a-priori bound of an FP32 evaluation of D_W (or D_W^+)
-    on the rounded inputs: gamma_m (|psi| + kappa |H||psi|) with |H||psi| the sum of the
-    absolute values of the real monomials (oracle.hop_abs_real) and m from
-    hop_rounding_count (Higham, Accuracy and Stability of Numerical Algorithms, Sec. 3.1,
-    3.6).  Returned as one complex array: real part for the real components, imaginary
-    part for the imaginary ones."""
-    hr = orc.hop_abs_real(dims, ur_r, psi_r, theta, dagger)
+def lowprec_bound(dims, ur_r, q_r, kappa, nr, theta=THETA_TW, dagger=False):
+    """Per real component of the storage basis, the a-priori bound of an FP32 evaluation of
+    D_W (or D_W^+) on the stored input q_r: gamma_m (|q| + kappa |H'||q|) with |H'||q| the sum
+    of the absolute values of the real monomials of the hop in that basis
+    (oracle.hop_abs_real with its gamma matrices) and m from hop_rounding_count (Higham,
+    Accuracy and Stability of Numerical Algorithms, Sec. 3.1, 3.6).  Returned as one complex
+    array: real part for the real components, imaginary part for the imaginary ones."""
+    hr = orc.hop_abs_real(dims, ur_r, q_r, theta, dagger, gammas=storage_gammas())
     gm = orc.gamma_k(hop_rounding_count(nr), U32)
-    p = np.asarray(psi_r)
+    p = np.asarray(q_r)
     return gm * (np.abs(p.real) + kappa * hr.real) + 1j * gm * (np.abs(p.imag) + kappa * hr.imag)
+
+
+def pair_slack(bound, rel=1e-12):
+    """rel times the bound summed over each spin pair (s, s + 2): room for the FP64 rounding
+    of the oracle's reference and of the basis conversions (relative 1e-16, four orders
+    below the FP32 bounds it is added to), which mix the two components of a pair."""
+    b = np.asarray(bound)
+    return rel * (b + np.concatenate([b[..., 2:4, :], b[..., 0:2, :]], axis=-2))
 
 
 def check_real_bound(out, ref, bound, unit_out):
@@ -73,8 +87,23 @@ def check_real_bound(out, ref, bound, unit_out):
     return excess
 
 
-def bound_check(dims, ur_r, psi_r, kappa, out, ref, nr, unit_out, theta=THETA_TW, dagger=False):
-    """A low-precision D_W apply against the oracle's FP64 D_W on the same rounded inputs,
-    per real component within lowprec_bound, plus one rounding to the output format
-    for 16-bit storage (FP32 output: unit_out is the FP32 unit, a harmless extra)."""
-    return check_real_bound(out, ref, lowprec_bound(dims, ur_r, psi_r, kappa, nr, theta, dagger), unit_out)
+def check_stored(out, ref, bound, unit_out):
+    """check_real_bound in the storage basis: out is the library's result in the chiral
+    basis (its stored output recovered exactly by to_storage), ref the oracle's FP64 value
+    in the chiral basis and bound a storage-basis bound (widened by pair_slack)."""
+    return check_real_bound(to_storage(out), to_storage(ref), bound + pair_slack(bound), unit_out)
+
+
+def stored_input(dtype, psi):
+    """(q_r, psi_r): the library's stored form of psi and the same field in the chiral basis
+    (exact), the input the oracle's reference is evaluated on."""
+    q_r = stored(dtype, psi)
+    return q_r, to_chiral(q_r)
+
+
+def bound_check(dims, ur_r, q_r, kappa, out, ref, nr, unit_out, theta=THETA_TW, dagger=False):
+    """A low-precision D_W apply against the oracle's FP64 D_W on the same stored input
+    (ref = D_W to_chiral(q_r)), per real component of the storage basis within
+    lowprec_bound, plus one rounding to the output format for 16-bit storage (FP32 output:
+    unit_out is the FP32 unit, a harmless extra)."""
+    return check_stored(out, ref, lowprec_bound(dims, ur_r, q_r, kappa, nr, theta, dagger), unit_out)

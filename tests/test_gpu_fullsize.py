@@ -22,7 +22,7 @@ import fixtures as fx
 import oracle as orc
 from paper_2405_19294_amd import hrw
 
-from gpu_helpers import THETA_AP, U32, bound_check, fp64_close, rel, to_dev
+from gpu_helpers import THETA_AP, U32, bound_check, fp64_close, rel, stored_input, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -51,9 +51,10 @@ def test_c2_operators_full_size(c2_field):
     for dagger in (False, True):
         out = hrw.deo_apply(g, KAPPA, to_dev(pe), THETA_AP, "f64", dagger=dagger).cpu().numpy()
         fp64_close(out, orc.deo(C2, ur, KAPPA, pe, THETA_AP, dagger=dagger))
-    ur_r, psi_r = orc.round_to("f32", ur), orc.round_to("f32", psi)
+    ur_r = orc.round_to("f32", ur)
+    q_r, psi_r = stored_input("f32", psi)
     out32 = hrw.dw_apply(g, KAPPA, to_dev(psi), THETA_AP, "f32").cpu().numpy()
-    bound_check(C2, ur_r, psi_r, KAPPA, out32, orc.dw(C2, ur_r, KAPPA, psi_r, THETA_AP), 3, 0.0, THETA_AP)
+    bound_check(C2, ur_r, q_r, KAPPA, out32, orc.dw(C2, ur_r, KAPPA, psi_r, THETA_AP), 3, 0.0, THETA_AP)
 
 
 def test_c2_solve_residual_by_oracle(c2_field):

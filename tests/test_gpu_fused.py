@@ -5,7 +5,9 @@ Tolerances:
   * FP64: the same as the stored-U_R path (l2 relative <= 1e-13, componentwise <= 1e-12 max|ref|);
     the rows of U_R are built from U in FP64 and R(U^+) = R(U)^+ holds to the unitarity of U.
   * FP32 arithmetic on FP32 / BF16 / FP16 storage: the oracle applies FP64 D with U_R = R(U_r), the
-    representation map of the rounded stored fundamental links U_r, to the rounded input.  Besides
+    representation map of the rounded stored fundamental links U_r, to the stored input (its
+    storage-basis components rounded; every bound is checked per real component of that basis,
+    gpu_helpers).  Besides
     the hop's own bound, per real component gamma_m (|psi| + kappa |H||psi|) with m = 2 N_R + 14
     and u = 2^-24 (gpu_helpers.lowprec_bound), the kernel's
     evaluation of each U_R entry from U_r adds at most 2 gamma_5 (every entry is a sum of at most
@@ -22,8 +24,9 @@ import fixtures as fx
 import oracle as orc
 from paper_2405_19294_amd import hrw
 
-from gpu_helpers import (THETA_AP, THETA_TW, U32, U_BF16, U_F16, bound_check, check_real_bound, fp64_close,
-                         lowprec_bound, rel, to_dev)
+from gpu_helpers import (THETA_AP, THETA_TW, U32, U_BF16, U_F16, bound_check, check_stored, fp64_close,
+                         lowprec_bound, rel, stored_input, to_dev)
+from spin_basis import storage_gammas
 
 pytestmark = pytest.mark.gpu
 
@@ -76,21 +79,21 @@ def test_fused_low_precision_within_bound(case, dtype):
     kappa = 0.137
     psi = fx.gaussian_spinor(dims, g.nr, seed=14)
     nr = g.nr
-    psi_r = orc.round_to(dtype, psi)
+    q_r, psi_r = stored_input(dtype, psi)
     out = hrw.dw_apply(g, kappa, to_dev(psi), THETA_TW, dtype).cpu().numpy()
     unit_out = {"f32": U32, "bf16": U_BF16, "f16": U_F16}[dtype]
     if dtype != "f32" and nr > 4:
         # 16-bit storage with N_R = 6 keeps reading the stored U_R (the fused hop does not pay there)
         ur_r = orc.round_to(dtype, ur)
-        bound_check(dims, ur_r, psi_r, kappa, out, orc.dw(dims, ur_r, kappa, psi_r, THETA_TW), nr, unit_out)
+        bound_check(dims, ur_r, q_r, kappa, out, orc.dw(dims, ur_r, kappa, psi_r, THETA_TW), nr, unit_out)
         return
     uf_r = orc.round_to(dtype, uf)
     ur_ref = orc.rep_map(nc, rep, uf_r)
     ref = orc.dw(dims, ur_ref, kappa, psi_r, THETA_TW)
     ones = np.ones_like(np.abs(ur_ref))
-    rows = 2 * orc.gamma_k(5, U32) * kappa * orc.hop_abs(dims, ones, np.abs(psi_r))
-    check_real_bound(out, ref, lowprec_bound(dims, ur_ref, psi_r, kappa, nr) + rows * (1 + 1j),
-                     0.0 if dtype == "f32" else unit_out)
+    rows = 2 * orc.gamma_k(5, U32) * kappa * orc.hop_abs(dims, ones, np.abs(q_r), gammas=storage_gammas())
+    check_stored(out, ref, lowprec_bound(dims, ur_ref, q_r, kappa, nr) + rows * (1 + 1j),
+                 0.0 if dtype == "f32" else unit_out)
     assert rel(out, orc.dw(dims, ur, kappa, psi, THETA_TW)) < {"f32": 1e-6, "bf16": 2e-2, "f16": 3e-3}[dtype]
 
 

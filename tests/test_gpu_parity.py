@@ -2,11 +2,12 @@
 
 Tolerances:
   * FP64 operators: l2 relative <= 1e-13 and componentwise <= 1e-12 max|ref|.
-  * FP32 operators: the oracle applies FP64 D to the FP32-rounded inputs and the
-    difference must sit inside the a-priori componentwise bound
-    gamma_m (|psi| + kappa |H||psi|) per real component, with |H||psi| summing the absolute
-    values of the real monomials and m = 2 N_R + 14 roundings (gpu_helpers.hop_rounding_count),
-    u = 2^-24.
+  * FP32 operators: the library stores the input's storage-basis components (spin_basis: q = T psi,
+    in which g_0 is diagonal) rounded to FP32; the oracle applies FP64 D to the same stored input
+    and the difference must sit inside the a-priori componentwise bound
+    gamma_m (|q| + kappa |H'||q|) per real component of the storage basis, with |H'||q| summing
+    the absolute values of the real monomials of the hop in that basis and m = 2 N_R + 14
+    roundings (gpu_helpers.hop_rounding_count), u = 2^-24.
   * BF16/FP16 storage: the same with the inputs rounded to the 16-bit format,
     plus one rounding of the stored output (u16 |ref|).
   * Storage rounding itself (kappa = 0 applies) is bit-exact.
@@ -23,7 +24,9 @@ import fixtures as fx
 import oracle as orc
 from paper_2405_19294_amd import hrw
 
-from gpu_helpers import (THETA_AP, THETA_TW, U32, U_BF16, U_F16, bound_check, fp64_close, rel, setup, to_dev)
+from gpu_helpers import (THETA_AP, THETA_TW, U32, U_BF16, U_F16, bound_check, fp64_close, rel, setup, stored_input,
+                         to_dev)
+from spin_basis import stored, to_chiral
 
 pytestmark = pytest.mark.gpu
 
@@ -87,11 +90,11 @@ def test_dw_low_precision_within_bound(case, dtype):
     psi = fx.gaussian_spinor(dims, g.nr, seed=8)
     kappa = 0.137
     ur_r = orc.round_to(dtype, ur)
-    psi_r = orc.round_to(dtype, psi)
+    q_r, psi_r = stored_input(dtype, psi)
     out = hrw.dw_apply(g, kappa, to_dev(psi), THETA_TW, dtype).cpu().numpy()
     ref = orc.dw(dims, ur_r, kappa, psi_r, THETA_TW)
     unit_out = {"f32": 0.0, "bf16": U_BF16, "f16": U_F16}[dtype]
-    bound_check(dims, ur_r, psi_r, kappa, out, ref, g.nr, unit_out)
+    bound_check(dims, ur_r, q_r, kappa, out, ref, g.nr, unit_out)
     # the storage error alone is reported against the unrounded FP64 operator
     exact = orc.dw(dims, ur, kappa, psi, THETA_TW)
     assert rel(out, exact) < {"f32": 1e-6, "bf16": 2e-2, "f16": 3e-3}[dtype]
@@ -99,14 +102,15 @@ def test_dw_low_precision_within_bound(case, dtype):
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
 def test_storage_rounding_bit_exact(dtype):
-    """kappa = 0 returns the stored input: it must equal the oracle's RNE rounding bit for bit."""
+    """kappa = 0 returns the stored input: the RNE rounding of its storage-basis components
+    (formed in FP64), brought back to the chiral basis in FP64, bit for bit."""
     dims = (4, 2, 2, 4)
     uf, ur, g = setup(dims, 3, "fund", "haar", seed=9, dtypes=(dtype,))
     g_ = fx.rng(10, 1)
     psi = (g_.standard_normal((fx.volume(dims), 4, 3)) * 10.0 ** g_.integers(-6, 4, (fx.volume(dims), 4, 3))
            + 1j * g_.standard_normal((fx.volume(dims), 4, 3)))
     out = hrw.dw_apply(g, 0.0, to_dev(psi), THETA_AP, dtype).cpu().numpy()
-    assert np.array_equal(out, orc.round_to(dtype, psi))
+    assert np.array_equal(out, to_chiral(stored(dtype, psi)))
 
 
 def test_multi_rhs_apply_equals_single():
@@ -168,8 +172,8 @@ def test_mfma_multi_source_within_fp32_bound(nc, rep, n, dims, monkeypatch):
     monkeypatch.delenv("HRW_MRHS_MFMA")
     ur_r = orc.round_to("f32", ur)
     for k in range(n):
-        psi_r = orc.round_to("f32", psi[k])
-        bound_check(dims, ur_r, psi_r, 0.12, many[k], orc.dw(dims, ur_r, 0.12, psi_r, THETA_TW), g.nr, 0.0)
+        q_r, psi_r = stored_input("f32", psi[k])
+        bound_check(dims, ur_r, q_r, 0.12, many[k], orc.dw(dims, ur_r, 0.12, psi_r, THETA_TW), g.nr, 0.0)
         for d in (False, True):
             one = hrw.deo_apply(g, 0.125, to_dev(pe[k]), THETA_TW, "f32", dagger=d).cpu().numpy()
             assert np.max(np.abs(many_eo[d][k] - one)) <= 1e-6 * np.max(np.abs(one))

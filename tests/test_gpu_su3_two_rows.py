@@ -5,7 +5,8 @@ Tolerances:
   * FP64: the same as the stored-link path (l2 relative <= 1e-13, componentwise <= 1e-12 max|ref|);
     the rebuilt row conj(u_0 x u_1) equals the stored one to the unitarity of the FP64 links.
   * FP32 arithmetic on FP32 / BF16 / FP16 storage: the oracle applies FP64 D with the rounded stored
-    links U_r (all three rows) to the rounded input.  Besides the hop's own bound
+    links U_r (all three rows) to the stored input (its storage-basis components rounded; every
+    bound is checked per real component of that basis, gpu_helpers).  Besides the hop's own bound
     gamma_m (|psi| + kappa |H||psi|) per real component (m = 2 N_R + 14, u = 2^-24,
     gpu_helpers.lowprec_bound), the rebuilt row differs from the
     rounded stored one: every entry is a difference of two products of rounded entries of modulus
@@ -21,7 +22,9 @@ import fixtures as fx
 import oracle as orc
 from paper_2405_19294_amd import hrw
 
-from gpu_helpers import THETA_AP, THETA_TW, U32, U_BF16, U_F16, check_real_bound, fp64_close, lowprec_bound, rel, to_dev
+from gpu_helpers import (THETA_AP, THETA_TW, U32, U_BF16, U_F16, check_stored, fp64_close, lowprec_bound, rel,
+                         stored_input, to_dev)
+from spin_basis import storage_gammas
 
 pytestmark = pytest.mark.gpu
 
@@ -70,13 +73,14 @@ def test_two_rows_low_precision_within_bound(case, dtype):
     uf, ur, g = two_row_setup(dims, kind, dtypes=(dtype,), seed=23)
     kappa = 0.137
     psi = fx.gaussian_spinor(dims, 3, seed=24)
-    psi_r, ur_r = orc.round_to(dtype, psi), orc.round_to(dtype, ur)
+    ur_r = orc.round_to(dtype, ur)
+    q_r, psi_r = stored_input(dtype, psi)
     out = hrw.dw_apply(g, kappa, to_dev(psi), THETA_TW, dtype).cpu().numpy()
     ref = orc.dw(dims, ur_r, kappa, psi_r, THETA_TW)
     ones = np.ones_like(np.abs(ur_r))
-    row2 = (8 * UNIT[dtype] + 8 * U32) * kappa * orc.hop_abs(dims, ones, np.abs(psi_r))
-    check_real_bound(out, ref, lowprec_bound(dims, ur_r, psi_r, kappa, 3) + row2 * (1 + 1j),
-                     0.0 if dtype == "f32" else UNIT[dtype])
+    row2 = (8 * UNIT[dtype] + 8 * U32) * kappa * orc.hop_abs(dims, ones, np.abs(q_r), gammas=storage_gammas())
+    check_stored(out, ref, lowprec_bound(dims, ur_r, q_r, kappa, 3) + row2 * (1 + 1j),
+                 0.0 if dtype == "f32" else UNIT[dtype])
     assert rel(out, orc.dw(dims, ur, kappa, psi, THETA_TW)) < {"f32": 1e-6, "bf16": 2e-2, "f16": 3e-3}[dtype]
 
 
