@@ -551,8 +551,11 @@ def workload_c1(args):
     torch.cuda.synchronize()
     apply_us = e0.elapsed_time(e1) / 200 * 1e3
     prm = hrw.solve_params(tol=1e-10, system="ddag_d_full", theta=theta)
+    for _ in range(args.warmup):
+        hrw.cg_solve(g, psi, kappa, prm)
+    torch.cuda.synchronize()
     hrw.timing_enable(True)
-    x, res, per, lat = _solve_timed(hrw, torch, g, psi, kappa, prm, max(args.steps, 20), args.warmup)
+    x, res, per, lat = _solve_timed(hrw, torch, g, psi, kappa, prm, max(args.steps, 20), 0)
     roof = _hop_roofline(hrw, "hop_kernel<N_R=2, double>")
     hrw.timing_enable(False)
     return _line(round(1.0 / per, 2), "solves/s", max(args.steps, 20), args.warmup, round(per * 1e3, 3), "f64",
@@ -679,8 +682,12 @@ def c4_rows(torch, hrw, dev, steps, extras=True):
         prm = hrw.solve_params(tol=1e-10, max_iter=20000, system="ddag_d_eo", inner_dtype="f32",
                                reliable_every=50, reliable_delta=hrw.RELIABLE_DELTA["f32"], theta=theta)
         b = srcs[:n].contiguous()
+        # the warm-up solve runs the first-use launch-shape search, whose trial launches
+        # stay out of the hop statistics
+        hrw.cg_solve(g, b, kappa, prm)
+        torch.cuda.synchronize()
         hrw.timing_enable(True)
-        x, res, per, lat = _solve_timed(hrw, torch, g, b, kappa, prm, steps, 1)
+        x, res, per, lat = _solve_timed(hrw, torch, g, b, kappa, prm, steps, 0)
         r = _hop_roofline(hrw, f"hop_mrhs_kernel<N_R=6, float, {n} sources>")
         hrw.timing_enable(False)
         err0 = float((torch.linalg.vector_norm(x[0] - x64[0]) / torch.linalg.vector_norm(x64[0])).item())
