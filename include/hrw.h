@@ -243,7 +243,9 @@ int hrw_workspace_size(const int dims[4], int nc, int rep, int n_rhs,
 
 /* out = D_W in (dagger = 0) or D_W^+ in (dagger = 1), D_W = 1 - kappa H
  * (Sec. 3.1), for n_rhs stacked full-lattice fields, computed with links and
- * spinors stored in dtype (inputs are rounded once to dtype; FP32
+ * spinors stored in dtype (inputs are rounded once to dtype, in the storage
+ * spin basis described with the canonical layout: with 16-bit storage
+ * |psi_s| + |psi_{s+2}| must lie within the format's range; FP32
  * accumulation below FP64).  in/out: device canonical FP64, must not overlap.
  * theta: host double[4]. */
 int hrw_dw_apply(const hrw_gauge *g, double kappa, const double theta[4], int dtype, int n_rhs,
