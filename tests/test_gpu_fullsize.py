@@ -12,7 +12,9 @@ recomputes (the residual of a solve):
     hop: D_hat in FP64, and the FP32-inner mixed solve's residual of the even/odd normal equations
     recomputed by the oracle;
   * SU(3) sym 32^4 with 24 sources: the multi-source FP32 kernel (the launch the multi-source CG uses)
-    bitwise equal to single-source applies, and the batched FP64 D_hat against the oracle.
+    bitwise equal to single-source applies, the batched FP64 D_hat against the oracle, and the mixed
+    multi-source CG of the benchmark (24 sources, FP32 inner) with the residual of two sources
+    recomputed by the oracle.
 """
 
 import numpy as np
@@ -167,22 +169,50 @@ def test_c3_operator_and_mixed_solve_full_size(nc, rep, fused):
         g.close()
 
 
-def test_c4_multi_source_full_size():
+@pytest.fixture(scope="module")
+def c4_field():
+    """SU(3) two-index symmetric 32^4 near-thermal links and the 24 point-smeared even sources
+    of the multi-source workload."""
     dims, nmax = C2, 24
     uf = fx.gauge_field(dims, 3, "thermal", seed=6, eps=0.3)
     ur = orc.rep_map(3, "sym", uf)
     g = hrw.Gauge(dims, 3, "sym", to_dev(uf), dtypes=("f64", "f32"))
     del uf
-    try:
-        src = np.stack([_even(dims, fx.point_smeared_sources(dims, g.nr, nmax, seed=7, which=[k]))[0]
-                        for k in range(nmax)])
-        dev_src = to_dev(src)
-        many32 = hrw.deo_apply(g, KAPPA, dev_src, THETA_AP, "f32").cpu().numpy()
-        for k in (0, 11, 23):
-            one = hrw.deo_apply(g, KAPPA, dev_src[k], THETA_AP, "f32").cpu().numpy()
-            assert np.array_equal(many32[k], one)
-        many64 = hrw.deo_apply(g, KAPPA, dev_src, THETA_AP, "f64").cpu().numpy()
-        for k in (0, 23):
-            fp64_close(many64[k], orc.deo(dims, ur, KAPPA, src[k], THETA_AP))
-    finally:
-        g.close()
+    src = np.stack([_even(dims, fx.point_smeared_sources(dims, g.nr, nmax, seed=7, which=[k]))[0]
+                    for k in range(nmax)])
+    yield ur, g, src
+    g.close()
+
+
+def test_c4_multi_source_full_size(c4_field):
+    ur, g, src = c4_field
+    dims = C2
+    dev_src = to_dev(src)
+    many32 = hrw.deo_apply(g, KAPPA, dev_src, THETA_AP, "f32").cpu().numpy()
+    for k in (0, 11, 23):
+        one = hrw.deo_apply(g, KAPPA, dev_src[k], THETA_AP, "f32").cpu().numpy()
+        assert np.array_equal(many32[k], one)
+    many64 = hrw.deo_apply(g, KAPPA, dev_src, THETA_AP, "f64").cpu().numpy()
+    for k in (0, 23):
+        fp64_close(many64[k], orc.deo(dims, ur, KAPPA, src[k], THETA_AP))
+
+
+def test_c4_mixed_multi_source_solve_residual_by_oracle(c4_field):
+    """The multi-source workload's solve as the benchmark runs it (24 sources in one call, FP32
+    inner fields, FP64 reliable updates every 50 iterations or on a drop of |r| by the FP32
+    trigger, tol 1e-10): every source converges, and for the first and last source the FP64
+    residual |eta - D_hat^+ D_hat x| / |eta| recomputed by the oracle meets the tolerance and
+    matches the reported one."""
+    ur, g, src = c4_field
+    dims = C2
+    prm = hrw.solve_params(tol=1e-10, max_iter=20000, system="ddag_d_eo", inner_dtype="f32",
+                           reliable_every=50, reliable_delta=hrw.RELIABLE_DELTA["f32"], theta=THETA_AP)
+    x, res, rc = hrw.cg_solve(g, to_dev(src), [KAPPA] * len(src), prm)
+    assert rc == 0, res
+    assert all(r["true_rel_resid"] <= 1e-10 for r in res)
+    x = x.cpu().numpy()
+    for k in (0, len(src) - 1):
+        ax = orc.deo(dims, ur, KAPPA, orc.deo(dims, ur, KAPPA, x[k], THETA_AP), THETA_AP, dagger=True)
+        r = rel(ax, src[k])
+        assert r <= 1.01e-10, (k, r)
+        assert abs(r - res[k]["true_rel_resid"]) <= 1e-3 * r, (k, r, res[k]["true_rel_resid"])
