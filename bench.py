@@ -39,6 +39,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "D_W GB/s & % HBM roofline; CG solves/s at 1e-10 resid vs FP64; p99 latency"
 HBM_PEAK_GBS = 8000.0
+# inside timed solves the library times one hopping launch in TIMING_EVERY of each epilogue
+# class with HIP events (odd, so launches that repeat in pairs are both sampled): timing every
+# launch added two event records per hop, about 4 ms to a 78 ms solve
+TIMING_EVERY = 9
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hop_traffic_su3_fund_32x4_f64.json")
 
 WORKLOAD = {
@@ -129,7 +133,7 @@ def main():
         log(f"warmup solve: {r['iters']} iterations, true residual {r['true_rel_resid']:.2e}")
 
     torch.cuda.synchronize()
-    hrw.timing_enable(True)
+    hrw.timing_enable(True, every=TIMING_EVERY)
     lat = []
     t_start = time.perf_counter()
     for k in range(args.steps):
@@ -153,8 +157,9 @@ def main():
     # HBM bytes per launch from the committed counter record, if it was taken
     # with the current kernel sources (None otherwise)
     from paper_2405_19294_amd import profsum
-    epi_tag = {"hop_plain": ", 0>", "hop_axpy": ", 1>", "hop_cg": ", 2>"}[dom_name]
-    traffic = profsum.traffic_for("hop_su3_kernel<double, false" + epi_tag, TRAFFIC_RECORD)
+    # (the instance name continues with the staging flag: "<double, false, 0, false>")
+    epi_tag = {"hop_plain": "false, 0,", "hop_axpy": "false, 1,", "hop_cg": "true, 2,"}[dom_name]
+    traffic = profsum.traffic_for("hop_su3_kernel<double, " + epi_tag, TRAFFIC_RECORD)
     roofline = {
         "bound": "hbm",
         "kernel": f"hop_su3_kernel<double, {dom_name[4:]} epilogue> (two rows of each link read, third rebuilt)",
@@ -303,7 +308,7 @@ def workload_clover(args):
         hrw.clover_bicgstab_solve(c, b_d, prm)
         torch.cuda.synchronize()
         if inner == "f32":
-            hrw.timing_enable(True)
+            hrw.timing_enable(True, every=TIMING_EVERY)
         t0 = time.perf_counter()
         for _ in range(args.steps):
             x, res, rc = hrw.clover_bicgstab_solve(c, b_d, prm)
@@ -350,7 +355,7 @@ def stored_link_row(torch, hrw, dims, nc, rep, uf_d, b_d, kappa, prm, ws, x_d, t
 
     step()
     torch.cuda.synchronize()
-    hrw.timing_enable(True)
+    hrw.timing_enable(True, every=TIMING_EVERY)
     t0 = time.perf_counter()
     for _ in range(steps):
         r = step()
@@ -390,7 +395,7 @@ def bicgstab_rows(torch, hrw, dev, dims, nc, rep, uf_d, b_d, kappa, theta, cg_va
         step()
         torch.cuda.synchronize()
         if timed == inner:
-            hrw.timing_enable(True)
+            hrw.timing_enable(True, every=TIMING_EVERY)
         t0 = time.perf_counter()
         for _ in range(steps):
             r = step()
@@ -554,7 +559,7 @@ def workload_c1(args):
     for _ in range(args.warmup):
         hrw.cg_solve(g, psi, kappa, prm)
     torch.cuda.synchronize()
-    hrw.timing_enable(True)
+    hrw.timing_enable(True, every=TIMING_EVERY)
     x, res, per, lat = _solve_timed(hrw, torch, g, psi, kappa, prm, max(args.steps, 20), 0)
     roof = _hop_roofline(hrw, "hop_kernel<N_R=2, double>")
     hrw.timing_enable(False)
@@ -595,8 +600,11 @@ def workload_c3(args):
             gg = gf if fused else g
             prm = hrw.solve_params(tol=1e-10, max_iter=20000, system="ddag_d_eo", inner_dtype=inner,
                                    reliable_every=50, reliable_delta=hrw.RELIABLE_DELTA[inner], theta=theta)
-            hrw.timing_enable(True)
-            x, res, per, lat = _solve_timed(hrw, torch, gg, b, kappa, prm, args.steps, args.warmup)
+            for _ in range(args.warmup):
+                hrw.cg_solve(gg, b, kappa, prm)
+            torch.cuda.synchronize()
+            hrw.timing_enable(True, every=TIMING_EVERY)
+            x, res, per, lat = _solve_timed(hrw, torch, gg, b, kappa, prm, args.steps, 0)
             kname = "hop_fused_kernel" if fused else "hop_kernel"
             r = _hop_roofline(hrw, f"{kname}<N_R={g.nr}, {inner}>")
             hrw.timing_enable(False)
@@ -686,7 +694,7 @@ def c4_rows(torch, hrw, dev, steps, extras=True):
         # stay out of the hop statistics
         hrw.cg_solve(g, b, kappa, prm)
         torch.cuda.synchronize()
-        hrw.timing_enable(True)
+        hrw.timing_enable(True, every=TIMING_EVERY)
         x, res, per, lat = _solve_timed(hrw, torch, g, b, kappa, prm, steps, 0)
         r = _hop_roofline(hrw, f"hop_mrhs_kernel<N_R=6, float, {n} sources>")
         hrw.timing_enable(False)

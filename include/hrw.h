@@ -427,14 +427,19 @@ int hrw_cg_session_destroy(hrw_cg_session *s);
 
 /* ---------------------------------------------------------------- timing
  * Optional per-kernel timing with HIP events recorded on the launch stream
- * around every hopping-kernel launch.  hrw_timing_enable(1) clears the
- * counters; hrw_timing_read fills, for kernel class k, the launch count,
- * summed event time in ms and summed algorithmic bytes (min-traffic model:
- * every link, neighbour spinor and epilogue operand counted once per launch).
- * Classes: 0 = all hopping launches; 3, 4, 5 = hopping launches with the
- * plain (out = H in), axpy (out = self - c H in) and fused CG-update
- * epilogues; 1, 2 are reserved (always zero).  EINVAL for an unknown class.
- * Timing adds two event records per launch on the launch stream. */
+ * around hopping-kernel launches.  hrw_timing_enable(n) with n >= 1 clears
+ * the counters and times one launch in n of each epilogue class (the 1st,
+ * (n+1)-th, ... since the call; n = 1: every launch), n <= 0 turns timing
+ * off; hrw_timing_read fills, for kernel class k, the count of timed
+ * launches, their summed event time in ms and summed algorithmic bytes
+ * (min-traffic model: every link, neighbour spinor and epilogue operand
+ * counted once per launch), so time / launches is the average duration of
+ * the sampled launches.  Classes: 0 = all hopping launches; 3, 4, 5 =
+ * hopping launches with the plain (out = H in), axpy (out = self - c H in)
+ * and fused CG-update epilogues; 1, 2 are reserved (always zero).  EINVAL for
+ * an unknown class.  Each timed launch adds two event records on its stream
+ * (a few microseconds each on MI355X); an odd n alternates between launches
+ * that repeat in pairs. */
 int hrw_timing_enable(int on);
 int hrw_timing_read(int kernel_class, long long *launches, double *total_ms, double *bytes);
 

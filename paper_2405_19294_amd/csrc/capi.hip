@@ -532,8 +532,10 @@ int hrw_timing_enable(int on)
     Timing &t = timing();
     timing_harvest();
     std::lock_guard<std::mutex> lk(t.mu);
-    t.on = on != 0;
+    t.on = on > 0;
+    t.every = on > 1 ? on : 1;
     for (int k = 0; k < KC_COUNT; ++k) {
+        t.seen[k] = 0;
         t.launches[k] = 0;
         t.ms[k] = 0;
         t.bytes[k] = 0;

@@ -67,6 +67,8 @@ struct Arena {
 struct Timing {
     std::mutex mu;
     bool on = false;
+    int every = 1;                  // time one launch in `every` of each class
+    long long seen[KC_COUNT] = {};  // launches of each class since enabling
     struct Pending {
         hipEvent_t a, b;
         int kc, kc2;  // kc2: second class credited (-1 = none)
@@ -79,8 +81,9 @@ struct Timing {
     double bytes[KC_COUNT] = {};
 };
 Timing &timing();
-// record a start event (returns false when timing is off)
-bool timed_begin(hipStream_t st, hipEvent_t *ev);
+// record a start event for a launch of class kc (returns false when timing
+// is off or this launch is not one of the sampled ones)
+bool timed_begin(hipStream_t st, hipEvent_t *ev, int kc);
 void timed_end(hipStream_t st, hipEvent_t start, int kc, int kc2, double bytes);
 int timing_harvest();
 

@@ -39,11 +39,12 @@ Timing &timing()
     return t;
 }
 
-bool timed_begin(hipStream_t st, hipEvent_t *ev)
+bool timed_begin(hipStream_t st, hipEvent_t *ev, int kc)
 {
     Timing &t = timing();
     std::lock_guard<std::mutex> lk(t.mu);
     if (!t.on) return false;
+    if (t.seen[kc]++ % t.every) return false;
     if (t.pool.empty()) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return false;
@@ -140,7 +141,7 @@ int run_hop(const hrw_gauge *g, const Phases &ph, const HopCall &c, hipStream_t 
     // SU(3) fundamental fields flagged special unitary: single-source hops read two rows per link
     const bool two_rows = !fused_nc && (g->mask & HRW_STORE_SU3_TWO_ROWS) && !hop_uses_mrhs(g->nr, c.dt, c.n_rhs);
     hipEvent_t ev;
-    const bool tm = timed_begin(st, &ev);
+    const bool tm = timed_begin(st, &ev, KC_HOP_PLAIN + c.epi);
     hipError_t err = hipErrorInvalidValue;
     dispatch_dtype(c.dt, [&](auto sv) {
         typedef decltype(sv) S;

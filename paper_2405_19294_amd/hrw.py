@@ -482,8 +482,10 @@ class Session:
             pass
 
 
-def timing_enable(on: bool = True):
-    _check(load().hrw_timing_enable(int(bool(on))))
+def timing_enable(on: bool = True, every: int = 1):
+    """Start (clearing the counters) or stop the hopping-kernel timing; `every` = n times one
+    launch in n of each epilogue class."""
+    _check(load().hrw_timing_enable(max(1, int(every)) if on else 0))
 
 
 def timing_read(kernel_class: int = 0):

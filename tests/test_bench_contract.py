@@ -38,3 +38,12 @@ def test_profsum_calibrates_on_the_copy_and_checks_the_source_hash(tmp_path):
     data["source_hash"] = "stale"
     json.dump(data, open(tmp_path / "t.json", "w"))
     assert profsum.traffic_for("hop_kernel<3, 3, double, false, 0>", str(tmp_path / "t.json")) is None
+
+
+def test_committed_traffic_record_names_the_dominant_instances():
+    """The committed counter record holds the two-row FP64 hop instances under the names the
+    bench looks up (the instance name carries the staging flag after the epilogue)."""
+    rec = json.load(open(os.path.join(ROOT, "profiles", "hop_traffic_su3_fund_32x4_f64.json")))
+    names = [r["kernel"] for r in rec["kernels"]]
+    for tag in ("false, 0,", "false, 1,", "true, 2,"):
+        assert sum("hop_su3_kernel<double, " + tag in n for n in names) == 1, (tag, names)
