@@ -63,7 +63,8 @@
  * Environment (read at each hopping-kernel launch):
  *   HRW_TUNE=0       use the occupancy model for the multi-source kernel's
  *                    launch shape instead of timing the candidates (16 or 32
- *                    sites per workgroup x threads x walk chunk) on the first
+ *                    sites per workgroup x threads x walk chunk and the
+ *                    x1-planes it spans) on the first
  *                    plain-epilogue launch of each (sources, extents);
  *                    results are bitwise the same either way;
  *   HRW_TUNE_CACHE   file of tuned launch shapes (JSON, keyed by architecture,
@@ -78,6 +79,9 @@
  *   HRW_MRHS_SITES=16|32  pin the multi-source workgroup to that many sites
  *                    (occupancy-model threads, no tuning; bitwise the same
  *                    results);
+ *   HRW_MRHS_PLANES=1|2|4|8  pin the x1-planes per chunk of the multi-source
+ *                    walk (the order workgroups visit the lattice; bitwise
+ *                    the same results);
  *   HRW_MRHS_MFMA=1  run FP32 N_R = 6 launches with >= 6 sources on the
  *                    matrix-core multi-source kernel (results differ from the
  *                    default vector kernel only by FP32 rounding; slower on

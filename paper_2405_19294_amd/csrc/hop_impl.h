@@ -537,6 +537,26 @@ __device__ __forceinline__ int tile_remap(int L, int n, int ts, int c)
     return t * ts + ch * c + w;
 }
 
+// The multi-source walk: a chunk is a block of p x1-planes by c / p
+// consecutive workgroups of each plane (B workgroups per plane), walked
+// through every time slice like tile_remap's; p <= 1 is tile_remap.  With one
+// 16-site line per workgroup the x1 neighbours of a line are B workgroups
+// apart, so flat chunks put them in another chunk, a whole walk through the
+// time slices away.
+__device__ __forceinline__ int tile_remap_planes(int L, int n, int ts, int c, int p, int B)
+{
+    if (p <= 1 || ts <= 0 || c <= 0) return tile_remap(L, n, ts, c);
+    const int T = n / ts;
+    const int q = c / p;
+    const int ch = L / (c * T);
+    const int rem = L - ch * c * T;
+    const int t = rem / c;
+    const int w = rem - t * c;
+    const int per_row = B / q;  // chunks side by side in one band of p planes
+    const int cha = ch / per_row, chb = ch - cha * per_row;
+    return t * ts + (cha * p + w / q) * B + chb * q + w % q;
+}
+
 // FP64 sum over the 16*G lanes (16 sites x G row threads) of one partial-sum
 // group, in a fixed tree; the result is valid in the group's first lane.
 // Groups wider than a wavefront (G = 8) combine their two halves through LDS.
@@ -795,7 +815,7 @@ hop_mrhs_kernel(const HopArgs<S> a)
         parity = bx >= a.grid_half;
         if (parity) bx -= a.grid_half;
     }
-    bx = tile_remap(xcd_remap(bx, a.grid_half), a.grid_half, a.tile_ts, a.tile_c);
+    bx = tile_remap_planes(xcd_remap(bx, a.grid_half), a.grid_half, a.tile_ts, a.tile_c, a.tile_p, a.tile_b);
     if (EPI == EPI_PLAIN) hop_alpha_on_the_side(a, sh);
     const int i0 = bx * MRS;
     const cpx<S> *__restrict__ gauge = a.gauge[parity];
@@ -852,6 +872,33 @@ inline void hop_tiling(const Geom &g, int sites_per_wg, int *ts, int *c, int cma
     *c = best;
 }
 
+// x1-plane blocking of the multi-source walk (tile_remap_planes): p planes per
+// chunk, set only where the chunk tiles whole planes of every time slice;
+// otherwise both stay 0 (the flat chunk)
+inline void hop_tiling_planes(const Geom &g, int sites_per_wg, int p, int ts, int c, int *tp, int *tb)
+{
+    *tp = 0;
+    *tb = 0;
+    if (p <= 1 || ts <= 0 || c <= 0 || c % p) return;
+    const long long plane = (long long)g.d[2] * g.d[3] / 2;  // half-sites of one x1-plane of a time slice
+    if (plane % sites_per_wg) return;
+    const int B = (int)(plane / sites_per_wg);
+    const int q = c / p;
+    if (B % q || ts % B || (ts / B) % p) return;
+    *tp = p;
+    *tb = B;
+}
+
+// HRW_MRHS_PLANES=1, 2, 4 or 8 pins the x1-planes per chunk of the
+// multi-source walk over the tuned choice: for tests and experiments
+inline int mr_planes_env()
+{
+    const char *e = getenv("HRW_MRHS_PLANES");
+    if (!e) return 0;
+    const int v = atoi(e);
+    return v == 1 || v == 2 || v == 4 || v == 8 ? v : 0;
+}
+
 // enum hrw_dtype of a storage type (0 FP64, 1 FP32, 2 BF16, 3 FP16)
 template <class S> constexpr int dtype_id() { return 1; }
 template <> constexpr int dtype_id<double>() { return 0; }
@@ -892,7 +939,8 @@ constexpr bool mr_has32() { return 32 * (NR / RS) <= WG / 2 && mr_lds<NR, S>(32)
 // ------------------------------------------------------------ launch-shape tuning
 //
 // Launch shape of the multi-source kernel: sites per workgroup (16 or 32),
-// threads per workgroup and the spatial chunk of the time-tiled walk.  None
+// threads per workgroup and the spatial chunk of the time-tiled walk (its
+// width and the x1-planes it spans, tile_remap_planes).  None
 // changes any result (the partial sums are per 16-site group, the per-source
 // arithmetic is fixed), so the shape is picked by timing.  On the first
 // plain-epilogue launch of each (instance family, sources, lattice extents)
@@ -904,12 +952,18 @@ constexpr bool mr_has32() { return 32 * (NR / RS) <= WG / 2 && mr_lds<NR, S>(32)
 // $HOME/.cache/hrw/tune.json; HRW_TUNE_CACHE set to an empty string keeps
 // the choices in memory only.  Until a key is tuned (or with HRW_TUNE=0, or
 // while the stream is being captured into a graph) the occupancy model
-// (mr_block, 16 sites) and chunk 16 are used.
+// (mr_block, 16 sites), chunk 16 and MR_PLANES planes are used.
 struct MrShape {
     int threads;
-    int cmax;   // chunk limit handed to hop_tiling (the chunk itself follows the launch's geometry)
-    int sites;  // sites per workgroup: 16 or 32
+    int cmax;    // chunk limit handed to hop_tiling (the chunk itself follows the launch's geometry)
+    int sites;   // sites per workgroup: 16 or 32
+    int planes = 1;  // x1-planes per chunk of the walk (tile_remap_planes; 1: flat chunks)
 };
+
+// the untuned walk: chunks of 16 workgroups over 4 x1-planes (at SU(3) sym
+// 32^4 with 24 sources the plain hop took 2229 us against 2531 us with flat
+// chunks; 2 planes 2340 us, 8 planes 2232 us)
+constexpr int MR_PLANES = 4;
 
 inline bool mr_tuning_enabled()
 {
@@ -919,7 +973,8 @@ inline bool mr_tuning_enabled()
 
 // The persistent part of the tuner: one JSON file shared by every instance
 // family, an object whose entries are  "key": {"threads": T, "cmax": C,
-// "sites": S, "us": U}  (written one per line).
+// "sites": S, "planes": P, "us": U}  (written one per line; an entry without
+// "planes" has flat chunks).
 struct TuneCache {
     std::mutex mu;
     bool loaded = false;
@@ -934,8 +989,8 @@ struct TuneCache {
         return std::string(h) + "/.cache/hrw/tune.json";
     }
 
-    // entries of an object of objects  {"key": {"threads": T, "cmax": C, "sites": S, "us": U}, ...}
-    // in any JSON layout; entries with unusable values are skipped
+    // entries of an object of objects  {"key": {"threads": T, "cmax": C, "sites": S, "planes": P,
+    // "us": U}, ...} in any JSON layout; entries with unusable values are skipped
     void read_file(const std::string &p, std::map<std::string, std::pair<MrShape, double>> &into)
     {
         FILE *f = fopen(p.c_str(), "r");
@@ -964,12 +1019,14 @@ struct TuneCache {
             const size_t b1 = b0 == std::string::npos ? b0 : text.find('}', b0);
             if (b1 == std::string::npos) break;
             const std::string key = text.substr(q0 + 1, q1 - q0 - 1), obj = text.substr(b0, b1 - b0 + 1);
-            double t = 0, c = 0, s = 0, us = 0;
+            double t = 0, c = 0, s = 0, pl = 1, us = 0;
             // range checks before any conversion: a value outside int's range would be undefined
+            const bool has_planes = obj.find("\"planes\"") != std::string::npos;
             if (field(obj, "threads", &t) && field(obj, "cmax", &c) && field(obj, "sites", &s) && t >= 64 &&
-                t <= MR_MAX_THREADS && (c == 16 || c == 4) && (s == 16 || s == 32)) {
+                t <= MR_MAX_THREADS && (c == 4 || c == 16 || c == 32 || c == 64) && (s == 16 || s == 32) &&
+                (!has_planes || (field(obj, "planes", &pl) && (pl == 1 || pl == 2 || pl == 4 || pl == 8)))) {
                 field(obj, "us", &us);
-                const MrShape sh{(int)t, (int)c, (int)s};
+                const MrShape sh{(int)t, (int)c, (int)s, (int)pl};
                 if (sh.threads == t && sh.threads % 64 == 0) into[key] = {sh, us};
             }
             pos = b1 + 1;
@@ -1014,8 +1071,9 @@ struct TuneCache {
         size_t n = 0;
         for (auto &kv : merged) {
             const MrShape &m = kv.second.first;
-            fprintf(f, "  \"%s\": {\"threads\": %d, \"cmax\": %d, \"sites\": %d, \"us\": %.1f}%s\n", kv.first.c_str(),
-                    m.threads, m.cmax, m.sites, kv.second.second, ++n < merged.size() ? "," : "");
+            fprintf(f, "  \"%s\": {\"threads\": %d, \"cmax\": %d, \"sites\": %d, \"planes\": %d, \"us\": %.1f}%s\n",
+                    kv.first.c_str(), m.threads, m.cmax, m.sites, m.planes, kv.second.second,
+                    ++n < merged.size() ? "," : "");
         }
         fprintf(f, "}\n");
         const bool ok = fclose(f) == 0;
@@ -1060,7 +1118,8 @@ struct MrTuner {
         while ((1LL << vc) < (long long)b.g.half) ++vc;
         static const char *names[] = {"f64", "f32", "bf16", "f16"};
         char buf[160];
-        snprintf(buf, sizeof buf, "%s/nr%d/rs%d/%s/n%d/v%d", device_arch().c_str(), NR, RS, names[dtype_id<S>()],
+        // "w2": shapes that carry the walk's planes (entries of earlier files are not reused)
+        snprintf(buf, sizeof buf, "%s/nr%d/rs%d/%s/n%d/v%d/w2", device_arch().c_str(), NR, RS, names[dtype_id<S>()],
                  b.n_rhs, vc);
         return buf;
     }
@@ -1104,7 +1163,7 @@ struct MrTuner {
             return false;
         }
         float best_ms = 0;
-        MrShape pick{0, 0, 0};
+        MrShape pick{0, 0, 0, 1};
         bool ok = true;
         for (int sites : {16, 32}) {
             if (sites == 32 && !mr_has32<NR, RS, S>()) continue;
@@ -1113,11 +1172,21 @@ struct MrTuner {
             HopArgs<S> b = b0;
             b.grid_half = (b0.ngroups + sites / PG_SITES - 1) / (sites / PG_SITES);
             const dim3 grid(b0.parity < 0 ? 2 * b.grid_half : b.grid_half, 1);
-            int ts16 = 0, c16 = 0;
-            hop_tiling(b0.g, sites, &ts16, &c16, 16);
-            for (int cmax : {16, 4}) {
+            // walks: (chunk limit, planes); a candidate whose chunk and planes repeat
+            // an earlier one's on this lattice is skipped
+            const int walks[6][2] = {{16, 1}, {4, 1}, {16, MR_PLANES}, {32, MR_PLANES}, {64, MR_PLANES}, {64, 8}};
+            int seen[6][2];
+            int nseen = 0;
+            for (const auto &wk : walks) {
+                const int cmax = wk[0];
                 hop_tiling(b.g, sites, &b.tile_ts, &b.tile_c, cmax);
-                if (cmax == 4 && b.tile_c == c16) continue;  // no distinct chunk
+                hop_tiling_planes(b.g, sites, wk[1], b.tile_ts, b.tile_c, &b.tile_p, &b.tile_b);
+                bool dup = false;
+                for (int k = 0; k < nseen; ++k) dup = dup || (seen[k][0] == b.tile_c && seen[k][1] == b.tile_p);
+                if (dup) continue;
+                seen[nseen][0] = b.tile_c;
+                seen[nseen][1] = b.tile_p;
+                ++nseen;
                 for (int t = MR_MAX_THREADS; t >= unit && ok; t -= 64) {
                     if (t % unit) continue;
                     float ms = 0;
@@ -1137,7 +1206,7 @@ struct MrTuner {
                     }
                     if (ok && (pick.threads == 0 || ms < best_ms)) {
                         best_ms = ms;
-                        pick = MrShape{t, cmax, sites};
+                        pick = MrShape{t, cmax, sites, wk[1]};
                     }
                 }
             }
@@ -1176,8 +1245,9 @@ MrShape mr_shape(const HopArgs<S> &b, hipStream_t st)
     MrShape sh;
     const int forced = mr_forced_sites();
     if (forced == 32 && mr_has32<NR, RS, S>())
-        return MrShape{mr_block<NR, RS, S, D, E, 32>(b.n_rhs, mr_lds<NR, S>(32)), 16, 32};
-    if (forced == 16) return MrShape{mr_block<NR, RS, S, D, E, 16>(b.n_rhs, mr_lds<NR, S>(16)), 16, 16};
+        return MrShape{mr_block<NR, RS, S, D, E, 32>(b.n_rhs, mr_lds<NR, S>(32)), 16, 32, MR_PLANES};
+    if (forced == 16)
+        return MrShape{mr_block<NR, RS, S, D, E, 16>(b.n_rhs, mr_lds<NR, S>(16)), 16, 16, MR_PLANES};
     auto &tuner = mr_tuner<NR, RS, S>();
     if (tuner.lookup(b, &sh)) return sh;
     if (E == EPI_PLAIN && mr_tuning_enabled()) {
@@ -1186,7 +1256,7 @@ MrShape mr_shape(const HopArgs<S> &b, hipStream_t st)
             tuner.template tune<D>(b, st, &sh))
             return sh;
     }
-    return MrShape{mr_block<NR, RS, S, D, E, 16>(b.n_rhs, mr_lds<NR, S>(16)), 16, 16};
+    return MrShape{mr_block<NR, RS, S, D, E, 16>(b.n_rhs, mr_lds<NR, S>(16)), 16, 16, MR_PLANES};
 }
 
 template <int NR, int RS, class S, bool D, int E>
@@ -1196,6 +1266,9 @@ void launch_mrhs(const HopArgs<S> &b, hipStream_t st)
     HopArgs<S> bt = b;
     bt.grid_half = (b.ngroups + sh.sites / PG_SITES - 1) / (sh.sites / PG_SITES);
     hop_tiling(bt.g, sh.sites, &bt.tile_ts, &bt.tile_c, sh.cmax);
+    const int forced_planes = mr_planes_env();
+    hop_tiling_planes(bt.g, sh.sites, forced_planes > 0 ? forced_planes : sh.planes, bt.tile_ts, bt.tile_c,
+                      &bt.tile_p, &bt.tile_b);
     const dim3 grid(b.parity < 0 ? 2 * bt.grid_half : bt.grid_half, 1);
     if constexpr (mr_has32<NR, RS, S>()) {
         if (sh.sites == 32) {

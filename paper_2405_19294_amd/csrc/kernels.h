@@ -79,6 +79,8 @@ struct HopArgs {
     int pstride;
     int tile_ts;                 // workgroups per time slice (0 = no tiling)
     int tile_c;                  // workgroups per spatial chunk of the walk
+    int tile_p;                  // multi-source walk: x1-planes per chunk (<= 1: the chunk is c consecutive workgroups)
+    int tile_b;                  // multi-source walk: workgroups per x1-plane of a time slice
     int ngroups;                 // 16-site partial-sum groups per parity
     // the CG alpha step run on the side of a plain-epilogue launch (null: none):
     // red_n systems, their partials of <p, A p> and state, alpha written per system

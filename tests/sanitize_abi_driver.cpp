@@ -102,7 +102,9 @@ static int cache_checks(const char *dir)
     const char *bad[] = {"", "{", "{\"k\": {", "{\"k\": {\"threads\": 100, \"cmax\": 4, \"sites\": 16}}",
                          "{\"k\": {\"threads\": 64, \"cmax\": 4, \"sites\": 17}}", "}}}}{{{{\"\"\"\":::",
                          "{\"k\": {\"threads\": -64, \"cmax\": 4, \"sites\": 16}}", "[1, 2, 3]",
-                         "{\"k\": {\"threads\": 1e999, \"cmax\": 4, \"sites\": 16}}"};
+                         "{\"k\": {\"threads\": 1e999, \"cmax\": 4, \"sites\": 16}}",
+                         "{\"k\": {\"threads\": 64, \"cmax\": 4, \"sites\": 16, \"planes\": 3}}",
+                         "{\"k\": {\"threads\": 64, \"cmax\": 4, \"sites\": 16, \"planes\": -1e300}}"};
     for (const char *b : bad) {
         m.clear();
         put(path.c_str(), b);
@@ -125,9 +127,12 @@ static int cache_checks(const char *dir)
     hrw::TuneCache w;
     w.store("gfx950/nr3/rs3/f32/n8/v10", hrw::MrShape{192, 16, 16}, 12.5);
     w.store("gfx950/nr6/rs6/f32/n24/v19", hrw::MrShape{256, 4, 32}, 99.0);
+    w.store("gfx950/nr6/rs6/f32/n12/v19/w2", hrw::MrShape{192, 32, 16, 4}, 50.0);
     hrw::TuneCache r;
-    hrw::MrShape sh{0, 0, 0};
-    CHECK(r.lookup("gfx950/nr6/rs6/f32/n24/v19", &sh) && sh.threads == 256 && sh.cmax == 4 && sh.sites == 32);
+    hrw::MrShape sh{0, 0, 0, 0};
+    CHECK(r.lookup("gfx950/nr6/rs6/f32/n24/v19", &sh) && sh.threads == 256 && sh.cmax == 4 && sh.sites == 32 &&
+          sh.planes == 1);
+    CHECK(r.lookup("gfx950/nr6/rs6/f32/n12/v19/w2", &sh) && sh.threads == 192 && sh.cmax == 32 && sh.planes == 4);
     CHECK(!r.lookup("missing", &sh));
     return 0;
 }

@@ -98,8 +98,9 @@ np.save({out!r}, out)
 
 
 def test_tuned_launch_shapes_persist_across_processes(tmp_path):
-    """The first process tunes the multi-source launch shape and writes it to the cache file
-    (JSON, keyed by architecture, N_R, row split, storage, sources and volume class); a later
+    """The first process tunes the multi-source launch shape (threads, sites, walk chunk and its
+    x1-planes) and writes it to the cache file (JSON, keyed by architecture, N_R, row split,
+    storage, sources and volume class); a later
     process takes a shape from the file instead of tuning (a hand-edited entry survives it
     unchanged); the results are bitwise the same either way."""
     import json
@@ -123,9 +124,10 @@ def test_tuned_launch_shapes_persist_across_processes(tmp_path):
     keys = [k for k in entries if "/nr6/rs6/f32/n8/" in k]
     assert keys, entries
     e = entries[keys[0]]
-    assert e["sites"] in (16, 32) and e["threads"] % 64 == 0 and e["cmax"] in (4, 16)
+    assert e["sites"] in (16, 32) and e["threads"] % 64 == 0 and e["cmax"] in (4, 16, 32, 64)
+    assert e["planes"] in (1, 2, 4, 8)
     # a different (valid) shape in the file: the next process uses it without tuning
-    entries[keys[0]] = {"threads": 128, "cmax": 4, "sites": 32 if e["sites"] == 16 else 16, "us": 1.0}
+    entries[keys[0]] = {"threads": 128, "cmax": 4, "sites": 32 if e["sites"] == 16 else 16, "planes": 1, "us": 1.0}
     cache.write_text(json.dumps(entries, indent=1))
     second = run("b")
     assert json.loads(cache.read_text())[keys[0]]["threads"] == 128
