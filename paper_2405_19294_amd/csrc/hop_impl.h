@@ -815,7 +815,10 @@ hop_mrhs_kernel(const HopArgs<S> a)
         parity = bx >= a.grid_half;
         if (parity) bx -= a.grid_half;
     }
-    bx = tile_remap_planes(xcd_remap(bx, a.grid_half), a.grid_half, a.tile_ts, a.tile_c, a.tile_p, a.tile_b);
+    // the remapped index is uniform over the workgroup: held in a scalar register (kept in a
+    // vector register it tipped the 16-site FP32 axpy instances into 12-28 B of spill)
+    bx = __builtin_amdgcn_readfirstlane(
+        tile_remap_planes(xcd_remap(bx, a.grid_half), a.grid_half, a.tile_ts, a.tile_c, a.tile_p, a.tile_b));
     if (EPI == EPI_PLAIN) hop_alpha_on_the_side(a, sh);
     const int i0 = bx * MRS;
     const cpx<S> *__restrict__ gauge = a.gauge[parity];
