@@ -747,7 +747,7 @@ def test_hop_abs_bounds_the_hop():
     pos = np.abs(psi)
     # free field, positive spinor: projector entries (1 -+ g) have mixed signs, so
     # only the diagonal spin part is exact; check the scale instead
-    assert np.allclose(orc.hop_abs(dims, unit, pos).sum(), 2 * 8 * pos.sum(), rtol=1e-12)
+    assert np.allclose(orc.hop_abs(dims, np.abs(unit), pos).sum(), 2 * 8 * pos.sum(), rtol=1e-12)
 
 
 def test_hop_abs_real_bounds_the_hop_and_free_field_closed_form():
