@@ -1177,8 +1177,8 @@ struct MrTuner {
             const dim3 grid(b0.parity < 0 ? 2 * b.grid_half : b.grid_half, 1);
             // walks: (chunk limit, planes); a candidate whose chunk and planes repeat
             // an earlier one's on this lattice is skipped
-            const int walks[6][2] = {{16, 1}, {4, 1}, {16, MR_PLANES}, {32, MR_PLANES}, {64, MR_PLANES}, {64, 8}};
-            int seen[6][2];
+            const int walks[4][2] = {{16, 1}, {16, MR_PLANES}, {32, MR_PLANES}, {64, MR_PLANES}};
+            int seen[4][2];
             int nseen = 0;
             for (const auto &wk : walks) {
                 const int cmax = wk[0];
