@@ -434,3 +434,30 @@ def test_multi_source_walk_over_planes_is_bitwise_neutral(monkeypatch):
             one = hrw.deo_apply(g, 0.125, pe[k], THETA_TW, "f32", dagger=d).cpu().numpy()
             assert np.array_equal(got["4"][d][k], one), (k, d)
     g.close()
+
+
+def test_fp64_storage_basis_round_trip_and_unit_spin_sources():
+    """FP64: kappa = 0 returns the input through the storage basis and back, bit for bit as the
+    same FP64 sums and halvings in numpy (spin_basis); and a point source in each spin and colour
+    component gives D_W and D_hat equal to the oracle's (every spin pair crosses the basis
+    change on its own)."""
+    from spin_basis import to_chiral, to_storage
+    dims = (4, 2, 2, 4)
+    uf, ur, g = setup(dims, 3, "fund", "haar", seed=63, dtypes=("f64",))
+    g_ = fx.rng(64, 1)
+    psi = (g_.standard_normal((fx.volume(dims), 4, 3)) * 10.0 ** g_.integers(-6, 4, (fx.volume(dims), 4, 3))
+           + 1j * g_.standard_normal((fx.volume(dims), 4, 3)))
+    out = hrw.dw_apply(g, 0.0, to_dev(psi), THETA_AP, "f64").cpu().numpy()
+    assert np.array_equal(out, to_chiral(to_storage(psi)))
+    site = 5
+    for sp in range(4):
+        for c in range(3):
+            src = np.zeros((fx.volume(dims), 4, 3), complex)
+            src[site, sp, c] = 1.0 - 0.5j
+            fp64_close(hrw.dw_apply(g, 0.13, to_dev(src), THETA_TW, "f64").cpu().numpy(),
+                       orc.dw(dims, ur, 0.13, src, THETA_TW))
+            pe = orc.split_eo(dims, src)[0]
+            if np.any(pe):
+                fp64_close(hrw.deo_apply(g, 0.13, to_dev(pe), THETA_TW, "f64", True).cpu().numpy(),
+                           orc.deo(dims, ur, 0.13, pe, THETA_TW, dagger=True))
+    g.close()
